@@ -1,0 +1,157 @@
+/*
+ * bz.h -- C ABI of the MI355X (gfx950) Brouwer-Zimmermann minimum-distance library.
+ *
+ * Computes the minimum Hamming distance d = min{wt(c) : c in C \ {0}} of a
+ * linear code over F_3 or F_7 given by a k x n generator matrix (problem
+ * statement: Hernando & Quintana-Orti, arXiv 2603.29942, Sec. 3), with the
+ * Brouwer-Zimmermann rounds of Algorithm 6 (Sec. 3.1).  Every step of the
+ * path runs on the GPU: the information-set decomposition into systematic
+ * matrices Gamma_j, the bit-sliced packing in the natural encoding (Sec. 2 and
+ * 4.1), the enumeration of all g-row combinations with the lowest coefficient
+ * fixed to 1 (Sec. 4.2), exact prefix sums with the F_3 / F_7 additions of
+ * Algorithms 3 and 4, the isometric last addition (Sec. 4.3), the popcount
+ * weight, the min-reduce against the upper bound U, and the stage-by-stage
+ * lower-bound test with early termination (Sec. 4.4).
+ *
+ * Conventions
+ *   - Every function returns BZ_OK (0) or a negative bz_status; nothing throws
+ *     or aborts across the ABI.
+ *   - G is k x n, row-major, one uint8 per symbol, entries in [0, p).
+ *   - Limits: p in {3, 7}; 1 <= k <= n; n <= BZ_MAX_N; k <= BZ_MAX_K.
+ *   - The caller owns every buffer it passes in; the library copies or reads
+ *     them during the call and keeps no pointer to them afterwards.  Device
+ *     memory for intermediate state is allocated once per device by the library
+ *     and reused by later calls.
+ *   - Calls on one device are serialised by a per-device lock.
+ *
+ * Readings of points the paper leaves open (all shared with the oracle):
+ *   - combinations range over F_p with the coefficient of the lowest-indexed
+ *     row fixed to 1; a round-g stage has C(k,g) (p-1)^(g-1) combinations;
+ *   - Gamma_j is the reduced row echelon form of G with the columns unused by
+ *     Gamma_1..Gamma_{j-1} first (ascending) and the used ones after
+ *     (ascending); k_j counts its pivots among the unused columns; matrices
+ *     with k_j = k are kept, the first partial one (0 < k_j < k) is kept as the
+ *     last, and none once k_j = 0 or no column is left;
+ *   - the early-termination test L_{g,j} >= U runs after every stage (g, j)
+ *     with L_{g,j} = sum_{i<=j} c_i(g) + sum_{i>j} c_i(g-1),
+ *     c_i(g) = max(0, g+1-(k-k_i)); BZ_CHECK_ROUND tests only at j = m.
+ */
+#ifndef BZ_H
+#define BZ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BZ_MAX_N 128
+#define BZ_MAX_K 64
+#define BZ_MAX_M 128
+#define BZ_MAX_STAGES 256
+
+typedef enum {
+    BZ_OK = 0,
+    BZ_ERR_ARG = -1,    /* p not in {3,7}, n or k out of range, NULL pointer, bad option */
+    BZ_ERR_VALUE = -2,  /* a generator entry >= p */
+    BZ_ERR_RANK = -3,   /* rank(G) < k */
+    BZ_ERR_DEVICE = -4, /* a HIP runtime error, or no gfx950 device */
+    BZ_ERR_NOMEM = -5,  /* a device or pinned-host allocation failed */
+    BZ_ERR_LIMIT = -6   /* the next required stage would exceed max_codewords, or a
+                           stage lies outside the kernel's index ranges */
+} bz_status;
+
+enum { BZ_CHECK_STAGE = 0, BZ_CHECK_ROUND = 1 };
+
+/* One stage: all combinations of g rows of Gamma_j. */
+typedef struct {
+    int32_t g, j;         /* round and matrix index, both 1-based */
+    uint64_t codewords;   /* combinations the kernel evaluated in this stage */
+    int32_t stage_min;    /* minimum weight seen in this stage */
+    int32_t upper_after;  /* U after the stage */
+    int32_t lower_after;  /* L_{g,j} */
+} bz_stage;
+
+typedef struct {
+    int32_t d;                    /* minimum distance (valid when the call returns BZ_OK) */
+    int32_t m;                    /* number of matrices Gamma_j */
+    int32_t ranks[BZ_MAX_M];      /* k_j */
+    int32_t n_stages;             /* stages run (and reported) */
+    int32_t terminated_by;        /* 0: L >= U after a stage; 1: every round done; 2: no stage needed (k = n) */
+    uint64_t codewords_total;
+    bz_stage stages[BZ_MAX_STAGES];
+    /* with options.timing: device time of the two kernels of the call, measured
+       with HIP events on the call's stream (milliseconds); else 0 */
+    float decompose_ms;
+    float enum_ms;
+} bz_result;
+
+typedef struct {
+    int32_t check;            /* BZ_CHECK_STAGE (default) or BZ_CHECK_ROUND */
+    int32_t no_termination;   /* 1: run every stage g = 1..k, j = 1..m (weight spectra) */
+    int32_t identity_skip;    /* 1 (default): weight = g + popcount over the n-k non-pivot
+                                 columns (Gamma_j is the identity on its k pivot columns);
+                                 0: popcount over all n columns */
+    int32_t histograms;       /* 1: fill hist_out */
+    uint64_t *hist_out;       /* host buffer, BZ_MAX_STAGES x (n+1) uint64, row s = stage s:
+                                 number of combinations of weight w; written when histograms */
+    uint64_t max_codewords;   /* work limit; 0 = default (2^44) */
+    void *hip_stream;         /* hipStream_t to run on; NULL = the library's stream */
+    int32_t device;           /* HIP device ordinal */
+    int32_t blocks_per_cu;    /* enumeration grid: workgroups per compute unit; 0 = default */
+    int32_t timing;           /* 1: fill bz_result.decompose_ms / enum_ms */
+} bz_options;
+
+/* Fill *o with the defaults above. */
+void bz_default_options(bz_options *o);
+
+/* Minimum distance of the code generated by the host matrix G (k x n), default options. */
+int bz_min_distance(int p, int n, int k, const uint8_t *G, bz_result *out);
+
+/* As bz_min_distance, with options.  G_is_device = 1: G is a device pointer
+ * (already resident in GPU memory on options->device, readable from the
+ * stream); 0: a host pointer, copied to the device inside the call.  On
+ * return the stream has been synchronised and *out is complete. */
+int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device,
+                       const bz_options *o, bz_result *out);
+
+/* Human-readable name of a status code. */
+const char *bz_status_str(int status);
+
+/* ---------------------------------------------------------------------- */
+/* Bit-sliced F_p vector arithmetic on the device (Sec. 2; Tables 1-2 of the
+ * paper time these additions).  Vectors of nsym symbols are stored sliced:
+ * planes[v][b][w], b < r planes (r = 2 for F_3, 3 for F_7), w < ceil(nsym/32)
+ * words; bit t of word w of plane b is bit b of symbol 32w+t; bits beyond
+ * nsym are zero.  Natural encoding (value = sum_b bit_b 2^b) unless stated.
+ * All pointers are device pointers; calls are asynchronous on `stream`
+ * (NULL: the null stream). */
+
+enum {
+    BZ_OP_ADD = 0,     /* a + b, Algorithm 3 (F_3) / Algorithm 4 (F_7) */
+    BZ_OP_SUB = 1,     /* a - b = a + (-b); -b is a plane swap (F_3) or masked complement (F_7) */
+    BZ_OP_DOUBLE = 2,  /* 2a as a circular shift of the planes (Sec. 4.2); b unused */
+    BZ_OP_ISO_ADD = 3, /* nonzero mask of a + b (isometric addition, Sec. 4.3) in plane 0, other planes 0 */
+    BZ_OP_ISO_SUB = 4, /* nonzero mask of a - b (isometric subtraction, Sec. 4.3) */
+    BZ_OP_KAT_ADD = 5  /* F_3 only: Algorithm 2 on planes in its encoding 0=(1,1), 1=(0,1), 2=(1,0) */
+};
+
+enum { BZ_ENC_NATURAL = 0, BZ_ENC_KAT = 1 };
+
+/* symbols (nvec x nsym uint8, row-major) -> planes; encoding BZ_ENC_KAT is for F_3 only */
+int bz_sliced_pack(int p, int encoding, int nvec, int nsym, const uint8_t *sym, uint32_t *planes,
+                   void *stream);
+/* planes -> symbols (inverse of bz_sliced_pack; a plane pattern outside the
+ * encoding decodes to 255) */
+int bz_sliced_unpack(int p, int encoding, int nvec, int nsym, const uint32_t *planes, uint8_t *sym,
+                     void *stream);
+/* out = op(a, b) for every vector, repeated `reps` times (each repetition
+ * recomputes the same result; reps > 1 is for timing). */
+int bz_sliced_op(int p, int op, int nvec, int nsym, const uint32_t *a, const uint32_t *b,
+                 uint32_t *out, int reps, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

@@ -1,0 +1,190 @@
+"""Python binding of the C ABI in ``include/bz.h`` (``libbz.so``, HIP for gfx950).
+
+Argument marshalling only: every step of the minimum-distance path runs in the
+library's GPU kernels.  The functions keep the C names; ``min_distance`` is a
+convenience wrapper returning a dict.  There is no CPU fallback: if the built
+library is missing, loading fails with an error.
+
+PyTorch is used only for device memory and streams: pass ``G`` as a CUDA
+(ROCm) uint8 tensor to hand the library a device pointer, and its current
+stream is used.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libbz.so")
+
+MAX_N, MAX_K, MAX_M, MAX_STAGES = 128, 64, 128, 256
+OK, ERR_ARG, ERR_VALUE, ERR_RANK, ERR_DEVICE, ERR_NOMEM, ERR_LIMIT = 0, -1, -2, -3, -4, -5, -6
+CHECK_STAGE, CHECK_ROUND = 0, 1
+OP_ADD, OP_SUB, OP_DOUBLE, OP_ISO_ADD, OP_ISO_SUB, OP_KAT_ADD = range(6)
+ENC_NATURAL, ENC_KAT = 0, 1
+
+EXPORTS = ("bz_default_options", "bz_min_distance", "bz_min_distance_ex", "bz_status_str",
+           "bz_sliced_pack", "bz_sliced_unpack", "bz_sliced_op")
+
+
+class bz_stage(ctypes.Structure):
+    _fields_ = [("g", ctypes.c_int32), ("j", ctypes.c_int32), ("codewords", ctypes.c_uint64),
+                ("stage_min", ctypes.c_int32), ("upper_after", ctypes.c_int32),
+                ("lower_after", ctypes.c_int32)]
+
+
+class bz_result(ctypes.Structure):
+    _fields_ = [("d", ctypes.c_int32), ("m", ctypes.c_int32), ("ranks", ctypes.c_int32 * MAX_M),
+                ("n_stages", ctypes.c_int32), ("terminated_by", ctypes.c_int32),
+                ("codewords_total", ctypes.c_uint64), ("stages", bz_stage * MAX_STAGES),
+                ("decompose_ms", ctypes.c_float), ("enum_ms", ctypes.c_float)]
+
+
+class bz_options(ctypes.Structure):
+    _fields_ = [("check", ctypes.c_int32), ("no_termination", ctypes.c_int32),
+                ("identity_skip", ctypes.c_int32), ("histograms", ctypes.c_int32),
+                ("hist_out", ctypes.POINTER(ctypes.c_uint64)), ("max_codewords", ctypes.c_uint64),
+                ("hip_stream", ctypes.c_void_p), ("device", ctypes.c_int32),
+                ("blocks_per_cu", ctypes.c_int32), ("timing", ctypes.c_int32)]
+
+
+_lib = None
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+def lib():
+    """Load ``libbz.so`` (build it with ``python -m paper_2603_29942_amd.build``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise LibraryMissing(f"{LIB_PATH} is not built; run python -m paper_2603_29942_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        u8p, u32p = ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_uint32)
+        vp = ctypes.c_void_p
+        L.bz_default_options.argtypes = [ctypes.POINTER(bz_options)]
+        L.bz_default_options.restype = None
+        L.bz_min_distance.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(bz_result)]
+        L.bz_min_distance_ex.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int,
+                                         ctypes.POINTER(bz_options), ctypes.POINTER(bz_result)]
+        L.bz_status_str.argtypes = [ctypes.c_int]
+        L.bz_status_str.restype = ctypes.c_char_p
+        L.bz_sliced_pack.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp]
+        L.bz_sliced_unpack.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp]
+        L.bz_sliced_op.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp,
+                                   ctypes.c_int, vp]
+        del u8p, u32p
+        _lib = L
+    return _lib
+
+
+def bz_default_options():
+    o = bz_options()
+    lib().bz_default_options(ctypes.byref(o))
+    return o
+
+
+def bz_status_str(status):
+    return lib().bz_status_str(int(status)).decode()
+
+
+def _stream_of(t):
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def bz_min_distance_ex(p, G, options=None, out=None):
+    """Run the library on G (numpy uint8 on the host, or a torch uint8 CUDA
+    tensor on the device).  Returns (status, bz_result)."""
+    out = out if out is not None else bz_result()
+    o = options if options is not None else bz_default_options()
+    if hasattr(G, "is_cuda") and G.is_cuda:
+        k, n = G.shape
+        if not G.is_contiguous():
+            raise ValueError("G must be contiguous")
+        if o.hip_stream is None:
+            o.hip_stream = _stream_of(G)
+        o.device = G.device.index or 0
+        st = lib().bz_min_distance_ex(p, n, k, ctypes.c_void_p(G.data_ptr()), 1, ctypes.byref(o),
+                                      ctypes.byref(out))
+    else:
+        G = np.ascontiguousarray(G, dtype=np.uint8)
+        k, n = G.shape
+        st = lib().bz_min_distance_ex(p, n, k, G.ctypes.data_as(ctypes.c_void_p), 0, ctypes.byref(o),
+                                      ctypes.byref(out))
+    return st, out
+
+
+def bz_min_distance(p, G):
+    G = np.ascontiguousarray(G, dtype=np.uint8)
+    k, n = G.shape
+    out = bz_result()
+    st = lib().bz_min_distance(p, n, k, G.ctypes.data_as(ctypes.c_void_p), ctypes.byref(out))
+    return st, out
+
+
+def result_dict(st, r, hist=None):
+    d = {"status": st, "d": r.d, "m": r.m, "ranks": [r.ranks[i] for i in range(r.m)],
+         "terminated_by": r.terminated_by, "codewords_total": r.codewords_total,
+         "stages": [(s.g, s.j, s.codewords, s.stage_min, s.upper_after, s.lower_after)
+                    for s in r.stages[:r.n_stages]]}
+    if hist is not None:
+        d["hist"] = hist[:r.n_stages].copy()
+    return d
+
+
+def min_distance(p, G, *, check="stage", no_termination=False, identity_skip=True, max_codewords=0,
+                 histograms=False, blocks_per_cu=0):
+    """Convenience wrapper: same keys as the oracle's result dict."""
+    o = bz_default_options()
+    o.check = CHECK_ROUND if check == "round" else CHECK_STAGE
+    o.no_termination = int(bool(no_termination))
+    o.identity_skip = int(bool(identity_skip))
+    o.max_codewords = int(max_codewords)
+    o.blocks_per_cu = int(blocks_per_cu)
+    n = G.shape[1]
+    hist = None
+    if histograms:
+        hist = np.zeros((MAX_STAGES, n + 1), dtype=np.uint64)
+        o.histograms = 1
+        o.hist_out = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
+    st, r = bz_min_distance_ex(p, G, o)
+    return result_dict(st, r, hist)
+
+
+# ---------------------------------------------------------------- sliced vectors
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def bz_sliced_pack(p, sym, encoding=ENC_NATURAL):
+    """sym: torch uint8 CUDA tensor (nvec, nsym) -> int32 tensor (nvec, r, words)."""
+    import torch
+    nvec, nsym = sym.shape
+    r = 2 if p == 3 else 3
+    planes = torch.empty((nvec, r, (nsym + 31) // 32), dtype=torch.int32, device=sym.device)
+    st = lib().bz_sliced_pack(p, encoding, nvec, nsym, _ptr(sym), _ptr(planes), _stream_of(sym))
+    if st != OK:
+        raise RuntimeError(bz_status_str(st))
+    return planes
+
+
+def bz_sliced_unpack(p, planes, nsym, encoding=ENC_NATURAL):
+    import torch
+    nvec = planes.shape[0]
+    sym = torch.empty((nvec, nsym), dtype=torch.uint8, device=planes.device)
+    st = lib().bz_sliced_unpack(p, encoding, nvec, nsym, _ptr(planes), _ptr(sym), _stream_of(planes))
+    if st != OK:
+        raise RuntimeError(bz_status_str(st))
+    return sym
+
+
+def bz_sliced_op(p, op, a, b, nsym, reps=1, out=None):
+    import torch
+    out = torch.empty_like(a) if out is None else out
+    st = lib().bz_sliced_op(p, op, a.shape[0], nsym, _ptr(a), _ptr(b), _ptr(out), reps, _stream_of(a))
+    if st != OK:
+        raise RuntimeError(bz_status_str(st))
+    return out

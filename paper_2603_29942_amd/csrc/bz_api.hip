@@ -1,0 +1,305 @@
+// bz_api.hip -- host side of the C ABI declared in include/bz.h.
+//
+// Per device, one context holds the library stream, the device workspace
+// (code state, packed Gamma_j rows, binomial table, histograms) and a pinned
+// host buffer for the results; it is created on first use and kept until the
+// process ends.  A call validates its arguments, launches the decomposition
+// and the persistent enumeration kernel back to back on the stream, copies the
+// compact result block back and rebuilds the stage trace from it.
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <mutex>
+
+#include "bz_kernels.hpp"
+
+using namespace bz;
+
+namespace {
+
+constexpr int MAX_DEV = 16;
+
+struct DevCtx {
+    bool ready = false;
+    int cu = 0;
+    hipStream_t stream = nullptr;
+    uint8_t *g_buf = nullptr;
+    CodeState *cs = nullptr;
+    u32 *rows = nullptr;
+    u64 *binom = nullptr;
+    u64 *hist = nullptr;
+    CodeResult *host_res = nullptr;
+    u64 *host_hist = nullptr;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    std::mutex mu;
+};
+
+DevCtx g_ctx[MAX_DEV];
+std::mutex g_init_mu;
+
+#define HIP_OK(expr)                              \
+    do {                                          \
+        if ((expr) != hipSuccess) return BZ_ERR_DEVICE; \
+    } while (0)
+
+int init_ctx(int dev) {
+    DevCtx &c = g_ctx[dev];
+    if (c.ready) return BZ_OK;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || dev >= ndev) return BZ_ERR_DEVICE;
+    HIP_OK(hipSetDevice(dev));
+    hipDeviceProp_t prop;
+    HIP_OK(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return BZ_ERR_DEVICE;
+    c.cu = prop.multiProcessorCount;
+    // a blocking stream: work queued earlier on the null stream (where callers such as
+    // torch place their copies by default) completes before the library reads its inputs
+    HIP_OK(hipStreamCreateWithFlags(&c.stream, hipStreamDefault));
+    if (hipMalloc(&c.g_buf, (size_t)BZ_MAX_K * BZ_MAX_N) != hipSuccess) return BZ_ERR_NOMEM;
+    if (hipMalloc(&c.cs, sizeof(CodeState)) != hipSuccess) return BZ_ERR_NOMEM;
+    if (hipMalloc(&c.rows, sizeof(u32) * BZ_MAX_M * BZ_MAX_K * ROW_WORDS) != hipSuccess) return BZ_ERR_NOMEM;
+    if (hipMalloc(&c.binom, sizeof(u64) * 65 * 65) != hipSuccess) return BZ_ERR_NOMEM;
+    if (hipMalloc(&c.hist, sizeof(u64) * BZ_MAX_STAGES * (BZ_MAX_N + 1)) != hipSuccess) return BZ_ERR_NOMEM;
+    if (hipHostMalloc(&c.host_res, sizeof(CodeResult), hipHostMallocDefault) != hipSuccess) return BZ_ERR_NOMEM;
+    if (hipHostMalloc(&c.host_hist, sizeof(u64) * BZ_MAX_STAGES * (BZ_MAX_N + 1), hipHostMallocDefault) !=
+        hipSuccess)
+        return BZ_ERR_NOMEM;
+    // binomial coefficients C(c, i), c, i <= 64 (exact in 64 bits)
+    static u64 tab[65 * 65];
+    for (int a = 0; a <= 64; a++)
+        for (int b = 0; b <= 64; b++) tab[a * 65 + b] = (b > a) ? 0 : (b == 0 || b == a) ? 1 : 0;
+    for (int a = 2; a <= 64; a++)
+        for (int b = 1; b < a; b++) tab[a * 65 + b] = tab[(a - 1) * 65 + b - 1] + tab[(a - 1) * 65 + b];
+    HIP_OK(hipMemcpy(c.binom, tab, sizeof(tab), hipMemcpyHostToDevice));
+    for (auto &e : c.ev) HIP_OK(hipEventCreate(&e));
+    c.ready = true;
+    return BZ_OK;
+}
+
+int get_ctx(int dev, DevCtx **out) {
+    if (dev < 0 || dev >= MAX_DEV) return BZ_ERR_ARG;
+    std::lock_guard<std::mutex> lk(g_init_mu);
+    int st = init_ctx(dev);
+    if (st != BZ_OK) return st;
+    *out = &g_ctx[dev];
+    return BZ_OK;
+}
+
+__global__ void zero_u64(u64 *p, size_t n) {
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        p[i] = 0;
+}
+
+// ---- kernel dispatch over (P, words)
+template <int P>
+hipError_t launch_decompose(int WF, const uint8_t *G, CodeState *cs, u32 *rows, RunArgs a, hipStream_t s) {
+    switch (WF) {
+    case 1: decompose_kernel<P, 1><<<1, 64, 0, s>>>(G, cs, rows, a); break;
+    case 2: decompose_kernel<P, 2><<<1, 64, 0, s>>>(G, cs, rows, a); break;
+    case 3: decompose_kernel<P, 3><<<1, 64, 0, s>>>(G, cs, rows, a); break;
+    default: decompose_kernel<P, 4><<<1, 64, 0, s>>>(G, cs, rows, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <int P, bool H>
+hipError_t launch_enum_h(int W, int grid, CodeState *cs, const u32 *rows, const u64 *binom, u64 *hist,
+                         hipStream_t s) {
+    switch (W) {
+    case 1: enum_kernel<P, 1, H><<<grid, 256, 0, s>>>(cs, rows, binom, hist); break;
+    case 2: enum_kernel<P, 2, H><<<grid, 256, 0, s>>>(cs, rows, binom, hist); break;
+    case 3: enum_kernel<P, 3, H><<<grid, 256, 0, s>>>(cs, rows, binom, hist); break;
+    default: enum_kernel<P, 4, H><<<grid, 256, 0, s>>>(cs, rows, binom, hist); break;
+    }
+    return hipGetLastError();
+}
+
+template <int P>
+hipError_t launch_enum(bool hist_mode, int W, int grid, CodeState *cs, const u32 *rows, const u64 *binom,
+                       u64 *hist, hipStream_t s) {
+    return hist_mode ? launch_enum_h<P, true>(W, grid, cs, rows, binom, hist, s)
+                     : launch_enum_h<P, false>(W, grid, cs, rows, binom, hist, s);
+}
+
+int check_args(int p, int n, int k, const void *G, const void *out) {
+    if (p != 3 && p != 7) return BZ_ERR_ARG;
+    if (n < 1 || n > BZ_MAX_N || k < 1 || k > BZ_MAX_K || k > n) return BZ_ERR_ARG;
+    if (!G || !out) return BZ_ERR_ARG;
+    return BZ_OK;
+}
+
+// Rebuild the trace from the per-stage minima and counts; returns the status.
+int finish(int p, int n, int k, int flags, u64 max_cw, const CodeResult &r, bz_result *out) {
+    std::memset(out, 0, sizeof *out);
+    out->m = r.m;
+    for (int j = 0; j < r.m && j < BZ_MAX_M; j++) out->ranks[j] = r.ranks[j];
+    if (r.status != BZ_OK) return r.status;
+    StageDesc st[BZ_MAX_STAGES];
+    int complete = 1;
+    u64 total = 0;
+    int ns = 0;
+    const int U0 = n - k + 1;
+    if ((flags & FLAG_NO_TERM) || U0 > 1)
+        ns = build_schedule(p, k, r.m, r.ranks, flags, max_cw ? max_cw : DEFAULT_LIMIT, 1, st, &complete, &total);
+    if (ns != r.n_table) return BZ_ERR_DEVICE;
+    int U = U0, term = -1;
+    out->terminated_by = 2;
+    for (int s = 0; s < ns; s++) {
+        bz_stage &o = out->stages[s];
+        o.g = st[s].g;
+        o.j = st[s].j;
+        o.codewords = r.stage_count[s];
+        o.stage_min = r.stage_min[s];
+        U = std::min(U, r.stage_min[s]);
+        o.upper_after = U;
+        o.lower_after = st[s].L;
+        out->codewords_total += o.codewords;
+        out->n_stages = s + 1;
+        out->terminated_by = 1;
+        if (st[s].check && st[s].L >= U) {
+            term = s;
+            out->terminated_by = 0;
+            break;
+        }
+    }
+    if (term != r.term_stage) return BZ_ERR_DEVICE;  // device and host disagree on the schedule
+    out->d = U;
+    if (term < 0 && !r.table_complete) {
+        out->terminated_by = 1;
+        return BZ_ERR_LIMIT;
+    }
+    return BZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void bz_default_options(bz_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->check = BZ_CHECK_STAGE;
+    o->identity_skip = 1;
+}
+
+const char *bz_status_str(int s) {
+    switch (s) {
+    case BZ_OK: return "ok";
+    case BZ_ERR_ARG: return "invalid argument";
+    case BZ_ERR_VALUE: return "generator entry >= p";
+    case BZ_ERR_RANK: return "generator matrix has rank < k";
+    case BZ_ERR_DEVICE: return "HIP device error or no gfx950 device";
+    case BZ_ERR_NOMEM: return "out of memory";
+    case BZ_ERR_LIMIT: return "work limit reached";
+    default: return "unknown status";
+    }
+}
+
+int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, const bz_options *opt,
+                       bz_result *out) {
+    int st = check_args(p, n, k, G, out);
+    if (st != BZ_OK) return st;
+    bz_options o;
+    if (opt) o = *opt;
+    else bz_default_options(&o);
+    if (o.check != BZ_CHECK_STAGE && o.check != BZ_CHECK_ROUND) return BZ_ERR_ARG;
+    if (o.histograms && !o.hist_out) return BZ_ERR_ARG;
+    if (o.blocks_per_cu < 0 || o.blocks_per_cu > 64) return BZ_ERR_ARG;
+    DevCtx *c = nullptr;
+    st = get_ctx(o.device, &c);
+    if (st != BZ_OK) return st;
+    std::lock_guard<std::mutex> lk(c->mu);
+    HIP_OK(hipSetDevice(o.device));
+    hipStream_t s = o.hip_stream ? (hipStream_t)o.hip_stream : c->stream;
+
+    const int flags = (o.check == BZ_CHECK_ROUND ? FLAG_ROUND : 0) | (o.no_termination ? FLAG_NO_TERM : 0) |
+                      (o.identity_skip ? FLAG_SKIP : 0) | (o.histograms ? FLAG_HIST : 0);
+    const u64 max_cw = o.max_codewords ? o.max_codewords : DEFAULT_LIMIT;
+    const int WF = (n + 31) / 32;
+    int W = o.identity_skip ? (n - k + 31) / 32 : WF;
+    if (W < 1) W = 1;
+    const int grid = c->cu * (o.blocks_per_cu ? o.blocks_per_cu : 4);
+
+    const uint8_t *Gd = G;
+    if (!G_is_device) {
+        HIP_OK(hipMemcpyAsync(c->g_buf, G, (size_t)k * n, hipMemcpyHostToDevice, s));
+        Gd = c->g_buf;
+    }
+    if (o.histograms) {
+        zero_u64<<<256, 256, 0, s>>>(c->hist, (size_t)BZ_MAX_STAGES * (BZ_MAX_N + 1));
+        HIP_OK(hipGetLastError());
+    }
+    RunArgs a;
+    a.n = n;
+    a.k = k;
+    a.flags = flags;
+    a.U0 = n - k + 1;
+    a.max_codewords = max_cw;
+    a.target_chunks = (u64)grid * 16;
+    if (o.timing) HIP_OK(hipEventRecord(c->ev[0], s));
+    HIP_OK(p == 3 ? launch_decompose<3>(WF, Gd, c->cs, c->rows, a, s)
+                  : launch_decompose<7>(WF, Gd, c->cs, c->rows, a, s));
+    if (o.timing) HIP_OK(hipEventRecord(c->ev[1], s));
+    HIP_OK(p == 3 ? launch_enum<3>(o.histograms != 0, W, grid, c->cs, c->rows, c->binom, c->hist, s)
+                  : launch_enum<7>(o.histograms != 0, W, grid, c->cs, c->rows, c->binom, c->hist, s));
+    if (o.timing) HIP_OK(hipEventRecord(c->ev[2], s));
+    HIP_OK(hipMemcpyAsync(c->host_res, &c->cs->res, sizeof(CodeResult), hipMemcpyDeviceToHost, s));
+    if (o.histograms)
+        HIP_OK(hipMemcpyAsync(c->host_hist, c->hist, sizeof(u64) * BZ_MAX_STAGES * (BZ_MAX_N + 1),
+                              hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    st = finish(p, n, k, flags, max_cw, *c->host_res, out);
+    if (o.timing) {
+        HIP_OK(hipEventElapsedTime(&out->decompose_ms, c->ev[0], c->ev[1]));
+        HIP_OK(hipEventElapsedTime(&out->enum_ms, c->ev[1], c->ev[2]));
+    }
+    if (o.histograms && (st == BZ_OK || st == BZ_ERR_LIMIT)) {
+        for (int sidx = 0; sidx < out->n_stages; sidx++)
+            for (int w = 0; w <= n; w++)
+                o.hist_out[(size_t)sidx * (n + 1) + w] = c->host_hist[(size_t)sidx * (BZ_MAX_N + 1) + w];
+    }
+    return st;
+}
+
+int bz_min_distance(int p, int n, int k, const uint8_t *G, bz_result *out) {
+    return bz_min_distance_ex(p, n, k, G, 0, nullptr, out);
+}
+
+// ---------------------------------------------------------------- sliced ops
+int bz_sliced_pack(int p, int enc, int nvec, int nsym, const uint8_t *sym, uint32_t *planes, void *stream) {
+    if ((p != 3 && p != 7) || nvec < 0 || nsym < 1 || !sym || !planes) return BZ_ERR_ARG;
+    if (enc != BZ_ENC_NATURAL && !(enc == BZ_ENC_KAT && p == 3)) return BZ_ERR_ARG;
+    const long long total = (long long)nvec * ((nsym + 31) / 32);
+    if (total == 0) return BZ_OK;
+    const int blocks = (int)((total + 255) / 256);
+    if (p == 3) pack_kernel<3><<<blocks, 256, 0, (hipStream_t)stream>>>(enc, nvec, nsym, sym, planes);
+    else pack_kernel<7><<<blocks, 256, 0, (hipStream_t)stream>>>(enc, nvec, nsym, sym, planes);
+    return hipGetLastError() == hipSuccess ? BZ_OK : BZ_ERR_DEVICE;
+}
+
+int bz_sliced_unpack(int p, int enc, int nvec, int nsym, const uint32_t *planes, uint8_t *sym, void *stream) {
+    if ((p != 3 && p != 7) || nvec < 0 || nsym < 1 || !sym || !planes) return BZ_ERR_ARG;
+    if (enc != BZ_ENC_NATURAL && !(enc == BZ_ENC_KAT && p == 3)) return BZ_ERR_ARG;
+    const long long total = (long long)nvec * nsym;
+    if (total == 0) return BZ_OK;
+    const int blocks = (int)((total + 255) / 256);
+    if (p == 3) unpack_kernel<3><<<blocks, 256, 0, (hipStream_t)stream>>>(enc, nvec, nsym, planes, sym);
+    else unpack_kernel<7><<<blocks, 256, 0, (hipStream_t)stream>>>(enc, nvec, nsym, planes, sym);
+    return hipGetLastError() == hipSuccess ? BZ_OK : BZ_ERR_DEVICE;
+}
+
+int bz_sliced_op(int p, int op, int nvec, int nsym, const uint32_t *a, const uint32_t *b, uint32_t *out,
+                 int reps, void *stream) {
+    if ((p != 3 && p != 7) || nvec < 0 || nsym < 1 || !a || !out || reps < 1) return BZ_ERR_ARG;
+    if (op < BZ_OP_ADD || op > BZ_OP_KAT_ADD || (op == BZ_OP_KAT_ADD && p != 3)) return BZ_ERR_ARG;
+    if (op != BZ_OP_DOUBLE && !b) return BZ_ERR_ARG;
+    const int words = (nsym + 31) / 32;
+    const long long total = (long long)nvec * words;
+    if (total == 0) return BZ_OK;
+    const int blocks = (int)((total + 255) / 256);
+    if (p == 3) op_kernel<3><<<blocks, 256, 0, (hipStream_t)stream>>>(op, nvec, words, a, b, out, reps);
+    else op_kernel<7><<<blocks, 256, 0, (hipStream_t)stream>>>(op, nvec, words, a, b, out, reps);
+    return hipGetLastError() == hipSuccess ? BZ_OK : BZ_ERR_DEVICE;
+}
+
+}  // extern "C"

@@ -1,0 +1,254 @@
+"""GPU parity: the HIP library (through its C ABI) against the CPU oracle.
+
+Every comparison is bit-exact: d, the information-set ranks, and the whole
+stage trace (g, j, combinations evaluated, stage minimum, U and L after the
+stage), the termination reason and, in histogram mode, the weight
+distribution of every stage.  Inputs come from the seeded generators and from
+classical codes; expected values come from the oracle only.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import codes
+from paper_2603_29942_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("status", "d", "m", "ranks", "stages", "terminated_by", "codewords_total")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def bz():
+    import torch
+    assert torch.cuda.is_available(), "no GPU visible"
+    from paper_2603_29942_amd import bz as _bz
+    _bz.lib()
+    return _bz
+
+
+def same(gpu, orc, hist=False):
+    for key in KEYS:
+        assert gpu[key] == orc[key], (key, gpu[key], orc[key])
+    if hist:
+        assert np.array_equal(gpu["hist"], orc["hist"])
+
+
+def run_both(bz, oracle, p, G, label, hist=False, **kw):
+    kw.setdefault("max_codewords", 1 << 34)  # bounds the GPU run even if termination misbehaved
+    say(f"case {label} p={p} shape={tuple(G.shape)} {kw}")
+    okw = {k: v for k, v in kw.items() if k in ("check", "no_termination", "max_codewords")}
+    orc = oracle.min_distance(p, G, histograms=hist, **okw)
+    gpu = bz.min_distance(p, G, histograms=hist, **kw)
+    same(gpu, orc, hist)
+    return gpu
+
+
+# ---------------------------------------------------------------- arithmetic
+
+
+def _pairs(p, nvec, nsym, seed):
+    rng = np.random.default_rng(seed)
+    a = rng.integers(0, p, size=(nvec, nsym), dtype=np.uint8)
+    b = rng.integers(0, p, size=(nvec, nsym), dtype=np.uint8)
+    # every (x, y) pair somewhere in the first vector
+    pa = np.array([x for x in range(p) for _ in range(p)], dtype=np.uint8)
+    pb = np.array([y for _ in range(p) for y in range(p)], dtype=np.uint8)
+    a[0, :p * p], b[0, :p * p] = pa, pb
+    return a, b
+
+
+@pytest.mark.parametrize("p", [3, 7])
+@pytest.mark.parametrize("nsym", [49, 64, 100, 512])
+def test_sliced_arithmetic(bz, p, nsym):
+    import torch
+    say(f"case sliced p={p} nsym={nsym}")
+    a, b = _pairs(p, 5, nsym, nsym + p)
+    A = bz.bz_sliced_pack(p, torch.from_numpy(a).cuda())
+    B = bz.bz_sliced_pack(p, torch.from_numpy(b).cuda())
+    assert np.array_equal(bz.bz_sliced_unpack(p, A, nsym).cpu().numpy(), a)
+    ai, bi = a.astype(int), b.astype(int)
+    expect = {bz.OP_ADD: (ai + bi) % p, bz.OP_SUB: (ai - bi) % p, bz.OP_DOUBLE: (2 * ai) % p}
+    for op, want in expect.items():
+        out = bz.bz_sliced_op(p, op, A, B, nsym, reps=3)
+        assert np.array_equal(bz.bz_sliced_unpack(p, out, nsym).cpu().numpy(), want), op
+    for op, want in [(bz.OP_ISO_ADD, (ai + bi) % p != 0), (bz.OP_ISO_SUB, (ai - bi) % p != 0)]:
+        out = bz.bz_sliced_op(p, op, A, B, nsym).cpu().numpy().view(np.uint32)
+        bits = np.unpackbits(out[:, 0, :].view(np.uint8), axis=1, bitorder="little")[:, :nsym]
+        assert np.array_equal(bits.astype(bool), want), op
+        assert not out[:, 1:, :].any()
+    if p == 3:
+        Ak = bz.bz_sliced_pack(3, torch.from_numpy(a).cuda(), encoding=bz.ENC_KAT)
+        Bk = bz.bz_sliced_pack(3, torch.from_numpy(b).cuda(), encoding=bz.ENC_KAT)
+        out = bz.bz_sliced_op(3, bz.OP_KAT_ADD, Ak, Bk, nsym)
+        assert np.array_equal(bz.bz_sliced_unpack(3, out, nsym, encoding=bz.ENC_KAT).cpu().numpy(),
+                              (ai + bi) % 3)
+
+
+def test_sliced_paper_examples(bz):
+    """Examples 1-2 of Sec. 2.1 (5+2 = 0, 5+6 = 4 in F_7) and 2*3 = 6, 4*3 = 5 (Sec. 4.2)."""
+    import torch
+    ex = codes.golden("paper_arith_examples.json")
+    a = torch.tensor([[e["V"] for e in ex["algorithm1"]]], dtype=torch.uint8).cuda()
+    b = torch.tensor([[e["W"] for e in ex["algorithm1"]]], dtype=torch.uint8).cuda()
+    out = bz.bz_sliced_op(7, bz.OP_ADD, bz.bz_sliced_pack(7, a), bz.bz_sliced_pack(7, b), 2)
+    assert bz.bz_sliced_unpack(7, out, 2).cpu().tolist() == [[e["result"] for e in ex["algorithm1"]]]
+    three = bz.bz_sliced_pack(7, torch.tensor([[3]], dtype=torch.uint8).cuda())
+    twice = bz.bz_sliced_op(7, bz.OP_DOUBLE, three, None, 1)
+    four = bz.bz_sliced_op(7, bz.OP_DOUBLE, twice, None, 1)
+    assert bz.bz_sliced_unpack(7, twice, 1).item() == 6 and bz.bz_sliced_unpack(7, four, 1).item() == 5
+
+
+# ---------------------------------------------------------------- minimum distance
+
+
+CLASSICAL = [
+    ("golay", 3, codes.ternary_golay, 5),
+    ("ext_golay", 3, codes.extended_golay, 6),
+    ("tetracode", 3, lambda: np.array([[1, 1, 1, 0], [0, 1, 2, 1]], dtype=np.uint8), 3),
+    ("rs_7_3", 7, lambda: codes.reed_solomon(7, 7, 3), 5),
+    ("rs_6_4", 7, lambda: codes.reed_solomon(7, 6, 4), 3),
+    ("rs_7_6", 7, lambda: codes.reed_solomon(7, 7, 6), 2),
+    ("simplex_7", 7, lambda: codes.simplex(2, 7), 7),
+    ("simplex_3", 3, lambda: codes.simplex(3, 3), 9),
+    ("hamming_3", 3, lambda: codes.hamming(3, 3), 3),
+    ("hamming_7", 7, lambda: codes.hamming(2, 7), 3),
+    ("golay+hamming", 3, lambda: codes.direct_sum(codes.ternary_golay(), codes.hamming(3, 3)), 3),
+]
+
+
+@pytest.mark.parametrize("name,p,builder,d", CLASSICAL, ids=[c[0] for c in CLASSICAL])
+def test_classical_codes(bz, oracle, name, p, builder, d):
+    G = builder()
+    for check in ("stage", "round"):
+        for skip in (True, False):
+            r = run_both(bz, oracle, p, G, name, check=check, identity_skip=skip)
+            assert r["d"] == d
+
+
+def test_config1_all_seeds(bz, oracle):
+    """F_3 [40,10], seeds 0..99 (brute force pins the oracle on these)."""
+    for seed in range(100):
+        p, G = synth.config_code(1, seed)
+        run_both(bz, oracle, p, G, f"cfg1 seed={seed}", hist=(seed < 10))
+
+
+SHAPES = [(3, 33, 8), (3, 63, 12), (3, 65, 10), (3, 95, 8), (3, 97, 10), (3, 127, 8), (3, 128, 12),
+          (7, 33, 6), (7, 64, 6), (7, 65, 5), (7, 128, 5), (7, 100, 8), (3, 70, 64), (7, 70, 64),
+          (3, 40, 30), (7, 30, 20), (7, 2, 1), (3, 64, 1), (7, 128, 1), (3, 20, 10), (7, 16, 8),
+          (3, 128, 6), (7, 90, 10), (3, 24, 12), (3, 30, 15), (3, 44, 22), (7, 26, 13), (3, 32, 16),
+          (7, 32, 8), (3, 96, 12), (7, 96, 7)]
+
+
+@pytest.mark.parametrize("p,n,k", SHAPES, ids=[f"F{p}_{n}_{k}" for p, n, k in SHAPES])
+def test_random_shapes(bz, oracle, p, n, k):
+    for seed in range(3):
+        G = synth.random_generator(p, n, k, seed, stream=500)
+        for check, skip in (("stage", True), ("round", True), ("stage", False)):
+            run_both(bz, oracle, p, G, f"shape seed={seed}", check=check, identity_skip=skip,
+                     max_codewords=1 << 30)
+
+
+@pytest.mark.parametrize("p,n,k", [(3, 9, 4), (3, 12, 5), (7, 7, 3), (7, 9, 3), (3, 13, 3), (7, 5, 4),
+                                   (3, 40, 6), (7, 33, 4), (3, 70, 5)])
+def test_no_termination_histograms(bz, oracle, p, n, k):
+    """Every stage g = 1..k, j = 1..m, with full per-stage weight distributions."""
+    for seed in range(3):
+        G = synth.random_generator(p, n, k, seed, stream=600)
+        for skip in (True, False):
+            run_both(bz, oracle, p, G, f"noterm seed={seed}", hist=True, no_termination=True,
+                     identity_skip=skip)
+
+
+def test_edge_cases(bz, oracle):
+    for p in (3, 7):
+        for n in (1, 2, 31, 32, 33, 64, 65, 128):
+            run_both(bz, oracle, p, codes.repetition(n, p), f"repetition n={n}")
+            if n <= 64:
+                r = run_both(bz, oracle, p, codes.full_space(n, p), f"full n={n}")
+                assert r["stages"] == [] and r["d"] == 1 and r["terminated_by"] == 2
+                r = run_both(bz, oracle, p, codes.full_space(n, p), f"full noterm n={n}",
+                             no_termination=(n <= 8))
+            if 2 <= n <= 65:
+                run_both(bz, oracle, p, codes.zero_sum(n, p), f"zero-sum n={n}")
+        # zero columns never become pivots
+        G = synth.random_generator(p, 40, 8, 3, stream=700)
+        G[:, 5] = 0
+        G[:, 31:35] = 0
+        run_both(bz, oracle, p, G, "zero columns")
+
+
+def test_error_statuses(bz, oracle):
+    G = synth.random_generator(3, 30, 6, 1, stream=800)
+    bad = G.copy()
+    bad[2, 17] = 3
+    run_both(bz, oracle, 3, bad, "value error")
+    low = G.copy()
+    low[4] = (low[1].astype(int) * 2 + low[3]) % 3
+    r = run_both(bz, oracle, 3, low, "rank error")
+    assert r["status"] == -3
+    zero = G.copy()
+    zero[0] = 0
+    run_both(bz, oracle, 3, zero, "zero row")
+    G7 = synth.random_generator(7, 20, 10, 1, stream=800)
+    G7[:, 3] = 9
+    run_both(bz, oracle, 7, G7, "value error F7")
+    for limit in (1, 50, 1000, 20000):
+        for p, cfg in ((3, 2), (7, 3)):
+            _, G = synth.config_code(cfg, 0)
+            r = run_both(bz, oracle, p, G, f"limit {limit}", max_codewords=limit)
+            assert r["status"] == -6
+
+
+def test_device_input_and_determinism(bz, oracle):
+    import torch
+    p, G = synth.config_code(1, 7)
+    ref = oracle.min_distance(p, G)
+    st, res = bz.bz_min_distance_ex(p, torch.from_numpy(G).cuda())
+    same(bz.result_dict(st, res), ref)
+    for bpc in (1, 2, 4, 8, 0):
+        for _ in range(3):
+            same(bz.min_distance(p, G, blocks_per_cu=bpc), ref)
+
+
+def test_config2_full_size(bz, oracle):
+    """F_3 [72,36]: the whole run against the oracle."""
+    for seed in (0, 2):
+        p, G = synth.config_code(2, seed)
+        run_both(bz, oracle, p, G, f"cfg2 seed={seed}")
+
+
+def test_config3_full_size(bz, oracle):
+    """F_7 [48,24]: the whole run against the oracle (about 1.2e9 combinations)."""
+    p, G = synth.config_code(3, 0)
+    run_both(bz, oracle, p, G, "cfg3 seed=0")
+
+
+def test_config3_sampled_seeds(bz, oracle):
+    """More F_7 [48,24] codes: the oracle recomputes the final stage's minimum
+    and count directly (one stage alone), and the trace obeys the bound logic."""
+    import math
+    for seed in (1, 2, 3):
+        p, G = synth.config_code(3, seed)
+        say(f"case cfg3 sampled seed={seed}")
+        r = bz.min_distance(p, G, max_codewords=1 << 34)
+        assert r["status"] == 0
+        m, gam, ranks, _ = oracle.decompose(p, G)
+        assert r["m"] == m and r["ranks"] == list(ranks)
+        U = 48 - 24 + 1
+        for g, j, cnt, smin, Ua, La in r["stages"]:
+            assert cnt == math.comb(24, g) * 6 ** (g - 1)
+            U = min(U, smin)
+            assert Ua == U
+        assert r["stages"][-1][5] >= r["d"] == U
+        # every stage up to round 5 recomputed by the oracle, one stage at a time
+        for g, j, cnt, smin, _, _ in r["stages"]:
+            if g <= 5:
+                mn, ocnt, _ = oracle.stage_enum(p, gam[j - 1], g)
+                assert (mn, ocnt) == (smin, cnt), (g, j)

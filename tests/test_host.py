@@ -1,0 +1,97 @@
+"""CPU-only checks of the GPU library: host logic and the exported C ABI.
+
+No GPU work is launched here: the shared host/device code is compiled with
+g++ and run on the CPU, and the HIP library is only loaded and called on
+argument-validation paths that return before touching a device.
+"""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CSRC = os.path.join(ROOT, "paper_2603_29942_amd", "csrc")
+HEADER = os.path.join(ROOT, "include", "bz.h")
+
+
+def test_host_checks(tmp_path):
+    exe = os.path.join(str(tmp_path), "host_checks")
+    subprocess.run(["g++", "-std=c++17", "-O1", "-Wall", "-DBZ_HD=inline", "-I", CSRC, "-I",
+                    os.path.join(ROOT, "include"), os.path.join(ROOT, "tests", "host_checks.cpp"), "-o", exe],
+                   check=True)
+    out = subprocess.run([exe], capture_output=True, text=True)
+    assert out.returncode == 0, out.stdout
+    assert out.stdout.split() == ["OK", "arith", "OK", "schedule", "OK", "unrank"]
+
+
+def _declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*(bz_\w+)\s*\(", src, re.M)))
+
+
+@pytest.fixture(scope="module")
+def bzlib():
+    from paper_2603_29942_amd import bz
+    if not os.path.exists(bz.LIB_PATH):
+        from paper_2603_29942_amd import build
+        build.build()
+    return bz
+
+
+def test_exports(bzlib):
+    names = _declared()
+    assert set(names) == set(bzlib.EXPORTS)
+    L = bzlib.lib()
+    for name in names:
+        assert hasattr(L, name), name
+    syms = subprocess.run(["nm", "-D", "--defined-only", bzlib.LIB_PATH], capture_output=True, text=True).stdout
+    for name in names:
+        assert re.search(rf"\bT {name}$", syms, re.M), name
+
+
+def test_struct_layout(bzlib, tmp_path):
+    """The ctypes mirrors match the C layout that gcc computes from include/bz.h."""
+    src = os.path.join(str(tmp_path), "layout.c")
+    with open(src, "w") as f:
+        f.write('#include <stdio.h>\n#include <stddef.h>\n#include "bz.h"\n'
+                'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(bz_stage), sizeof(bz_result),'
+                ' offsetof(bz_result, stages), offsetof(bz_result, codewords_total), sizeof(bz_options),'
+                ' offsetof(bz_options, max_codewords), offsetof(bz_options, blocks_per_cu)); return 0;}\n')
+    exe = os.path.join(str(tmp_path), "layout")
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
+    c_vals = [int(x) for x in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
+    py_vals = [ctypes.sizeof(bzlib.bz_stage), ctypes.sizeof(bzlib.bz_result), bzlib.bz_result.stages.offset,
+               bzlib.bz_result.codewords_total.offset, ctypes.sizeof(bzlib.bz_options),
+               bzlib.bz_options.max_codewords.offset, bzlib.bz_options.blocks_per_cu.offset]
+    assert c_vals == py_vals
+
+
+def test_defaults_and_status_strings(bzlib):
+    o = bzlib.bz_default_options()
+    assert (o.check, o.no_termination, o.identity_skip, o.histograms, o.max_codewords) == (0, 0, 1, 0, 0)
+    for st, text in [(0, "ok"), (-1, "invalid argument"), (-3, "generator matrix has rank < k"),
+                     (-6, "work limit reached")]:
+        assert bzlib.bz_status_str(st) == text
+
+
+def test_argument_errors_need_no_device(bzlib):
+    G = np.zeros((4, 10), dtype=np.uint8)
+    for p, Gx in [(5, G), (2, G), (3, np.zeros((11, 10), dtype=np.uint8)),
+                  (3, np.zeros((65, 70), dtype=np.uint8)), (7, np.zeros((2, 129), dtype=np.uint8))]:
+        st, _ = bzlib.bz_min_distance(p, Gx)
+        assert st == bzlib.ERR_ARG
+    o = bzlib.bz_default_options()
+    o.check = 5
+    st, _ = bzlib.bz_min_distance_ex(3, G, o)
+    assert st == bzlib.ERR_ARG
+    o = bzlib.bz_default_options()
+    o.histograms = 1  # without a buffer
+    st, _ = bzlib.bz_min_distance_ex(3, G, o)
+    assert st == bzlib.ERR_ARG
+    L = bzlib.lib()
+    assert L.bz_sliced_op(7, bzlib.OP_KAT_ADD, 1, 32, ctypes.c_void_p(8), ctypes.c_void_p(8),
+                          ctypes.c_void_p(8), 1, None) == bzlib.ERR_ARG
+    assert L.bz_sliced_pack(5, 0, 1, 32, ctypes.c_void_p(8), ctypes.c_void_p(8), None) == bzlib.ERR_ARG
