@@ -100,6 +100,8 @@ typedef struct {
     int32_t device;           /* HIP device ordinal */
     int32_t blocks_per_cu;    /* enumeration grid: workgroups per compute unit; 0 = default */
     int32_t timing;           /* 1: fill bz_result.decompose_ms / enum_ms */
+    int32_t wait_timeout_s;   /* workgroups that wait for earlier stages give up (BZ_ERR_DEVICE)
+                                 after this many seconds; 0 = default (120) */
 } bz_options;
 
 /* Fill *o with the defaults above. */

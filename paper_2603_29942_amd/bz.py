@@ -45,7 +45,8 @@ class bz_options(ctypes.Structure):
                 ("identity_skip", ctypes.c_int32), ("histograms", ctypes.c_int32),
                 ("hist_out", ctypes.POINTER(ctypes.c_uint64)), ("max_codewords", ctypes.c_uint64),
                 ("hip_stream", ctypes.c_void_p), ("device", ctypes.c_int32),
-                ("blocks_per_cu", ctypes.c_int32), ("timing", ctypes.c_int32)]
+                ("blocks_per_cu", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("wait_timeout_s", ctypes.c_int32)]
 
 
 _lib = None

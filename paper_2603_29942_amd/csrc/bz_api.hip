@@ -22,6 +22,7 @@ constexpr int MAX_DEV = 16;
 struct DevCtx {
     bool ready = false;
     int cu = 0;
+    u64 ticks_per_s = 0;
     hipStream_t stream = nullptr;
     uint8_t *g_buf = nullptr;
     CodeState *cs = nullptr;
@@ -36,6 +37,14 @@ struct DevCtx {
 
 DevCtx g_ctx[MAX_DEV];
 std::mutex g_init_mu;
+
+// binomial coefficients C(c, i), c, i <= 64 (exact in 64 bits)
+const u64 *host_binom() {
+    static u64 tab[65 * 65];
+    static std::once_flag once;
+    std::call_once(once, [] { fill_binomials(tab); });
+    return tab;
+}
 
 #define HIP_OK(expr)                              \
     do {                                          \
@@ -52,6 +61,9 @@ int init_ctx(int dev) {
     HIP_OK(hipGetDeviceProperties(&prop, dev));
     if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return BZ_ERR_DEVICE;
     c.cu = prop.multiProcessorCount;
+    int rate_khz = 0;
+    HIP_OK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
+    c.ticks_per_s = (u64)(rate_khz > 0 ? rate_khz : 100000) * 1000ull;
     // a blocking stream: work queued earlier on the null stream (where callers such as
     // torch place their copies by default) completes before the library reads its inputs
     HIP_OK(hipStreamCreateWithFlags(&c.stream, hipStreamDefault));
@@ -64,13 +76,7 @@ int init_ctx(int dev) {
     if (hipHostMalloc(&c.host_hist, sizeof(u64) * BZ_MAX_STAGES * (BZ_MAX_N + 1), hipHostMallocDefault) !=
         hipSuccess)
         return BZ_ERR_NOMEM;
-    // binomial coefficients C(c, i), c, i <= 64 (exact in 64 bits)
-    static u64 tab[65 * 65];
-    for (int a = 0; a <= 64; a++)
-        for (int b = 0; b <= 64; b++) tab[a * 65 + b] = (b > a) ? 0 : (b == 0 || b == a) ? 1 : 0;
-    for (int a = 2; a <= 64; a++)
-        for (int b = 1; b < a; b++) tab[a * 65 + b] = tab[(a - 1) * 65 + b - 1] + tab[(a - 1) * 65 + b];
-    HIP_OK(hipMemcpy(c.binom, tab, sizeof(tab), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(c.binom, host_binom(), sizeof(u64) * 65 * 65, hipMemcpyHostToDevice));
     for (auto &e : c.ev) HIP_OK(hipEventCreate(&e));
     c.ready = true;
     return BZ_OK;
@@ -92,33 +98,73 @@ __global__ void zero_u64(u64 *p, size_t n) {
 
 // ---- kernel dispatch over (P, words)
 template <int P>
-hipError_t launch_decompose(int WF, const uint8_t *G, CodeState *cs, u32 *rows, RunArgs a, hipStream_t s) {
+hipError_t launch_decompose(int WF, const uint8_t *G, CodeState *cs, u32 *rows, const u64 *binom, RunArgs a,
+                            hipStream_t s) {
     switch (WF) {
-    case 1: decompose_kernel<P, 1><<<1, 64, 0, s>>>(G, cs, rows, a); break;
-    case 2: decompose_kernel<P, 2><<<1, 64, 0, s>>>(G, cs, rows, a); break;
-    case 3: decompose_kernel<P, 3><<<1, 64, 0, s>>>(G, cs, rows, a); break;
-    default: decompose_kernel<P, 4><<<1, 64, 0, s>>>(G, cs, rows, a); break;
+    case 1: decompose_kernel<P, 1><<<1, 64, 0, s>>>(G, cs, rows, binom, a); break;
+    case 2: decompose_kernel<P, 2><<<1, 64, 0, s>>>(G, cs, rows, binom, a); break;
+    case 3: decompose_kernel<P, 3><<<1, 64, 0, s>>>(G, cs, rows, binom, a); break;
+    default: decompose_kernel<P, 4><<<1, 64, 0, s>>>(G, cs, rows, binom, a); break;
     }
     return hipGetLastError();
+}
+
+// The enumeration kernel is launched cooperatively: every workgroup of the grid
+// is resident at once, which its waits for earlier stages rely on.  The grid
+// (see enum_grid) is clamped to the kernel's occupancy.
+template <int P, int W, bool H>
+hipError_t launch_enum_one(int grid, CodeState *cs, const u32 *rows, const u64 *binom, u64 *hist, int lookahead,
+                           u64 timeout, hipStream_t s) {
+    void *args[] = {&cs, &rows, &binom, &hist, &lookahead, &timeout};
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(enum_kernel<P, W, H>), dim3(grid), dim3(256),
+                                      args, 0, s);
 }
 
 template <int P, bool H>
-hipError_t launch_enum_h(int W, int grid, CodeState *cs, const u32 *rows, const u64 *binom, u64 *hist,
-                         hipStream_t s) {
+hipError_t launch_enum_h(int W, int grid, CodeState *cs, const u32 *rows, const u64 *binom, u64 *hist, int la,
+                         u64 to, hipStream_t s) {
     switch (W) {
-    case 1: enum_kernel<P, 1, H><<<grid, 256, 0, s>>>(cs, rows, binom, hist); break;
-    case 2: enum_kernel<P, 2, H><<<grid, 256, 0, s>>>(cs, rows, binom, hist); break;
-    case 3: enum_kernel<P, 3, H><<<grid, 256, 0, s>>>(cs, rows, binom, hist); break;
-    default: enum_kernel<P, 4, H><<<grid, 256, 0, s>>>(cs, rows, binom, hist); break;
+    case 1: return launch_enum_one<P, 1, H>(grid, cs, rows, binom, hist, la, to, s);
+    case 2: return launch_enum_one<P, 2, H>(grid, cs, rows, binom, hist, la, to, s);
+    case 3: return launch_enum_one<P, 3, H>(grid, cs, rows, binom, hist, la, to, s);
+    default: return launch_enum_one<P, 4, H>(grid, cs, rows, binom, hist, la, to, s);
     }
-    return hipGetLastError();
 }
 
 template <int P>
-hipError_t launch_enum(bool hist_mode, int W, int grid, CodeState *cs, const u32 *rows, const u64 *binom,
-                       u64 *hist, hipStream_t s) {
-    return hist_mode ? launch_enum_h<P, true>(W, grid, cs, rows, binom, hist, s)
-                     : launch_enum_h<P, false>(W, grid, cs, rows, binom, hist, s);
+hipError_t launch_enum(bool hist_mode, int W, int grid, CodeState *cs, const u32 *rows, const u64 *binom, u64 *hist,
+                       int la, u64 to, hipStream_t s) {
+    return hist_mode ? launch_enum_h<P, true>(W, grid, cs, rows, binom, hist, la, to, s)
+                     : launch_enum_h<P, false>(W, grid, cs, rows, binom, hist, la, to, s);
+}
+
+// Largest grid the enumeration kernel may get for (p, W, histograms): the
+// schedule is dealt to exactly this many workgroups.
+template <int P, int W, bool H>
+int grid_for(int cu, int bpc) {
+    static int max_bpc = -1;
+    if (max_bpc < 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, enum_kernel<P, W, H>, 256, 0) != hipSuccess || nb < 1)
+            return -1;
+        max_bpc = nb;
+    }
+    return cu * (bpc < max_bpc ? bpc : max_bpc);
+}
+
+template <int P, bool H>
+int grid_for_w(int W, int cu, int bpc) {
+    switch (W) {
+    case 1: return grid_for<P, 1, H>(cu, bpc);
+    case 2: return grid_for<P, 2, H>(cu, bpc);
+    case 3: return grid_for<P, 3, H>(cu, bpc);
+    default: return grid_for<P, 4, H>(cu, bpc);
+    }
+}
+
+int enum_grid(int p, bool hist, int W, int cu, int bpc) {
+    if (p == 3) return hist ? grid_for_w<3, true>(W, cu, bpc) : grid_for_w<3, false>(W, cu, bpc);
+    return hist ? grid_for_w<7, true>(W, cu, bpc) : grid_for_w<7, false>(W, cu, bpc);
 }
 
 int check_args(int p, int n, int k, const void *G, const void *out) {
@@ -136,11 +182,11 @@ int finish(int p, int n, int k, int flags, u64 max_cw, const CodeResult &r, bz_r
     if (r.status != BZ_OK) return r.status;
     StageDesc st[BZ_MAX_STAGES];
     int complete = 1;
-    u64 total = 0;
     int ns = 0;
     const int U0 = n - k + 1;
     if ((flags & FLAG_NO_TERM) || U0 > 1)
-        ns = build_schedule(p, k, r.m, r.ranks, flags, max_cw ? max_cw : DEFAULT_LIMIT, 1, st, &complete, &total);
+        ns = build_schedule(p, k, r.m, r.ranks, flags, max_cw ? max_cw : DEFAULT_LIMIT, 1, r.W, host_binom(), st,
+                            &complete);
     if (ns != r.n_table) return BZ_ERR_DEVICE;
     int U = U0, term = -1;
     out->terminated_by = 2;
@@ -162,7 +208,7 @@ int finish(int p, int n, int k, int flags, u64 max_cw, const CodeResult &r, bz_r
             break;
         }
     }
-    if (term != r.term_stage) return BZ_ERR_DEVICE;  // device and host disagree on the schedule
+    if (term != ctl_term(r.ctl)) return BZ_ERR_DEVICE;  // device and host disagree on the schedule
     out->d = U;
     if (term < 0 && !r.table_complete) {
         out->terminated_by = 1;
@@ -218,7 +264,10 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, c
     const int WF = (n + 31) / 32;
     int W = o.identity_skip ? (n - k + 31) / 32 : WF;
     if (W < 1) W = 1;
-    const int grid = c->cu * (o.blocks_per_cu ? o.blocks_per_cu : 4);
+    const int bpc = o.blocks_per_cu ? o.blocks_per_cu : 4;
+    const int grid = enum_grid(p, o.histograms != 0, W, c->cu, bpc);
+    if (grid < 1) return BZ_ERR_DEVICE;
+    const u64 timeout = c->ticks_per_s * (u64)(o.wait_timeout_s > 0 ? o.wait_timeout_s : 120);
 
     const uint8_t *Gd = G;
     if (!G_is_device) {
@@ -235,13 +284,17 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, c
     a.flags = flags;
     a.U0 = n - k + 1;
     a.max_codewords = max_cw;
-    a.target_chunks = (u64)grid * 16;
+    a.grid = (uint32_t)grid;
+    a.lookahead = LOOKAHEAD;
+    a.timeout_ticks = timeout;
     if (o.timing) HIP_OK(hipEventRecord(c->ev[0], s));
-    HIP_OK(p == 3 ? launch_decompose<3>(WF, Gd, c->cs, c->rows, a, s)
-                  : launch_decompose<7>(WF, Gd, c->cs, c->rows, a, s));
+    HIP_OK(p == 3 ? launch_decompose<3>(WF, Gd, c->cs, c->rows, c->binom, a, s)
+                  : launch_decompose<7>(WF, Gd, c->cs, c->rows, c->binom, a, s));
     if (o.timing) HIP_OK(hipEventRecord(c->ev[1], s));
-    HIP_OK(p == 3 ? launch_enum<3>(o.histograms != 0, W, grid, c->cs, c->rows, c->binom, c->hist, s)
-                  : launch_enum<7>(o.histograms != 0, W, grid, c->cs, c->rows, c->binom, c->hist, s));
+    HIP_OK(p == 3 ? launch_enum<3>(o.histograms != 0, W, grid, c->cs, c->rows, c->binom, c->hist, LOOKAHEAD,
+                                   timeout, s)
+                  : launch_enum<7>(o.histograms != 0, W, grid, c->cs, c->rows, c->binom, c->hist, LOOKAHEAD,
+                                   timeout, s));
     if (o.timing) HIP_OK(hipEventRecord(c->ev[2], s));
     HIP_OK(hipMemcpyAsync(c->host_res, &c->cs->res, sizeof(CodeResult), hipMemcpyDeviceToHost, s));
     if (o.histograms)

@@ -4,14 +4,14 @@
 //                     planes, computes the information-set decomposition
 //                     Gamma_1..Gamma_m by Gauss-Jordan on bit-sliced rows (one
 //                     row per lane), packs each Gamma_j for the enumeration, and
-//                     writes the stage schedule and the initial queue state.
-//   enum_kernel       persistent: every wavefront pulls chunks of work from a
-//                     global queue that runs through the stages in order,
-//                     builds exact prefix sums in registers, finishes every
+//                     writes the stage schedule and the initial completion state.
+//   enum_kernel       persistent: every workgroup walks the stages in order and
+//                     takes its share of each stage's tiles; a lane builds the
+//                     exact prefix sums of its item in registers, finishes every
 //                     combination with the isometric addition, takes the weight
-//                     by popcount and min-reduces it; the wavefront that
-//                     completes a stage's last chunk applies the L >= U test and
-//                     stops the queue when it holds.
+//                     by popcount and min-reduces it.  The workgroup that
+//                     completes a stage last applies the L >= U test; workgroups
+//                     that already moved on to later stages stop when it holds.
 //
 // Paper: Hernando & Quintana-Orti, arXiv 2603.29942 (Sec. 2-4, Algorithm 6).
 #pragma once
@@ -23,12 +23,13 @@
 namespace bz {
 
 constexpr u32 BIG = 0x7fffffffu;
+constexpr int BIN_I = 17;  // binomials C(c, i) with i < BIN_I are kept in LDS
 
 __device__ __forceinline__ u32 uni(u32 x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 __device__ __forceinline__ u64 uni64(u64 x) {
-    u32 lo = __builtin_amdgcn_readfirstlane((u32)x);
-    u32 hi = __builtin_amdgcn_readfirstlane((u32)(x >> 32));
+    const u32 lo = __builtin_amdgcn_readfirstlane((u32)x);
+    const u32 hi = __builtin_amdgcn_readfirstlane((u32)(x >> 32));
     return ((u64)hi << 32) | lo;
 }
 
@@ -37,36 +38,64 @@ __device__ __forceinline__ T ld_acq(T *p) {
     return __hip_atomic_load(p, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
 }
 template <typename T>
+__device__ __forceinline__ T ld_relaxed(T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
 __device__ __forceinline__ void st_rel(T *p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// select word q of a small register array with a uniform index (no dynamic
-// register indexing)
-template <int N>
-__device__ __forceinline__ u32 pick(const u32 (&a)[N], int q) {
-    u32 v = a[0];
-#pragma unroll
-    for (int i = 1; i < N; i++) v = (q == i) ? a[i] : v;
-    return v;
+struct RunArgs {
+    int32_t n, k, flags, U0;
+    u64 max_codewords;
+    uint32_t grid;  // workgroups of the enumeration launch
+    int32_t lookahead;
+    u64 timeout_ticks;  // wall_clock64() ticks a workgroup may wait for earlier stages
+};
+
+// q-groups of a stage with g >= 3 computed by the 64 lanes of a wavefront
+// (lane = q - (g-3)); the same values as fill_qtable.  Returns the number of
+// tasks (wave-uniform); with tab != nullptr the lanes also store their entry.
+__device__ __forceinline__ u64 wave_qtable(int k, int g, u64 M, uint32_t cap, const u64 *__restrict__ binom,
+                                           QEntry *tab) {
+    const int lane = __lane_id();
+    const int q = g - 3 + lane;
+    const bool in = q <= k - 3;
+    u64 bases = 0, val = 0;
+    uint32_t B = 1, nb = 0;
+    if (in) {
+        qgroup(k, g, M, cap, binom, q, &bases, &B, &nb);
+        val = sat_mul((bases + 63) / 64, (u64)nb);
+    }
+    // inclusive scan of val over the lanes (saturating)
+    u64 inc = val;
+    for (int off = 1; off < 64; off <<= 1) {
+        const u64 o = __shfl_up(inc, off);
+        if (lane >= off) inc = sat_add(inc, o);
+    }
+    if (tab && in) {
+        QEntry &e = tab[lane];
+        e.first = inc - val;
+        e.bases = bases;
+        e.B = B;
+        e.nb = nb;
+    }
+    return uni64(__shfl(inc, 63));
 }
 
 // =====================================================================
 // Decomposition: one wavefront per code, lane i holds row i.
 // =====================================================================
-struct RunArgs {
-    int32_t n, k, flags, U0;
-    u64 max_codewords;
-    u64 target_chunks;
-};
-
 template <int P, int WF>
 __global__ __launch_bounds__(64) void decompose_kernel(const uint8_t *__restrict__ G, CodeState *cs,
-                                                       u32 *__restrict__ rows, RunArgs args) {
+                                                       u32 *__restrict__ rows, const u64 *__restrict__ binom,
+                                                       RunArgs args) {
     constexpr int R = (P == 3) ? 2 : 3;
+    __shared__ __align__(16) uint8_t gl[BZ_MAX_K * BZ_MAX_N];
+    __shared__ int32_t sranks[BZ_MAX_M];
     const int lane = threadIdx.x;
     const int n = args.n, k = args.k, flags = args.flags;
-    const u64 target_chunks = args.target_chunks;
     CodeResult &res = cs->res;
     if (lane == 0) {
         cs->p = P;
@@ -77,7 +106,20 @@ __global__ __launch_bounds__(64) void decompose_kernel(const uint8_t *__restrict
         cs->max_codewords = args.max_codewords;
     }
 
-    // -- load G: lanes walk 64 columns of one row, ballots transpose the bits
+    // -- G into LDS with independent loads, then one ballot per row, plane and
+    //    64 columns transposes it into per-lane bit-plane rows
+    const int nbytes = k * n;
+    if ((reinterpret_cast<uintptr_t>(G) & 15) == 0) {
+        const int n16 = nbytes / 16;
+        const uint4 *G4 = reinterpret_cast<const uint4 *>(G);
+        uint4 *gl4 = reinterpret_cast<uint4 *>(gl);
+#pragma unroll 8
+        for (int i = lane; i < n16; i += 64) gl4[i] = G4[i];
+        for (int i = n16 * 16 + lane; i < nbytes; i += 64) gl[i] = G[i];
+    } else {
+        for (int i = lane; i < nbytes; i += 64) gl[i] = G[i];
+    }
+    __syncthreads();
     u32 x[3][4];
 #pragma unroll
     for (int b = 0; b < 3; b++)
@@ -88,7 +130,7 @@ __global__ __launch_bounds__(64) void decompose_kernel(const uint8_t *__restrict
 #pragma unroll
         for (int cb = 0; cb < WF; cb += 2) {
             const int c = cb * 32 + lane;
-            const int v = (c < n) ? (int)G[(size_t)i * n + c] : 0;
+            const int v = (c < n) ? (int)gl[i * n + c] : 0;
             bad |= (v >= P);
 #pragma unroll
             for (int b = 0; b < R; b++) {
@@ -124,6 +166,8 @@ __global__ __launch_bounds__(64) void decompose_kernel(const uint8_t *__restrict
             anyu |= unused[w] != 0;
         }
         if (!anyu) break;
+        // Gauss-Jordan with the unused columns first, then the used ones, each
+        // ascending; piv_lane = pivot index of this lane's row
         int piv_lane = -1, npiv = 0, kj = 0;
         u32 pivmask[4] = {0, 0, 0, 0};
         for (int pass = 0; pass < 2 && npiv < k; pass++) {
@@ -140,7 +184,7 @@ __global__ __launch_bounds__(64) void decompose_kernel(const uint8_t *__restrict
                     const u64 cm = __ballot(cand);
                     if (cm == 0) continue;
                     const int pl = __ffsll((unsigned long long)cm) - 1;
-                    const int pv = __shfl(v, pl);
+                    const int pv = __builtin_amdgcn_readlane(v, pl);
                     const int inv = inv_mod(P, pv);
                     // normalised pivot row, wave-uniform
                     u32 pr[3][4];
@@ -148,7 +192,7 @@ __global__ __launch_bounds__(64) void decompose_kernel(const uint8_t *__restrict
                     for (int ww = 0; ww < WF; ww++) {
                         u32 raw[3] = {0, 0, 0}, sc[3] = {0, 0, 0};
 #pragma unroll
-                        for (int b = 0; b < R; b++) raw[b] = __shfl(x[b][ww], pl);
+                        for (int b = 0; b < R; b++) raw[b] = __builtin_amdgcn_readlane(x[b][ww], pl);
                         scale<P>(inv, raw, sc);
 #pragma unroll
                         for (int b = 0; b < 3; b++) pr[b][ww] = sc[b];
@@ -184,15 +228,16 @@ __global__ __launch_bounds__(64) void decompose_kernel(const uint8_t *__restrict
             break;
         }
         if (kj == 0) break;
-        // -- pack Gamma_m: row piv_lane of matrix m
+        // -- pack Gamma_m: row piv_lane of matrix m; slot 3 of each word = OR of planes
         if (lane < k) {
-            u32 *dst = rows + ((size_t)(m * BZ_MAX_K + piv_lane) * 3) * 4;
+            u32 *dst = rows + (size_t)(m * BZ_MAX_K + piv_lane) * ROW_WORDS;
+            u32 out[3][4];
+#pragma unroll
+            for (int b = 0; b < 3; b++)
+#pragma unroll
+                for (int w = 0; w < 4; w++) out[b][w] = 0;
             if (skip) {
-                u32 out[3][4];
-#pragma unroll
-                for (int b = 0; b < 3; b++)
-#pragma unroll
-                    for (int w = 0; w < 4; w++) out[b][w] = 0;
+                // the non-pivot columns, compacted in ascending order
                 int ob = 0;
 #pragma unroll
                 for (int w = 0; w < WF; w++) {
@@ -211,53 +256,74 @@ __global__ __launch_bounds__(64) void decompose_kernel(const uint8_t *__restrict
                         ob++;
                     }
                 }
-#pragma unroll
-                for (int b = 0; b < 3; b++)
-#pragma unroll
-                    for (int w = 0; w < 4; w++) dst[b * 4 + w] = out[b][w];
             } else {
 #pragma unroll
                 for (int b = 0; b < 3; b++)
 #pragma unroll
-                    for (int w = 0; w < 4; w++) dst[b * 4 + w] = (w < WF) ? x[b][w] : 0u;
+                    for (int w = 0; w < 4; w++) out[b][w] = (w < WF) ? x[b][w] : 0u;
+            }
+#pragma unroll
+            for (int w = 0; w < 4; w++) {
+                dst[w * 4 + 0] = out[0][w];
+                dst[w * 4 + 1] = out[1][w];
+                dst[w * 4 + 2] = out[2][w];
+                dst[w * 4 + 3] = out[0][w] | out[1][w] | out[2][w];
             }
         }
-        if (lane == 0) res.ranks[m] = kj;
+        if (lane == 0) sranks[m] = kj;
         m++;
 #pragma unroll
         for (int w = 0; w < 4; w++) used[w] |= pivmask[w] & unused[w];
         if (kj < k || m == BZ_MAX_M) break;
     }
-    __syncthreads();  // ranks written by lane 0 are read back below by lane 0 only
+    __syncthreads();
 
-    // -- schedule and queue state
+    // -- schedule and completion state, built in LDS and copied out with all lanes
+    __shared__ StageDesc sst[BZ_MAX_STAGES];
+    __shared__ int s_ns, s_complete;
     if (lane == 0) {
-        res.status = status;
-        res.m = m;
-        res.W = W;
-        res.term_stage = -1;
-        res.checked = 0;
-        cs->next_chunk = 0;
         int complete = 1;
-        u64 total = 0;
         int ns = 0;
         if (status == BZ_OK) {
             const bool no_term = (flags & FLAG_NO_TERM) != 0;
             if (no_term || args.U0 > 1)
-                ns = build_schedule(P, k, m, res.ranks, flags, args.max_codewords, target_chunks, cs->stages,
-                                    &complete, &total);
+                ns = build_schedule(P, k, m, sranks, flags, args.max_codewords, args.grid, W, binom, sst,
+                                    &complete, false);
         }
-        res.n_table = ns;
-        res.table_complete = complete;
-        cs->total_chunks = total;
+        s_ns = ns;
+        s_complete = complete;
     }
     __syncthreads();
-    const int ns = res.n_table;
+    const int ns = s_ns;
+    // task counts of the stages with g >= 3, one wave-parallel pass per round g
+    for (int s = 0; s < ns; s++) {
+        const StageDesc &d = sst[s];
+        if (d.g < 3 || d.j != 1) continue;
+        const u64 tasks = wave_qtable(k, d.g, d.coef_combos, d.sweep_cap, binom, nullptr);
+        const int g = d.g;
+        for (int t = s + lane; t < ns && t < s + BZ_MAX_M; t += 64) {
+            StageDesc &e = sst[t];
+            if (e.g != g) continue;
+            e.tasks = tasks;
+            e.tiles = (tasks + WAVES_PER_GROUP - 1) / WAVES_PER_GROUP;
+            e.parts = (uint32_t)(e.tiles < (u64)args.grid ? e.tiles : (u64)args.grid);
+        }
+        __syncthreads();
+    }
     for (int s = lane; s < ns; s += 64) {
+        cs->stages[s] = sst[s];
         res.stage_min[s] = (int)BIG;
         res.stage_count[s] = 0;
         cs->stage_done[s] = 0;
-        cs->U_after[s] = 0;
+    }
+    for (int j = lane; j < m; j += 64) res.ranks[j] = sranks[j];
+    if (lane == 0) {
+        res.status = status;
+        res.m = m;
+        res.W = W;
+        res.ctl = ctl_make(0, -1, args.U0);
+        res.n_table = ns;
+        res.table_complete = s_complete;
     }
 }
 
@@ -265,55 +331,28 @@ __global__ __launch_bounds__(64) void decompose_kernel(const uint8_t *__restrict
 // Enumeration
 // =====================================================================
 
-// weights of the 2 (F_3) or 6 (F_7) completions of prefix Pv by row Rl
-template <int P, int W, bool HIST>
-__device__ __forceinline__ void complete(const u32 (&Pv)[3][W], const u32 (&anyP)[W], const u32 (&Rl)[3][W],
-                                         u32 &lmin, u32 *lh, u32 woff) {
-    if constexpr (P == 3) {
-        u32 wa = 0, ws = 0;
-#pragma unroll
-        for (int w = 0; w < W; w++) {
-            wa += __builtin_popcount(f3_iso_add(Pv[0][w], Pv[1][w], Rl[0][w], Rl[1][w]));
-            ws += __builtin_popcount(f3_iso_sub(Pv[0][w], Pv[1][w], Rl[0][w], Rl[1][w]));
-        }
-        lmin = min(lmin, min(wa, ws));
-        if constexpr (HIST) {
-            atomicAdd(&lh[wa + woff], 1u);
-            atomicAdd(&lh[ws + woff], 1u);
-        }
-    } else {
-        u32 anyPR[W];
-#pragma unroll
-        for (int w = 0; w < W; w++) anyPR[w] = anyP[w] | Rl[0][w] | Rl[1][w] | Rl[2][w];
-#pragma unroll
-        for (int e = 0; e < 3; e++) {
-            u32 wa = 0, ws = 0;
-#pragma unroll
-            for (int w = 0; w < W; w++) {
-                // rotation by e: S_i = R_{i-e}  (times 2^e, Sec. 4.2)
-                const u32 s0 = Rl[(3 - e) % 3][w], s1 = Rl[(4 - e) % 3][w], s2 = Rl[(5 - e) % 3][w];
-                const u32 x0 = Pv[0][w] ^ s0, x1 = Pv[1][w] ^ s1, x2 = Pv[2][w] ^ s2;
-                ws += __builtin_popcount(x0 | x1 | x2);             // P - 2^e R
-                wa += __builtin_popcount(~(x0 & x1 & x2) & anyPR[w]);  // P + 2^e R
-            }
-            lmin = min(lmin, min(wa, ws));
-            if constexpr (HIST) {
-                atomicAdd(&lh[wa + woff], 1u);
-                atomicAdd(&lh[ws + woff], 1u);
-            }
-        }
-    }
-}
+template <int W>
+struct Row {
+    u32 p[3][W];  // planes
+    u32 any[W];   // OR of the planes
+};
 
 template <int P, int W>
-__device__ __forceinline__ void load_row(const u32 *__restrict__ rows, int j, int i, u32 (&r)[3][W]) {
-    const u32 *src = rows + ((size_t)(j * BZ_MAX_K + i) * 3) * 4;
+__device__ __forceinline__ Row<W> load_row(const u32 *__restrict__ rows, int j, int i) {
+    const uint4 *src = reinterpret_cast<const uint4 *>(rows + (size_t)(j * BZ_MAX_K + i) * ROW_WORDS);
+    Row<W> r;
 #pragma unroll
-    for (int b = 0; b < 3; b++)
-#pragma unroll
-        for (int w = 0; w < W; w++) r[b][w] = (b < ((P == 3) ? 2 : 3)) ? src[b * 4 + w] : 0u;
+    for (int w = 0; w < W; w++) {
+        const uint4 v = src[w];
+        r.p[0][w] = v.x;
+        r.p[1][w] = v.y;
+        r.p[2][w] = (P == 3) ? 0u : v.z;
+        r.any[w] = v.w;
+    }
+    return r;
 }
 
+// x = x + h * r (exact, Algorithm 3 / 4 after the scaling of Sec. 4.2)
 template <int P, int W>
 __device__ __forceinline__ void add_scaled(u32 (&x)[3][W], const u32 (&r)[3][W], int h) {
 #pragma unroll
@@ -325,193 +364,304 @@ __device__ __forceinline__ void add_scaled(u32 (&x)[3][W], const u32 (&r)[3][W],
     }
 }
 
-template <int W>
-__device__ __forceinline__ void any_planes(const u32 (&x)[3][W], u32 (&a)[W]) {
-#pragma unroll
-    for (int w = 0; w < W; w++) a[w] = x[0][w] | x[1][w] | x[2][w];
+template <int P, int W, bool HIST>
+__device__ __forceinline__ void count_hist(u32 *lh, u32 wt) {
+    if constexpr (HIST) atomicAdd(&lh[wt], 1u);
 }
 
-// the lane's combinations of one chunk; returns the number of combinations
-// the wavefront evaluated (wave-uniform)
-template <int P, int W, bool HIST>
-__device__ u64 run_chunk(const StageDesc &sd, int k, int j, const u32 *__restrict__ rows,
-                         const u64 *__restrict__ binom, u64 first, u64 last, u32 &lmin, u32 *lh, u32 woff) {
-    const int lane = __lane_id();
-    const int g = sd.g;
-    u64 cnt = 0;
-    for (u64 base = first; base < last; base += 64) {
-        const u64 item = base + (u64)lane;
-        const bool valid = item < last;
-        if (g == 1) {
-            if (valid) {
-                u32 r[3][W], a[W];
-                load_row<P, W>(rows, j, (int)item, r);
-                any_planes<W>(r, a);
-                u32 wt = 0;
+// Weights of the combinations prefix + h * row for the p-1 prefixes of one
+// lane and every multiplier h: F_3 needs v + w and v - w (Sec. 4.2); F_7 needs
+// v +- 2^e w, e = 0, 1, 2, the scaling being a rotation of the planes.
+// Isometric additions (Sec. 4.3) give the nonzero masks, popcount the weights.
+template <int P, int W, int NA, bool HIST>
+__device__ __forceinline__ void complete_all(const u32 (&Pv)[NA][3][W], const u32 (&anyP)[NA][W],
+                                             const Row<W> &R, u32 &lmin, u32 *lh, u32 woff, u32 cap) {
 #pragma unroll
-                for (int w = 0; w < W; w++) wt += __builtin_popcount(a[w]);
-                lmin = min(lmin, wt);
-                if constexpr (HIST) atomicAdd(&lh[wt + woff], 1u);
+    for (int a = 0; a < NA; a++) {
+        if constexpr (P == 3) {
+            u32 wa = 0, ws = 0;
+#pragma unroll
+            for (int w = 0; w < W; w++) {
+                wa += __builtin_popcount(f3_iso_add(Pv[a][0][w], Pv[a][1][w], R.p[0][w], R.p[1][w]));
+                ws += __builtin_popcount(f3_iso_sub(Pv[a][0][w], Pv[a][1][w], R.p[0][w], R.p[1][w]));
             }
-            cnt += (u64)__popcll(__ballot(valid));
-            continue;
-        }
-        int q;  // highest row of the lane's prefix
-        u32 Q[3][W], anyQ[W];
-        if (g == 2) {
-            q = valid ? (int)item : k;
-            if (valid) load_row<P, W>(rows, j, q, Q);
-            else {
-#pragma unroll
-                for (int b = 0; b < 3; b++)
-#pragma unroll
-                    for (int w = 0; w < W; w++) Q[b][w] = 0;
+            lmin = min(lmin, min(wa, ws));
+            if constexpr (HIST) {
+                count_hist<P, W, HIST>(lh, min(wa + woff, cap));
+                count_hist<P, W, HIST>(lh, min(ws + woff, cap));
             }
-            any_planes<W>(Q, anyQ);
-            const int qmin = uni(q);
-            for (int L = qmin + 1; L < k; L++) {
-                const bool act = valid && L > q;
-                u32 Rl[3][W];
-                load_row<P, W>(rows, j, uni(L), Rl);
-                if (act) complete<P, W, HIST>(Q, anyQ, Rl, lmin, lh, woff);
-                cnt += (u64)(P - 1) * (u64)__popcll(__ballot(act));
-            }
-            continue;
-        }
-        // g >= 3: base of g-2 rows c_1 < ... < c_{g-2} from colex rank sr,
-        // coefficients of c_2.. from the digits of ci in base p-1
-        const int t = g - 2;
-        const u32 M = sd.coef_combos;
+        } else {
+            u32 anyPR[W];
 #pragma unroll
-        for (int b = 0; b < 3; b++)
+            for (int w = 0; w < W; w++) anyPR[w] = anyP[a][w] | R.any[w];
 #pragma unroll
-            for (int w = 0; w < W; w++) Q[b][w] = 0;
-        q = k;
-        if (valid) {
-            const u64 sr = item / M;
-            u32 ci = (u32)(item - sr * M);
-            colex_unrank(sr, t, k - 3, binom, [&](int i, int c) {
-                u32 r[3][W];
-                load_row<P, W>(rows, j, c, r);
-                int coef = 1;
-                if (i > 1) {
-                    coef = (int)(ci % (u32)(P - 1)) + 1;
-                    ci /= (u32)(P - 1);
+            for (int e = 0; e < 3; e++) {
+                u32 wa = 0, ws = 0;
+#pragma unroll
+                for (int w = 0; w < W; w++) {
+                    // rotation by e: S_i = R_{i-e} (multiplication by 2^e)
+                    const u32 s0 = R.p[(3 - e) % 3][w], s1 = R.p[(4 - e) % 3][w], s2 = R.p[(5 - e) % 3][w];
+                    const u32 x0 = Pv[a][0][w] ^ s0, x1 = Pv[a][1][w] ^ s1, x2 = Pv[a][2][w] ^ s2;
+                    ws += __builtin_popcount(x0 | x1 | x2);                // prefix - 2^e row
+                    wa += __builtin_popcount(~(x0 & x1 & x2) & anyPR[w]);  // prefix + 2^e row
                 }
-                if (i == t) {
-                    q = c;
-#pragma unroll
-                    for (int w = 0; w < W; w++) {
-                        u32 src[3] = {r[0][w], r[1][w], r[2][w]}, sc[3] = {0, 0, 0};
-                        scale<P>(coef, src, sc);
-#pragma unroll
-                        for (int b = 0; b < 3; b++) Q[b][w] = sc[b];
-                    }
-                } else {
-                    add_scaled<P, W>(Q, r, coef);
-                }
-            });
-        }
-        const int qmin = uni(q);
-        for (int s = qmin + 1; s < k - 1; s++) {
-            const bool act = valid && s > q;
-            const u64 nact = (u64)__popcll(__ballot(act));
-            if (nact == 0) continue;
-            u32 Rs[3][W];
-            load_row<P, W>(rows, j, uni(s), Rs);
-            for (int a = 1; a < P; a++) {
-                u32 Pv[3][W], anyP[W];
-#pragma unroll
-                for (int b = 0; b < 3; b++)
-#pragma unroll
-                    for (int w = 0; w < W; w++) Pv[b][w] = Q[b][w];
-                add_scaled<P, W>(Pv, Rs, a);
-                any_planes<W>(Pv, anyP);
-                for (int L = s + 1; L < k; L++) {
-                    u32 Rl[3][W];
-                    load_row<P, W>(rows, j, uni(L), Rl);
-                    if (act) complete<P, W, HIST>(Pv, anyP, Rl, lmin, lh, woff);
-                    cnt += (u64)(P - 1) * nact;
+                lmin = min(lmin, min(wa, ws));
+                if constexpr (HIST) {
+                    count_hist<P, W, HIST>(lh, min(wa + woff, cap));
+                    count_hist<P, W, HIST>(lh, min(ws + woff, cap));
                 }
             }
         }
     }
+}
+
+// Prefixes Q + h * Rs for the NA coefficients h = 1..NA of row s, then every
+// last row L = s+1..k-1 for all of them; the next row is loaded while the
+// current one is combined.
+template <int P, int W, int NA, bool HIST>
+__device__ __forceinline__ void extend_and_sweep(const u32 *__restrict__ rows, int j, int s, int k,
+                                                 const u32 (&Q)[3][W], const Row<W> &Rs, u32 &lmin, u32 *lh,
+                                                 u32 woff, u32 cap) {
+    u32 Pv[NA][3][W], anyP[NA][W];
+#pragma unroll
+    for (int a = 0; a < NA; a++) {
+#pragma unroll
+        for (int b = 0; b < 3; b++)
+#pragma unroll
+            for (int w = 0; w < W; w++) Pv[a][b][w] = Q[b][w];
+        add_scaled<P, W>(Pv[a], Rs.p, a + 1);
+#pragma unroll
+        for (int w = 0; w < W; w++) anyP[a][w] = Pv[a][0][w] | Pv[a][1][w] | Pv[a][2][w];
+    }
+    const int L0 = uni(s + 1);
+    Row<W> Rc = load_row<P, W>(rows, j, L0);
+    for (int L = L0; L < k; L++) {
+        const Row<W> Rn = load_row<P, W>(rows, j, min(L + 1, k - 1));
+        complete_all<P, W, NA, HIST>(Pv, anyP, Rc, lmin, lh, woff, cap);
+        Rc = Rn;
+    }
+}
+
+// binomial C(c, i): LDS for small i, global memory otherwise
+__device__ __forceinline__ u64 binom_at(const u64 *sbin, const u64 *__restrict__ gbin, int c, int i) {
+    return (i < BIN_I) ? sbin[c * BIN_I + i] : gbin[c * 65 + i];
+}
+
+// g = 1 and g = 2: one item per lane (a row, or the lowest row of a pair).
+// Returns the number of combinations the wavefront evaluated (wave-uniform).
+template <int P, int W, bool HIST>
+__device__ u64 run_small_task(int g, int k, int j, const u32 *__restrict__ rows, u64 task, u32 &lmin, u32 *lh,
+                              u32 woff, u32 cap) {
+    const int lane = __lane_id();
+    const int nitems = (g == 1) ? k : k - 1;
+    const int item = (int)(task * 64) + lane;
+    const bool valid = item < nitems;
+    if (g == 1) {
+        if (valid) {
+            const Row<W> r = load_row<P, W>(rows, j, item);
+            u32 wt = 0;
+#pragma unroll
+            for (int w = 0; w < W; w++) wt += __builtin_popcount(r.any[w]);
+            lmin = min(lmin, wt);
+            if constexpr (HIST) count_hist<P, W, HIST>(lh, min(wt + woff, cap));
+        }
+        return (u64)__popcll(__ballot(valid));
+    }
+    // g = 2: the item is the lowest row s itself, with coefficient 1
+    u64 cnt = 0;
+    u32 Q[3][W];
+#pragma unroll
+    for (int b = 0; b < 3; b++)
+#pragma unroll
+        for (int w = 0; w < W; w++) Q[b][w] = 0;
+    const int q = valid ? item : k;
+    const int smin = uni(q);
+    for (int s = smin; s < k - 1; s++) {
+        const bool act = valid && s == q;
+        const u64 nact = (u64)__popcll(__ballot(act));
+        if (nact == 0) continue;
+        cnt += nact * (u64)((P - 1) * (k - 1 - s));
+        const Row<W> Rs = load_row<P, W>(rows, j, uni(s));
+        if (act) extend_and_sweep<P, W, 1, HIST>(rows, j, s, k, Q, Rs, lmin, lh, woff, cap);
+    }
     return cnt;
 }
 
-// stage-completion check (lane 0 of a wavefront): advance over every stage
-// whose chunks are all done, in stage order, applying L_{g,j} >= U
+// g >= 3: one task = (q, chunk of 64 bases, block of rows s); see StageDesc.
+template <int P, int W, bool HIST>
+__device__ u64 run_base_task(const StageDesc &sd, int k, int j, const u32 *__restrict__ rows, const u64 *sbin,
+                             const u64 *__restrict__ gbin, const QEntry *qtab, int nq, u64 task, u32 &lmin,
+                             u32 *lh, u32 woff, u32 cap) {
+    const int lane = __lane_id();
+    const int g = sd.g;
+    const u64 M = sd.coef_combos;
+    const int qi = uni(qtable_find(qtab, nq, task));
+    const int q = g - 3 + qi;
+    const QEntry e = qtab[qi];
+    const u64 local = uni64(task - e.first);
+    const u64 chunk = uni64(local / e.nb);
+    const int block = uni((int)(local - chunk * e.nb));
+    const int s_lo = q + 1 + block * (int)e.B;
+    const int s_hi = min(s_lo + (int)e.B, k - 1);
+    const u64 bi = chunk * 64 + (u64)lane;
+    const bool valid = bi < e.bases;
+    u32 Q[3][W];
+#pragma unroll
+    for (int b = 0; b < 3; b++)
+#pragma unroll
+        for (int w = 0; w < W; w++) Q[b][w] = 0;
+    if (valid) {
+        decode_base(P, g, q, M, bi, [&](int c, int i) { return binom_at(sbin, gbin, c, i); },
+                    [&](int row, int coef) {
+                        const Row<W> r = load_row<P, W>(rows, j, row);
+                        add_scaled<P, W>(Q, r.p, coef);
+                    });
+    }
+    const u64 nact = (u64)__popcll(__ballot(valid));
+    u64 cnt = 0;
+    for (int s = s_lo; s < s_hi; s++) {
+        // p-1 coefficients of row s, k-1-s last rows, p-1 multipliers, on nact lanes
+        cnt += nact * (u64)((P - 1) * (P - 1) * (k - 1 - s));
+        const Row<W> Rs = load_row<P, W>(rows, j, uni(s));
+        if (valid) extend_and_sweep<P, W, P - 1, HIST>(rows, j, s, k, Q, Rs, lmin, lh, woff, cap);
+    }
+    return cnt;
+}
+
+// stage-completion check (one thread): advance over every stage whose
+// workgroups are all done, in stage order, applying L_{g,j} >= U
 __device__ void run_checker(CodeState *cs) {
     const int ns = cs->res.n_table;
-    for (int guard = 0; guard <= BZ_MAX_STAGES; guard++) {
-        const int c = ld_acq(&cs->res.checked);
-        if (c >= ns) return;
-        if (ld_acq(&cs->res.term_stage) >= 0) return;
-        if (ld_acq(&cs->stage_done[c]) != cs->stages[c].n_chunks) return;
-        const int Uprev = (c == 0) ? cs->U0 : ld_acq(&cs->U_after[c - 1]);
-        const int smin = ld_acq(&cs->res.stage_min[c]);
-        const int Uc = min(Uprev, smin);
-        st_rel(&cs->U_after[c], Uc);
-        if (cs->stages[c].check && cs->stages[c].L >= Uc) {
-            int expect = -1;
-            __hip_atomic_compare_exchange_strong(&cs->res.term_stage, &expect, c, __ATOMIC_SEQ_CST,
-                                                 __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
+    for (int guard = 0; guard <= 2 * BZ_MAX_STAGES; guard++) {
+        u64 st = __hip_atomic_load(&cs->res.ctl, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        const int c = ctl_checked(st);
+        if (c >= ns || ctl_term(st) >= 0) return;
+        // every participant published its minimum before its release-increment of done
+        if (__hip_atomic_load(&cs->stage_done[c], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != cs->stages[c].parts)
             return;
-        }
-        int expect = c;
-        __hip_atomic_compare_exchange_strong(&cs->res.checked, &expect, c + 1, __ATOMIC_SEQ_CST,
-                                             __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
+        const int smin = __hip_atomic_load(&cs->res.stage_min[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int Uc = min(ctl_U(st), smin);
+        const bool stop = cs->stages[c].check && cs->stages[c].L >= Uc;
+        const u64 nw = stop ? ctl_make(c, c, Uc) : ctl_make(c + 1, -1, Uc);
+        if (__hip_atomic_compare_exchange_strong(&cs->res.ctl, &st, nw, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+                                                 __HIP_MEMORY_SCOPE_AGENT) &&
+            stop)
+            return;
     }
 }
 
 template <int P, int W, bool HIST>
 __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__restrict__ rows,
-                                                   const u64 *__restrict__ binom, u64 *__restrict__ hist) {
-    __shared__ u32 lhist[HIST ? 4 * (BZ_MAX_N + 1) : 1];
+                                                   const u64 *__restrict__ gbin, u64 *__restrict__ hist,
+                                                   int lookahead, u64 timeout_ticks) {
+    __shared__ u64 sbin[BZ_MAX_K * BIN_I];
+    __shared__ StageDesc sdesc[BZ_MAX_STAGES];
+    __shared__ QEntry qtab[BZ_MAX_K];
+    __shared__ u32 lhist[HIST ? WAVES_PER_GROUP * (BZ_MAX_N + 1) : 1];
+    __shared__ u32 red_min[WAVES_PER_GROUP];
+    __shared__ u64 red_cnt[WAVES_PER_GROUP];
+    __shared__ int s_term;
+    __shared__ int s_crit;
     const int lane = __lane_id();
     const int wid = threadIdx.x >> 6;
+    const uint32_t grid = gridDim.x, b = blockIdx.x;
     if (cs->res.status != BZ_OK) return;
     const int k = cs->k, n = cs->n;
     const int ns = cs->res.n_table;
-    const u64 total = cs->total_chunks;
+    for (int i = threadIdx.x; i < BZ_MAX_K * BIN_I; i += blockDim.x) sbin[i] = gbin[(i / BIN_I) * 65 + i % BIN_I];
+    for (int i = threadIdx.x; i < ns; i += blockDim.x) sdesc[i] = cs->stages[i];
+    __syncthreads();
     const bool skip = (cs->flags & FLAG_SKIP) != 0;
     u32 *lh = HIST ? &lhist[wid * (BZ_MAX_N + 1)] : nullptr;
-    int s = 0;
-    for (;;) {
-        u64 ch = 0;
-        if (lane == 0) ch = atomicAdd((unsigned long long *)&cs->next_chunk, 1ull);
-        ch = uni64(__shfl(ch, 0));
-        if (ch >= total) break;
-        while (s + 1 < ns && cs->stages[s + 1].chunk_begin <= ch) s++;
-        s = uni(s);
-        const int term = uni(ld_acq(&cs->res.term_stage));
-        if (term >= 0 && s > term) break;
-        const StageDesc sd = cs->stages[s];
-        const u64 first = (ch - sd.chunk_begin) * sd.items_per_chunk;
-        const u64 last = min(first + sd.items_per_chunk, sd.items);
+    const u32 cap = (u32)n;
+    for (int s = 0; s < ns; s++) {
+        const StageDesc &sd = sdesc[s];
+        if (tile_of(0, b, grid, s) >= sd.tiles) continue;  // no tile of this stage here
+        if (threadIdx.x == 0) {
+            // a large stage waits until every stage before s - lookahead is checked
+            // (small ones never wait), or the run ended
+            const long long t0 = wall_clock64();
+            int term;
+            u64 st;
+            for (;;) {
+                st = ld_relaxed(&cs->res.ctl);
+                term = ctl_term(st);
+                if (term >= 0 || sd.codewords <= SMALL_STAGE || ctl_checked(st) >= s - lookahead) break;
+                if (ld_relaxed(&cs->res.status) != BZ_OK) {
+                    term = -2;
+                    break;
+                }
+                if ((u64)(wall_clock64() - t0) > timeout_ticks) {
+                    __hip_atomic_store(&cs->res.status, (int)BZ_ERR_DEVICE, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+                    term = -2;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(8);
+            }
+            s_term = term;
+            s_crit = ctl_checked(st) >= s;  // the earliest unchecked stage: no later stage can wait on it
+        }
+        if (wid == 0 && sd.g >= 3) wave_qtable(k, sd.g, sd.coef_combos, sd.sweep_cap, gbin, qtab);
+        __syncthreads();
+        const int term = s_term;
+        const bool crit = s_crit != 0;
+        __syncthreads();  // every thread has read s_term: one decision for the whole workgroup
+        if (term == -2 || (term >= 0 && s > term)) break;
+        // work on the earliest unchecked stage runs at a higher wave priority than run-ahead work
+        if (crit) __builtin_amdgcn_s_setprio(2);
+        else __builtin_amdgcn_s_setprio(0);
+        const int nq = k - 2 - (sd.g - 3);
+        const int j = sd.j - 1;
         const u32 woff = skip ? (u32)sd.g : 0u;
-        if constexpr (HIST) {
-            for (int w = lane; w <= n; w += 64) lh[w] = 0;
-        }
         u32 lmin = BIG;
-        const u64 cnt = run_chunk<P, W, HIST>(sd, k, sd.j - 1, rows, binom, first, last, lmin, lh, woff);
-        // wave min
-        for (int off = 32; off >= 1; off >>= 1) lmin = min(lmin, (u32)__shfl_xor((int)lmin, off));
-        if (lane == 0) {
-            if (lmin != BIG) atomicMin(&cs->res.stage_min[s], (int)(lmin + woff));
-            atomicAdd((unsigned long long *)&cs->res.stage_count[s], (unsigned long long)cnt);
-        }
-        if constexpr (HIST) {
-            for (int w = lane; w <= n; w += 64) {
-                const u32 c = lh[w];
-                if (c) atomicAdd((unsigned long long *)&hist[(size_t)s * (BZ_MAX_N + 1) + w], (unsigned long long)c);
+        u64 cnt = 0;
+        for (u64 r = 0;; r++) {
+            const u64 tile = tile_of(r, b, grid, s);
+            if (tile >= sd.tiles) break;  // a missing tile only happens in the last round
+            if (r > 0) {
+                // a later stage after termination is abandoned (its results are never read)
+                const int t2 = uni(lane == 0 ? ctl_term(ld_relaxed(&cs->res.ctl)) : 0);
+                if (t2 >= 0 && s > t2) break;
+            }
+            const u64 task = tile * WAVES_PER_GROUP + (u64)wid;
+            if (task >= sd.tasks) continue;
+            if constexpr (HIST) {
+                for (int w = lane; w <= n; w += 64) lh[w] = 0;
+            }
+            if (sd.g >= 3)
+                cnt += run_base_task<P, W, HIST>(sd, k, j, rows, sbin, gbin, qtab, nq, task, lmin, lh, woff, cap);
+            else
+                cnt += run_small_task<P, W, HIST>(sd.g, k, j, rows, task, lmin, lh, woff, cap);
+            if constexpr (HIST) {
+                for (int w = lane; w <= n; w += 64) {
+                    const u32 c = lh[w];
+                    if (c) atomicAdd((unsigned long long *)&hist[(size_t)s * (BZ_MAX_N + 1) + w], (unsigned long long)c);
+                }
             }
         }
-        __threadfence();
+        // workgroup reduction, then one set of atomics per workgroup and stage
+        for (int off = 32; off >= 1; off >>= 1) lmin = min(lmin, (u32)__shfl_xor((int)lmin, off));
         if (lane == 0) {
-            __hip_atomic_fetch_add(&cs->stage_done[s], 1ull, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
-            run_checker(cs);
+            red_min[wid] = lmin;
+            red_cnt[wid] = cnt;
         }
+        if constexpr (HIST) __threadfence();
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            u32 bm = red_min[0];
+            u64 bc = red_cnt[0];
+            for (int w = 1; w < WAVES_PER_GROUP; w++) {
+                bm = min(bm, red_min[w]);
+                bc += red_cnt[w];
+            }
+            if (bm != BIG) atomicMin(&cs->res.stage_min[s], (int)(bm + woff));
+            atomicAdd((unsigned long long *)&cs->res.stage_count[s], (unsigned long long)bc);
+            const uint32_t done =
+                __hip_atomic_fetch_add(&cs->stage_done[s], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+            if (done == sd.parts) run_checker(cs);
+        }
+        __syncthreads();  // qtab and red_* are rewritten by the next stage
     }
 }
 

@@ -14,38 +14,58 @@ namespace bz {
 
 typedef uint64_t u64;
 
-// Row storage: Gamma_j row i, plane b, word w at rows[((j*BZ_MAX_K + i)*3 + b)*4 + w].
-constexpr int ROW_WORDS = 12;
+// Row storage: Gamma_j row i, word w, plane b at rows[(j*BZ_MAX_K + i)*ROW_WORDS + w*4 + b]
+// for b < 3; slot b = 3 holds the OR of the planes (the row's nonzero mask).  The
+// W words of a row are one contiguous, 16-byte aligned run that scalar loads
+// fetch in one go.
+constexpr int ROW_WORDS = 16;
 constexpr uint64_t DEFAULT_LIMIT = 1ull << 44;
 
-// One stage (g, j) of Algorithm 6, and how its work is cut into queue chunks.
-//   g = 1: an item is a row i (one combination).
-//   g = 2: an item is the lowest row s; the kernel adds every later row.
-//   g >= 3: an item is a "base" of g-2 rows (lowest coefficient 1, the others
-//           any of the (p-1)^(g-3) nonzero choices); the kernel extends it by a
-//           row s above the base with any nonzero coefficient, and then by a last
-//           row above s with every nonzero multiplier.
+// One stage (g, j) of Algorithm 6, and how its work is cut into wave tasks
+// (64 lanes each):
+//   g = 1: a task covers 64 rows i (one combination per lane).
+//   g = 2: a task covers 64 lowest rows s; each lane adds every later row.
+//   g >= 3: a combination is  base + h_s R_s + h_L R_L  with a base of g-2 rows
+//           whose top row is q (its lowest row has coefficient 1, the others any
+//           of the (p-1)^(g-3) nonzero choices), then a row s > q with every
+//           nonzero coefficient and a last row L > s with every nonzero
+//           multiplier.  Bases are grouped by q.  A task is (q, a chunk of 64
+//           bases, a block of consecutive rows s): each lane holds one base, and
+//           all lanes share q and the rows s, so the sweeps over L are
+//           wave-uniform.  Blocks are sized so that a lane's sweep is bounded
+//           (the heaviest bases, with the smallest q, are split over many tasks).
+// Tasks are dealt four at a time (one per wavefront of a workgroup), round by
+// round, to the workgroups of the grid.
+constexpr int WAVES_PER_GROUP = 4;
+
 struct StageDesc {
     int32_t g, j;
     int32_t L;          // L_{g,j}
     int32_t check;      // 1: test L >= U after this stage
-    u64 items;          // work items in the stage
-    u64 items_per_chunk;
-    u64 chunk_begin;    // first global chunk index of the stage
-    u64 n_chunks;
+    u64 tasks;          // wave tasks in the stage
+    u64 tiles;          // ceil(tasks / WAVES_PER_GROUP)
     u64 codewords;      // C(k,g) (p-1)^(g-1)
     uint32_t coef_combos;  // (p-1)^(g-3) for g >= 3, else 1
+    uint32_t parts;        // workgroups that own at least one tile: min(grid, tiles)
+    uint32_t sweep_cap;    // g >= 3: target (s, L) steps per lane and task
     uint32_t pad;
+};
+
+// Bases with top row q (g >= 3): how many, and how their rows s are blocked.
+struct QEntry {
+    u64 first;     // first task of the group
+    u64 bases;     // C(q, g-3) (p-1)^(g-3)
+    uint32_t B;    // rows s per block
+    uint32_t nb;   // blocks: ceil((k-2-q) / B)
 };
 
 // Results the host reads back (kept contiguous and first in CodeState).
 struct CodeResult {
-    int32_t status;       // BZ_OK or a negative status from the decomposition
+    int32_t status;       // BZ_OK or a negative status
     int32_t m;
     int32_t n_table;      // stages in the schedule
     int32_t table_complete;  // 1: the schedule reaches g = k, j = m; 0: cut by the work limit
-    int32_t term_stage;   // stage after which L >= U held, or -1
-    int32_t checked;      // stages checked without termination
+    u64 ctl;              // checker state, see ctl_make
     int32_t W;            // words per plane of the packed rows
     int32_t pad;
     int32_t ranks[BZ_MAX_M];
@@ -60,15 +80,30 @@ struct CodeState {
     int32_t U0;           // n - k + 1
     int32_t pad0;
     u64 max_codewords;
-    u64 total_chunks;
-    // queue and completion tracking
-    u64 next_chunk;
-    u64 stage_done[BZ_MAX_STAGES];
-    int32_t U_after[BZ_MAX_STAGES];
+    // completion tracking: workgroups done with each stage
+    uint32_t stage_done[BZ_MAX_STAGES];
     StageDesc stages[BZ_MAX_STAGES];
 };
 
 enum { FLAG_ROUND = 1, FLAG_NO_TERM = 2, FLAG_SKIP = 4, FLAG_HIST = 8 };
+
+// Checker state in one 64-bit word, so that it is read and advanced with a
+// single atomic: stages checked (bits 0-15), terminating stage + 1 (bits
+// 16-31, 0 = none), U after the checked stages (bits 32-47).
+BZ_HD u64 ctl_make(int checked, int term, int U) {
+    return (u64)(uint32_t)checked | ((u64)(uint32_t)(term + 1) << 16) | ((u64)(uint32_t)U << 32);
+}
+BZ_HD int ctl_checked(u64 c) { return (int)(c & 0xffff); }
+BZ_HD int ctl_term(u64 c) { return (int)((c >> 16) & 0xffff) - 1; }
+BZ_HD int ctl_U(u64 c) { return (int)((c >> 32) & 0xffff); }
+
+// Stages with at most this many combinations never wait for earlier stages.
+constexpr uint64_t SMALL_STAGE = 1ull << 22;
+
+// Workgroups start a stage only once every stage more than LOOKAHEAD places
+// before it has been checked (so work on stages after the terminating one is
+// bounded).
+constexpr int LOOKAHEAD = 1;
 
 BZ_HD u64 sat_mul(u64 a, u64 b) {
     if (a == 0 || b == 0) return 0;
@@ -93,52 +128,124 @@ BZ_HD int bound_c(int g, int k, int kj) {
     return v > 0 ? v : 0;
 }
 
-// Colex unranking: the t-subset c_1 < ... < c_t of {0, ..., hi} whose rank is
-// sr = sum_i C(c_i, i).  Elements come out from the largest (i = t) to the
-// smallest; visit(i, c_i) is called for each.  binom[c * 65 + i] = C(c, i).
-template <typename Visit>
-BZ_HD void colex_unrank(u64 sr, int t, int hi, const u64 *binom, Visit visit) {
+// Target (s, L) steps per lane in one task: about 3000 VALU operations, from
+// the per-step cost of the completions (F_3: two prefixes, add and subtract;
+// F_7: six prefixes, three rotations, add and subtract).
+BZ_HD uint32_t sweep_cap_for(int p, int W) {
+    const uint32_t per = (p == 3) ? 2u * (6u * (uint32_t)W + 1u) : 6u * (25u * (uint32_t)W + 3u);
+    const uint32_t cap = 3000u / per;
+    return cap < 4u ? 4u : cap;
+}
+
+// The q-group of bases with top row q (g >= 3): its number of bases and the
+// blocking of its rows s.
+BZ_HD void qgroup(int k, int g, u64 M, uint32_t cap, const u64 *binom, int q, u64 *bases, uint32_t *B,
+                  uint32_t *nb) {
+    *bases = sat_mul(binom[q * 65 + (g - 3)], M);
+    const uint32_t len = (uint32_t)(k - 2 - q);  // rows s = q+1 .. k-2; the first has len rows L
+    uint32_t b = cap / len;
+    if (b < 1) b = 1;
+    *B = b;
+    *nb = (len + b - 1) / b;
+}
+
+// Number of tasks of a stage with g >= 3 (saturating); with tab != NULL also
+// fills the q-groups (entries for q = g-3 .. k-3, index q-(g-3)).
+BZ_HD u64 fill_qtable(int k, int g, u64 M, uint32_t cap, const u64 *binom, QEntry *tab) {
+    u64 first = 0;
+    for (int q = g - 3; q <= k - 3; q++) {
+        u64 bases;
+        uint32_t B, nb;
+        qgroup(k, g, M, cap, binom, q, &bases, &B, &nb);
+        if (tab) {
+            QEntry &e = tab[q - (g - 3)];
+            e.first = first;
+            e.bases = bases;
+            e.B = B;
+            e.nb = nb;
+        }
+        first = sat_add(first, sat_mul((bases + 63) / 64, (u64)nb));
+    }
+    return first;
+}
+
+// Locate task t among the q-groups (binary search on .first): returns the
+// index of its group.
+BZ_HD int qtable_find(const QEntry *tab, int nq, u64 t) {
+    int lo = 0, hi = nq - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].first <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Decode base number bi (< bases) of the group with top row q: its lower rows
+// (the (g-3)-subset of {0..q-1} of colex rank bi / M) and the coefficients from
+// the base-(p-1) digits of bi % M.  visit(row, coef) is called for every row
+// of the base, the top row q first.  The lowest row of the base gets
+// coefficient 1.  bin(c, i) returns C(c, i).
+template <typename Bin, typename Visit>
+BZ_HD void decode_base(int p, int g, int q, u64 M, u64 bi, Bin bin, Visit visit) {
+    u64 rho = bi / M;
+    u64 ci = bi - rho * M;
+    const int t = g - 3;  // lower rows
+    int coef = 1;
+    if (t > 0) {
+        coef = (int)(ci % (u64)(p - 1)) + 1;
+        ci /= (u64)(p - 1);
+    }
+    visit(q, coef);
+    int hi = q - 1;
     for (int i = t; i >= 1; i--) {
         int lo = i - 1, h = hi;
         while (lo < h) {
             const int mid = (lo + h + 1) >> 1;
-            if (binom[mid * 65 + i] <= sr) lo = mid;
+            if (bin(mid, i) <= rho) lo = mid;
             else h = mid - 1;
         }
-        sr -= binom[lo * 65 + i];
+        rho -= bin(lo, i);
         hi = lo - 1;
-        visit(i, lo);
+        int cf = 1;
+        if (i > 1) {
+            cf = (int)(ci % (u64)(p - 1)) + 1;
+            ci /= (u64)(p - 1);
+        }
+        visit(lo, cf);
     }
 }
 
 // Build the schedule: stages (g, j) for g = 1..k, j = 1..m in order, while the
 // cumulative combination count stays within max_codewords, at most
-// BZ_MAX_STAGES stages, and every index fits the kernel (items < 2^62,
-// (p-1)^(g-3) < 2^32).  lanes_target: aim for about this many chunks per
-// large stage.  Returns the number of stages; *complete = 1 if the schedule
-// reaches (k, m).
+// BZ_MAX_STAGES stages, and every index fits the kernel ((p-1)^(g-3) < 2^32,
+// tasks < 2^62; the last condition only when count_tasks).  grid: workgroups of the enumeration launch; W: words per
+// plane of the packed rows.  Returns the number of stages; *complete = 1 if
+// the schedule reaches (k, m).  binom[c*65+i] = C(c, i) for c, i <= 64.
 BZ_HD int build_schedule(int p, int k, int m, const int32_t *ranks, int flags, u64 max_codewords,
-                         u64 target_chunks, StageDesc *st, int *complete, u64 *total_chunks) {
+                         uint32_t grid, int W, const u64 *binom, StageDesc *st, int *complete,
+                         bool count_tasks = true) {
     int ns = 0;
-    u64 cum = 0, chunk = 0;
+    u64 cum = 0;
     *complete = 1;
+    const uint32_t cap = sweep_cap_for(p, W);
     for (int g = 1; g <= k; g++) {
         u64 pw = 1;  // (p-1)^(g-1)
         for (int t = 1; t < g; t++) pw = sat_mul(pw, (u64)(p - 1));
-        u64 cw = sat_mul(binom_sat(k, g), pw);
-        u64 items;
+        const u64 cw = sat_mul(binom[k * 65 + g], pw);
+        u64 tasks;
         u64 combos = 1;
-        if (g == 1) items = (u64)k;
-        else if (g == 2) items = (u64)(k - 1);
+        if (g == 1) tasks = ((u64)k + 63) / 64;
+        else if (g == 2) tasks = ((u64)(k - 1) + 63) / 64;
         else {
             for (int t = 3; t < g; t++) combos = sat_mul(combos, (u64)(p - 1));
-            items = sat_mul(binom_sat(k - 2, g - 2), combos);
+            // without count_tasks the caller fills tasks, tiles and parts of these stages
+            tasks = (combos >= (1ull << 32)) ? ~0ull : count_tasks ? fill_qtable(k, g, combos, cap, binom, nullptr) : 0;
         }
         for (int j = 1; j <= m; j++) {
             if (ns >= BZ_MAX_STAGES || sat_add(cum, cw) > max_codewords || combos >= (1ull << 32) ||
-                items >= (1ull << 62)) {
+                tasks >= (1ull << 62)) {
                 *complete = 0;
-                *total_chunks = chunk;
                 return ns;
             }
             StageDesc &d = st[ns];
@@ -148,24 +255,34 @@ BZ_HD int build_schedule(int p, int k, int m, const int32_t *ranks, int flags, u
             for (int i = 1; i <= m; i++) L += bound_c(i <= j ? g : g - 1, k, ranks[i - 1]);
             d.L = L;
             d.check = (flags & FLAG_NO_TERM) ? 0 : ((flags & FLAG_ROUND) ? (j == m) : 1);
-            d.items = items;
-            // chunks of 64 * t items; t grows for stages with far more items than lanes
-            u64 t = items / (64ull * target_chunks);
-            if (t < 1) t = 1;
-            if (t > 64) t = 64;
-            d.items_per_chunk = 64ull * t;
-            d.n_chunks = (items + d.items_per_chunk - 1) / d.items_per_chunk;
-            d.chunk_begin = chunk;
+            d.tasks = tasks;
+            d.tiles = (tasks + WAVES_PER_GROUP - 1) / WAVES_PER_GROUP;
             d.codewords = cw;
             d.coef_combos = (uint32_t)combos;
+            d.parts = (uint32_t)(d.tiles < (u64)grid ? d.tiles : (u64)grid);
+            d.sweep_cap = cap;
             d.pad = 0;
-            chunk += d.n_chunks;
             cum = sat_add(cum, cw);
             ns++;
         }
     }
-    *total_chunks = chunk;
     return ns;
+}
+
+// Tile owned by workgroup b in round r of stage s.  Rounds alternate direction
+// so that the heavy-first order of the items spreads evenly over the
+// workgroups, and the deal starts at a different workgroup in every stage so
+// that the heaviest tiles of successive stages land on different workgroups.
+BZ_HD u64 tile_of(u64 r, uint32_t b, uint32_t grid, int s) {
+    const uint32_t bb = (uint32_t)((b + (u64)s * 97u) % grid);
+    return r * grid + ((r & 1) ? (grid - 1 - bb) : bb);
+}
+
+BZ_HD void fill_binomials(u64 *tab) {
+    for (int a = 0; a <= 64; a++)
+        for (int b = 0; b <= 64; b++) tab[a * 65 + b] = (b > a) ? 0 : (b == 0 || b == a) ? 1 : 0;
+    for (int a = 2; a <= 64; a++)
+        for (int b = 1; b < a; b++) tab[a * 65 + b] = tab[(a - 1) * 65 + b - 1] + tab[(a - 1) * 65 + b];
 }
 
 }  // namespace bz

@@ -3,12 +3,13 @@
 //   arith     exhaustive: every pair of symbols, at every bit position of a
 //             word, through the bit-sliced F_3 / F_7 functions, against
 //             plain mod-p integers
-//   schedule  stage counts, work items, chunk accounting and bounds L_{g,j}
+//   schedule  stage counts, work items, tile dealing and bounds L_{g,j}
 //   unrank    the work decomposition visits every g-row combination with the
 //             lowest coefficient 1 exactly once
 //
 // Prints "OK <check>" per passing check; exits 1 on the first failure.
 #include <cstdio>
+#include <algorithm>
 #include <cstdlib>
 #include <map>
 #include <set>
@@ -117,6 +118,7 @@ static void check_arith() {
 }
 
 static u64 C(int n, int r) { return binom_sat(n, r); }
+static u64 BINOM[65 * 65];
 
 static void check_schedule() {
     const int before = fails;
@@ -128,9 +130,9 @@ static void check_schedule() {
         for (int flags : {0, (int)FLAG_ROUND, (int)FLAG_NO_TERM}) {
             StageDesc st[BZ_MAX_STAGES];
             int complete = 0;
-            u64 total = 0;
-            int ns = build_schedule(c.p, c.k, c.m, c.ranks.data(), flags, ~0ull, 64, st, &complete, &total);
-            u64 chunk = 0, cum = 0;
+            const uint32_t grid = 1000;
+            int ns = build_schedule(c.p, c.k, c.m, c.ranks.data(), flags, ~0ull, grid, 2, BINOM, st, &complete);
+            u64 cum = 0;
             for (int s = 0; s < ns; s++) {
                 const StageDesc &d = st[s];
                 CHECK(d.g == s / c.m + 1 && d.j == s % c.m + 1);
@@ -145,9 +147,23 @@ static void check_schedule() {
                                                    (u64)(c.p - 1) * (c.p - 1) * C(c.k - 1 - q, 2)));
                     CHECK(sum == d.codewords || d.codewords == ~0ull);
                 }
-                CHECK(d.chunk_begin == chunk);
-                CHECK(d.n_chunks * d.items_per_chunk >= d.items && (d.n_chunks - 1) * d.items_per_chunk < d.items);
-                chunk += d.n_chunks;
+                CHECK(d.tiles * WAVES_PER_GROUP >= d.tasks && (d.tiles - 1) * WAVES_PER_GROUP < d.tasks);
+                CHECK(d.parts == std::min<u64>(d.tiles, grid));
+                // the rounds of tile_of() deal every tile exactly once
+                if (d.tiles <= 50000) {
+                    std::vector<int> seen(d.tiles, 0);
+                    for (uint32_t b = 0; b < grid; b++)
+                        for (u64 r = 0;; r++) {
+                            const u64 t = tile_of(r, b, grid, s);
+                            if (t >= d.tiles) break;
+                            seen[t]++;
+                        }
+                    for (u64 t = 0; t < d.tiles; t++) CHECK(seen[t] == 1);
+                    // the workgroups that own a round-0 tile are exactly d.parts many
+                    uint32_t owners = 0;
+                    for (uint32_t b = 0; b < grid; b++) owners += tile_of(0, b, grid, s) < d.tiles;
+                    CHECK(owners == d.parts);
+                }
                 cum = sat_add(cum, d.codewords);
                 // L_{g,j} at j = m is Algorithm 6's (m-1)(g+1) + max(0, g+1-k+k_m) when only
                 // the last matrix may be partial
@@ -159,14 +175,12 @@ static void check_schedule() {
                 }
                 CHECK(d.check == ((flags & FLAG_NO_TERM) ? 0 : (flags & FLAG_ROUND) ? (d.j == c.m) : 1));
             }
-            CHECK(chunk == total);
             if (complete) CHECK(ns == c.k * c.m);
         }
         // the work limit cuts the schedule before the stage that would exceed it
         StageDesc st[BZ_MAX_STAGES];
         int complete = 1;
-        u64 total = 0;
-        int ns = build_schedule(c.p, c.k, c.m, c.ranks.data(), 0, 1000, 64, st, &complete, &total);
+        int ns = build_schedule(c.p, c.k, c.m, c.ranks.data(), 0, 1000, 64, 2, BINOM, st, &complete);
         u64 cum = 0;
         for (int s = 0; s < ns; s++) cum += st[s].codewords;
         CHECK(cum <= 1000);
@@ -180,60 +194,98 @@ static void check_schedule() {
     if (fails == before) std::printf("OK schedule\n");
 }
 
+// The kernel's work decomposition, replayed on the host: every g-row
+// combination with lowest coefficient 1 is visited exactly once, and the
+// per-task counts the kernel adds up equal the combinations visited.
 static void check_unrank() {
     const int before = fails;
-    static u64 binom[65 * 65];
-    for (int a = 0; a <= 64; a++)
-        for (int b = 0; b <= 64; b++) binom[a * 65 + b] = C(a, b);
     for (int P : {3, 7}) {
-        for (int k = 3; k <= 9; k++) {
-            for (int g = 3; g <= k && g <= 6; g++) {
-                StageDesc st[BZ_MAX_STAGES];
-                int complete;
-                u64 total;
-                int32_t ranks[1] = {k};
-                int ns = build_schedule(P, k, 1, ranks, FLAG_NO_TERM, ~0ull, 64, st, &complete, &total);
-                CHECK(ns == k);
-                const StageDesc &d = st[g - 1];
-                std::map<std::vector<int>, int> seen;  // (rows..., coefs...) -> count
-                for (u64 item = 0; item < d.items; item++) {
-                    const u64 sr = item / d.coef_combos;
-                    u32 ci = (u32)(item - sr * d.coef_combos);
-                    std::vector<int> rows(g - 2), coef(g - 2);
-                    int q = -1;
-                    colex_unrank(sr, g - 2, k - 3, binom, [&](int i, int c) {
-                        rows[i - 1] = c;
-                        int h = 1;
-                        if (i > 1) {
-                            h = (int)(ci % (u32)(P - 1)) + 1;
-                            ci /= (u32)(P - 1);
+        for (int W : {1, 2, 4}) {
+            for (int k = 3; k <= 10; k++) {
+                for (int g = 1; g <= k && g <= 6; g++) {
+                    StageDesc st[BZ_MAX_STAGES];
+                    int complete;
+                    int32_t ranks[1] = {k};
+                    int ns = build_schedule(P, k, 1, ranks, FLAG_NO_TERM, ~0ull, 64, W, BINOM, st, &complete);
+                    CHECK(ns == k);
+                    const StageDesc &d = st[g - 1];
+                    std::map<std::vector<int>, int> seen;
+                    u64 counted = 0;
+                    auto add = [&](std::vector<int> rows, std::vector<int> coefs) {
+                        // canonical key: rows ascending with their coefficients
+                        std::vector<std::pair<int, int>> rc;
+                        for (size_t i = 0; i < rows.size(); i++) rc.push_back({rows[i], coefs[i]});
+                        std::sort(rc.begin(), rc.end());
+                        std::vector<int> key;
+                        for (auto &x : rc) { key.push_back(x.first); key.push_back(x.second); }
+                        seen[key]++;
+                    };
+                    if (g == 1) {
+                        for (u64 t = 0; t < d.tasks; t++)
+                            for (int l = 0; l < 64; l++) {
+                                int i = (int)(t * 64) + l;
+                                if (i < k) { add({i}, {1}); counted++; }
+                            }
+                    } else if (g == 2) {
+                        for (u64 t = 0; t < d.tasks; t++)
+                            for (int l = 0; l < 64; l++) {
+                                int s = (int)(t * 64) + l;
+                                if (s >= k - 1) continue;
+                                for (int L = s + 1; L < k; L++)
+                                    for (int h = 1; h < P; h++) { add({s, L}, {1, h}); counted++; }
+                            }
+                    } else {
+                        std::vector<QEntry> tab(BZ_MAX_K);
+                        const u64 tasks = fill_qtable(k, g, d.coef_combos, d.sweep_cap, BINOM, tab.data());
+                        CHECK(tasks == d.tasks);
+                        const int nq = k - 2 - (g - 3);
+                        for (u64 t = 0; t < d.tasks; t++) {
+                            const int qi = qtable_find(tab.data(), nq, t);
+                            const int q = g - 3 + qi;
+                            const QEntry &e = tab[qi];
+                            CHECK(e.first <= t && (qi + 1 == nq || tab[qi + 1].first > t));
+                            const u64 local = t - e.first;
+                            const u64 chunk = local / e.nb;
+                            const int block = (int)(local - chunk * e.nb);
+                            const int s_lo = q + 1 + block * (int)e.B;
+                            const int s_hi = std::min(s_lo + (int)e.B, k - 1);
+                            CHECK(s_lo < s_hi);
+                            // a lane's (s, L) steps in one task stay near the cap
+                            int steps = 0;
+                            for (int s = s_lo; s < s_hi; s++) steps += k - 1 - s;
+                            CHECK(steps <= (int)std::max<uint32_t>(d.sweep_cap, (uint32_t)(k - 2 - q)));
+                            u64 nvalid = 0;
+                            for (int l = 0; l < 64; l++) {
+                                const u64 bi = chunk * 64 + (u64)l;
+                                if (bi >= e.bases) continue;
+                                nvalid++;
+                                std::vector<int> rows, coefs;
+                                decode_base(P, g, q, d.coef_combos, bi, [&](int c, int i) { return BINOM[c * 65 + i]; },
+                                            [&](int row, int coef) { rows.push_back(row); coefs.push_back(coef); });
+                                CHECK((int)rows.size() == g - 2);
+                                CHECK(rows[0] == q);
+                                for (size_t i = 1; i < rows.size(); i++) CHECK(rows[i] < rows[i - 1]);
+                                for (int s = s_lo; s < s_hi; s++)
+                                    for (int a = 1; a < P; a++)
+                                        for (int L = s + 1; L < k; L++)
+                                            for (int h = 1; h < P; h++) {
+                                                std::vector<int> r2(rows), c2(coefs);
+                                                r2.push_back(s); c2.push_back(a);
+                                                r2.push_back(L); c2.push_back(h);
+                                                add(r2, c2);
+                                            }
+                            }
+                            for (int s = s_lo; s < s_hi; s++) counted += nvalid * (u64)((P - 1) * (P - 1) * (k - 1 - s));
                         }
-                        coef[i - 1] = h;
-                        if (i == g - 2) q = c;
-                    });
-                    for (int i = 1; i < g - 2; i++) CHECK(rows[i - 1] < rows[i]);
-                    // extensions as the kernel makes them: row s with every nonzero
-                    // coefficient, last row L with every nonzero multiplier
-                    for (int s = q + 1; s < k - 1; s++)
-                        for (int a = 1; a < P; a++)
-                            for (int L = s + 1; L < k; L++)
-                                for (int h = 1; h < P; h++) {
-                                    std::vector<int> key(rows);
-                                    key.push_back(s);
-                                    key.push_back(L);
-                                    key.insert(key.end(), coef.begin(), coef.end());
-                                    key.push_back(a);
-                                    key.push_back(h);
-                                    seen[key]++;
-                                }
-                }
-                // every g-subset, lowest coefficient 1, others nonzero: exactly once
-                u64 expect = C(k, g);
-                for (int t = 1; t < g; t++) expect *= (u64)(P - 1);
-                CHECK((u64)seen.size() == expect);
-                for (auto &kv : seen) {
-                    CHECK(kv.second == 1);
-                    CHECK(kv.first[g] == 1);  // the coefficient of the lowest row
+                    }
+                    u64 expect = C(k, g);
+                    for (int t = 1; t < g; t++) expect *= (u64)(P - 1);
+                    CHECK((u64)seen.size() == expect);
+                    CHECK(counted == expect);
+                    for (auto &kv : seen) {
+                        CHECK(kv.second == 1);
+                        CHECK(kv.first[1] == 1);  // coefficient of the lowest row
+                    }
                 }
             }
         }
@@ -242,6 +294,9 @@ static void check_unrank() {
 }
 
 int main() {
+    fill_binomials(BINOM);
+    for (int a = 0; a <= 64; a++)
+        for (int b = 0; b <= 64; b++) CHECK(binom_sat(a, b) == ~0ull || BINOM[a * 65 + b] == binom_sat(a, b));
     check_arith();
     check_schedule();
     check_unrank();
