@@ -102,6 +102,12 @@ typedef struct {
     int32_t timing;           /* 1: fill bz_result.decompose_ms / enum_ms */
     int32_t wait_timeout_s;   /* workgroups that wait for earlier stages give up (BZ_ERR_DEVICE)
                                  after this many seconds; 0 = default (120) */
+    uint64_t *trace_out;      /* NULL, or a host buffer of (BZ_MAX_STAGES + 2) x 4 uint64 that
+                                 receives a device wall-clock timeline in nanoseconds from the
+                                 start of the decomposition kernel: row 0 = decomposition
+                                 {start, rows loaded, matrices reduced, end}; row 1 =
+                                 enumeration kernel {first workgroup start, last workgroup end};
+                                 row 2+s = stage s {first start, last end, checked, workgroups} */
 } bz_options;
 
 /* Fill *o with the defaults above. */

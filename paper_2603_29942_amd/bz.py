@@ -46,7 +46,7 @@ class bz_options(ctypes.Structure):
                 ("hist_out", ctypes.POINTER(ctypes.c_uint64)), ("max_codewords", ctypes.c_uint64),
                 ("hip_stream", ctypes.c_void_p), ("device", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("wait_timeout_s", ctypes.c_int32)]
+                ("wait_timeout_s", ctypes.c_int32), ("trace_out", ctypes.POINTER(ctypes.c_uint64))]
 
 
 _lib = None
@@ -137,9 +137,14 @@ def result_dict(st, r, hist=None):
 
 
 def min_distance(p, G, *, check="stage", no_termination=False, identity_skip=True, max_codewords=0,
-                 histograms=False, blocks_per_cu=0):
-    """Convenience wrapper: same keys as the oracle's result dict."""
+                 histograms=False, blocks_per_cu=0, trace=False):
+    """Convenience wrapper: same keys as the oracle's result dict (plus
+    ``trace``, the device timeline in ns, when asked for)."""
     o = bz_default_options()
+    tr = None
+    if trace:
+        tr = np.zeros((MAX_STAGES + 2, 4), dtype=np.uint64)
+        o.trace_out = tr.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
     o.check = CHECK_ROUND if check == "round" else CHECK_STAGE
     o.no_termination = int(bool(no_termination))
     o.identity_skip = int(bool(identity_skip))
@@ -152,7 +157,10 @@ def min_distance(p, G, *, check="stage", no_termination=False, identity_skip=Tru
         o.histograms = 1
         o.hist_out = hist.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64))
     st, r = bz_min_distance_ex(p, G, o)
-    return result_dict(st, r, hist)
+    out = result_dict(st, r, hist)
+    if trace:
+        out["trace"] = tr[:2 + r.n_stages].copy()
+    return out
 
 
 # ---------------------------------------------------------------- sliced vectors

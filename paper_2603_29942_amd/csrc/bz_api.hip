@@ -31,6 +31,7 @@ struct DevCtx {
     u64 *hist = nullptr;
     CodeResult *host_res = nullptr;
     u64 *host_hist = nullptr;
+    u64 (*host_trace)[4] = nullptr;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     std::mutex mu;
 };
@@ -76,6 +77,8 @@ int init_ctx(int dev) {
     if (hipHostMalloc(&c.host_hist, sizeof(u64) * BZ_MAX_STAGES * (BZ_MAX_N + 1), hipHostMallocDefault) !=
         hipSuccess)
         return BZ_ERR_NOMEM;
+    if (hipHostMalloc(&c.host_trace, sizeof(CodeState::trace), hipHostMallocDefault) != hipSuccess)
+        return BZ_ERR_NOMEM;
     HIP_OK(hipMemcpy(c.binom, host_binom(), sizeof(u64) * 65 * 65, hipMemcpyHostToDevice));
     for (auto &e : c.ev) HIP_OK(hipEventCreate(&e));
     c.ready = true;
@@ -98,13 +101,13 @@ __global__ void zero_u64(u64 *p, size_t n) {
 
 // ---- kernel dispatch over (P, words)
 template <int P>
-hipError_t launch_decompose(int WF, const uint8_t *G, CodeState *cs, u32 *rows, const u64 *binom, RunArgs a,
+hipError_t launch_decompose(int WF, const uint8_t *G, CodeState *cs, u32 *rows, RunArgs a,
                             hipStream_t s) {
     switch (WF) {
-    case 1: decompose_kernel<P, 1><<<1, 64, 0, s>>>(G, cs, rows, binom, a); break;
-    case 2: decompose_kernel<P, 2><<<1, 64, 0, s>>>(G, cs, rows, binom, a); break;
-    case 3: decompose_kernel<P, 3><<<1, 64, 0, s>>>(G, cs, rows, binom, a); break;
-    default: decompose_kernel<P, 4><<<1, 64, 0, s>>>(G, cs, rows, binom, a); break;
+    case 1: decompose_kernel<P, 1><<<1, 64, 0, s>>>(G, cs, rows, a); break;
+    case 2: decompose_kernel<P, 2><<<1, 64, 0, s>>>(G, cs, rows, a); break;
+    case 3: decompose_kernel<P, 3><<<1, 64, 0, s>>>(G, cs, rows, a); break;
+    default: decompose_kernel<P, 4><<<1, 64, 0, s>>>(G, cs, rows, a); break;
     }
     return hipGetLastError();
 }
@@ -259,7 +262,8 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, c
     hipStream_t s = o.hip_stream ? (hipStream_t)o.hip_stream : c->stream;
 
     const int flags = (o.check == BZ_CHECK_ROUND ? FLAG_ROUND : 0) | (o.no_termination ? FLAG_NO_TERM : 0) |
-                      (o.identity_skip ? FLAG_SKIP : 0) | (o.histograms ? FLAG_HIST : 0);
+                      (o.identity_skip ? FLAG_SKIP : 0) | (o.histograms ? FLAG_HIST : 0) |
+                      (o.trace_out ? FLAG_TRACE : 0);
     const u64 max_cw = o.max_codewords ? o.max_codewords : DEFAULT_LIMIT;
     const int WF = (n + 31) / 32;
     int W = o.identity_skip ? (n - k + 31) / 32 : WF;
@@ -288,8 +292,8 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, c
     a.lookahead = LOOKAHEAD;
     a.timeout_ticks = timeout;
     if (o.timing) HIP_OK(hipEventRecord(c->ev[0], s));
-    HIP_OK(p == 3 ? launch_decompose<3>(WF, Gd, c->cs, c->rows, c->binom, a, s)
-                  : launch_decompose<7>(WF, Gd, c->cs, c->rows, c->binom, a, s));
+    HIP_OK(p == 3 ? launch_decompose<3>(WF, Gd, c->cs, c->rows, a, s)
+                  : launch_decompose<7>(WF, Gd, c->cs, c->rows, a, s));
     if (o.timing) HIP_OK(hipEventRecord(c->ev[1], s));
     HIP_OK(p == 3 ? launch_enum<3>(o.histograms != 0, W, grid, c->cs, c->rows, c->binom, c->hist, LOOKAHEAD,
                                    timeout, s)
@@ -300,11 +304,31 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, c
     if (o.histograms)
         HIP_OK(hipMemcpyAsync(c->host_hist, c->hist, sizeof(u64) * BZ_MAX_STAGES * (BZ_MAX_N + 1),
                               hipMemcpyDeviceToHost, s));
+    if (o.trace_out)
+        HIP_OK(hipMemcpyAsync(c->host_trace, c->cs->trace, sizeof(c->cs->trace), hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
     st = finish(p, n, k, flags, max_cw, *c->host_res, out);
     if (o.timing) {
         HIP_OK(hipEventElapsedTime(&out->decompose_ms, c->ev[0], c->ev[1]));
         HIP_OK(hipEventElapsedTime(&out->enum_ms, c->ev[1], c->ev[2]));
+    }
+    if (o.trace_out) {
+        // ticks -> ns from the decomposition start; keep the stage rows the run reached
+        const u64 t0 = c->host_trace[0][0];
+        auto ns = [&](u64 t) -> u64 {
+            if (t == 0 || t == ~0ull) return 0;
+            return (u64)((double)(t - t0) * 1e9 / (double)c->ticks_per_s);
+        };
+        for (int r = 0; r < BZ_MAX_STAGES + 2; r++)
+            for (int i = 0; i < 4; i++) o.trace_out[r * 4 + i] = 0;
+        for (int i = 0; i < 4; i++) o.trace_out[i] = ns(c->host_trace[0][i]);
+        o.trace_out[4] = ns(c->host_trace[1][0]);
+        o.trace_out[5] = ns(c->host_trace[1][1]);
+        const int nt = c->host_res->n_table;
+        for (int sidx = 0; sidx < nt; sidx++) {
+            for (int i = 0; i < 3; i++) o.trace_out[(2 + sidx) * 4 + i] = ns(c->host_trace[2 + sidx][i]);
+            o.trace_out[(2 + sidx) * 4 + 3] = c->host_trace[2 + sidx][3];
+        }
     }
     if (o.histograms && (st == BZ_OK || st == BZ_ERR_LIMIT)) {
         for (int sidx = 0; sidx < out->n_stages; sidx++)

@@ -46,6 +46,15 @@ __device__ __forceinline__ void st_rel(T *p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// word q of a small register array, q wave-uniform (no dynamic register indexing)
+template <int N>
+__device__ __forceinline__ u32 pick(const u32 (&a)[N], int q) {
+    u32 v = a[0];
+#pragma unroll
+    for (int i = 1; i < N; i++) v = (q == i) ? a[i] : v;
+    return v;
+}
+
 struct RunArgs {
     int32_t n, k, flags, U0;
     u64 max_codewords;
@@ -89,14 +98,16 @@ __device__ __forceinline__ u64 wave_qtable(int k, int g, u64 M, uint32_t cap, co
 // =====================================================================
 template <int P, int WF>
 __global__ __launch_bounds__(64) void decompose_kernel(const uint8_t *__restrict__ G, CodeState *cs,
-                                                       u32 *__restrict__ rows, const u64 *__restrict__ binom,
-                                                       RunArgs args) {
+                                                       u32 *__restrict__ rows, RunArgs args) {
     constexpr int R = (P == 3) ? 2 : 3;
     __shared__ __align__(16) uint8_t gl[BZ_MAX_K * BZ_MAX_N];
+    __shared__ u64 binom[(BZ_MAX_K + 1) * 65];  // C(c, i) at [c * 65 + i], rows c <= k
     __shared__ int32_t sranks[BZ_MAX_M];
     const int lane = threadIdx.x;
     const int n = args.n, k = args.k, flags = args.flags;
     CodeResult &res = cs->res;
+    const bool tracing = (flags & FLAG_TRACE) != 0;
+    const u64 t_start = tracing ? (u64)wall_clock64() : 0;
     if (lane == 0) {
         cs->p = P;
         cs->n = n;
@@ -118,6 +129,17 @@ __global__ __launch_bounds__(64) void decompose_kernel(const uint8_t *__restrict
         for (int i = n16 * 16 + lane; i < nbytes; i += 64) gl[i] = G[i];
     } else {
         for (int i = lane; i < nbytes; i += 64) gl[i] = G[i];
+    }
+    // binomials for the schedule by Pascal's rule, lane i holding C(c, i)
+    // (exact: every C(c, i) with c <= 64 fits 64 bits)
+    {
+        u64 v = (lane == 0) ? 1u : 0u;
+        for (int c = 0; c <= k; c++) {
+            binom[c * 65 + lane] = v;
+            if (lane == 0) binom[c * 65 + 64] = (c == 64) ? 1u : 0u;
+            const u64 left = __shfl_up(v, 1);
+            if (lane >= 1) v += left;
+        }
     }
     __syncthreads();
     u32 x[3][4];
@@ -148,6 +170,7 @@ __global__ __launch_bounds__(64) void decompose_kernel(const uint8_t *__restrict
         const int lo = w * 32;
         colmask[w] = (n >= lo + 32) ? 0xffffffffu : (n > lo ? ((1u << (n - lo)) - 1u) : 0u);
     }
+    const u64 t_loaded = tracing ? (u64)wall_clock64() : 0;
 
     int status = BZ_OK;
     if (__any(bad)) status = BZ_ERR_VALUE;
@@ -197,26 +220,29 @@ __global__ __launch_bounds__(64) void decompose_kernel(const uint8_t *__restrict
 #pragma unroll
                         for (int b = 0; b < 3; b++) pr[b][ww] = sc[b];
                     }
-                    if (lane == pl) {
+                    // every row: row -= v * pivot (row + (p - v) * pivot, nothing when v = 0);
+                    // the pivot's own row becomes the normalised pivot row.  Branch-free: the
+                    // multiple is picked per lane from the p - 1 scaled copies of the pivot row.
+                    const bool me = lane == pl;
 #pragma unroll
-                        for (int ww = 0; ww < WF; ww++)
+                    for (int ww = 0; ww < WF; ww++) {
+                        u32 sc[3] = {0, 0, 0};
 #pragma unroll
-                            for (int b = 0; b < R; b++) x[b][ww] = pr[b][ww];
-                        piv_lane = npiv;
-                    } else if (v != 0) {
-                        // row -= v * pivot  ==  row + (p - v) * pivot
+                        for (int h = 1; h < P; h++) {
+                            u32 src[3] = {pr[0][ww], pr[1][ww], pr[2][ww]}, t[3] = {0, 0, 0};
+                            scale<P>(h, src, t);
+                            const bool pick = (v != 0) && (P - v == h);
 #pragma unroll
-                        for (int ww = 0; ww < WF; ww++) {
-                            u32 src[3] = {pr[0][ww], pr[1][ww], pr[2][ww]}, sc[3] = {0, 0, 0};
-                            scale<P>(P - v, src, sc);
-                            if (P == 3) {
-                                f3_add(x[0][ww], x[1][ww], sc[0], sc[1], x[0][ww], x[1][ww]);
-                            } else {
-                                f7_add(x[0][ww], x[1][ww], x[2][ww], sc[0], sc[1], sc[2], x[0][ww],
-                                       x[1][ww], x[2][ww]);
-                            }
+                            for (int b = 0; b < 3; b++) sc[b] = pick ? t[b] : sc[b];
                         }
+                        u32 y0, y1, y2 = 0;
+                        if constexpr (P == 3) f3_add(x[0][ww], x[1][ww], sc[0], sc[1], y0, y1);
+                        else f7_add(x[0][ww], x[1][ww], x[2][ww], sc[0], sc[1], sc[2], y0, y1, y2);
+                        x[0][ww] = me ? pr[0][ww] : y0;
+                        x[1][ww] = me ? pr[1][ww] : y1;
+                        if constexpr (P == 7) x[2][ww] = me ? pr[2][ww] : y2;
                     }
+                    if (me) piv_lane = npiv;
                     npiv++;
                     if (pass == 0) kj++;
                     pivmask[w] |= 1u << t;
@@ -237,24 +263,62 @@ __global__ __launch_bounds__(64) void decompose_kernel(const uint8_t *__restrict
 #pragma unroll
                 for (int w = 0; w < 4; w++) out[b][w] = 0;
             if (skip) {
-                // the non-pivot columns, compacted in ascending order
-                int ob = 0;
+                // the n-k non-pivot columns moved into columns 0 .. n-k-1: every
+                // non-pivot column at or beyond n-k takes the place of a pivot column
+                // below n-k (pairs taken in ascending order); the columns of a row
+                // can be permuted freely since only weights are used
 #pragma unroll
-                for (int w = 0; w < WF; w++) {
-                    u32 bits = colmask[w] & ~pivmask[w];
-                    while (bits) {
-                        const int t = __builtin_ctz(bits);
-                        bits &= bits - 1;
-                        const int q = ob >> 5, sh = ob & 31;
+                for (int b = 0; b < 3; b++)
 #pragma unroll
-                        for (int b = 0; b < R; b++) {
-                            const u32 bit = ((x[b][w] >> t) & 1u) << sh;
+                    for (int w = 0; w < 4; w++) out[b][w] = (w < WF) ? x[b][w] : 0u;
+                const int nk = n - k;
+                // 128-bit column sets as two 64-bit halves (wave-uniform)
+                u64 lp[2] = {0, 0}, hn[2] = {0, 0};
 #pragma unroll
-                            for (int qq = 0; qq < 4; qq++)
-                                if (qq == q) out[b][qq] |= bit;
-                        }
-                        ob++;
+                for (int w = 0; w < 4; w++) {
+                    const int lo = w * 32;
+                    const u32 below = (nk >= lo + 32) ? 0xffffffffu : (nk > lo ? ((1u << (nk - lo)) - 1u) : 0u);
+                    lp[w >> 1] |= (u64)(pivmask[w] & below) << (32 * (w & 1));
+                    hn[w >> 1] |= (u64)(colmask[w] & ~pivmask[w] & ~below) << (32 * (w & 1));
+                }
+                // each plane as two 64-bit halves held in scalars (no indexed arrays)
+                u64 h0l = (u64)out[0][0] | ((u64)out[0][1] << 32), h0h = (u64)out[0][2] | ((u64)out[0][3] << 32);
+                u64 h1l = (u64)out[1][0] | ((u64)out[1][1] << 32), h1h = (u64)out[1][2] | ((u64)out[1][3] << 32);
+                u64 h2l = (u64)out[2][0] | ((u64)out[2][1] << 32), h2h = (u64)out[2][2] | ((u64)out[2][3] << 32);
+                for (;;) {
+                    if ((lp[0] | lp[1]) == 0 || (hn[0] | hn[1]) == 0) break;
+                    const int pa = lp[0] ? __builtin_ctzll(lp[0]) : 64 + __builtin_ctzll(lp[1]);
+                    const int pb = hn[0] ? __builtin_ctzll(hn[0]) : 64 + __builtin_ctzll(hn[1]);
+                    if (lp[0]) lp[0] &= lp[0] - 1;
+                    else lp[1] &= lp[1] - 1;
+                    if (hn[0]) hn[0] &= hn[0] - 1;
+                    else hn[1] &= hn[1] - 1;
+                    // pb >= n-k > pa: move bit pb to bit pa in every plane
+                    const u64 ma = 1ull << (pa & 63);
+                    const int sb = pb & 63;
+                    const bool la = pa < 64, lb = pb < 64;
+                    u64 b0 = ((lb ? h0l : h0h) >> sb) & 1ull, b1 = ((lb ? h1l : h1h) >> sb) & 1ull,
+                        b2 = ((lb ? h2l : h2h) >> sb) & 1ull;
+                    if (la) {
+                        h0l = (h0l & ~ma) | (b0 << (pa & 63));
+                        h1l = (h1l & ~ma) | (b1 << (pa & 63));
+                        h2l = (h2l & ~ma) | (b2 << (pa & 63));
+                    } else {
+                        h0h = (h0h & ~ma) | (b0 << (pa & 63));
+                        h1h = (h1h & ~ma) | (b1 << (pa & 63));
+                        h2h = (h2h & ~ma) | (b2 << (pa & 63));
                     }
+                }
+                out[0][0] = (u32)h0l; out[0][1] = (u32)(h0l >> 32); out[0][2] = (u32)h0h; out[0][3] = (u32)(h0h >> 32);
+                out[1][0] = (u32)h1l; out[1][1] = (u32)(h1l >> 32); out[1][2] = (u32)h1h; out[1][3] = (u32)(h1h >> 32);
+                out[2][0] = (u32)h2l; out[2][1] = (u32)(h2l >> 32); out[2][2] = (u32)h2h; out[2][3] = (u32)(h2h >> 32);
+                // clear everything from column n-k on
+#pragma unroll
+                for (int w = 0; w < 4; w++) {
+                    const int lo = w * 32;
+                    const u32 below = (nk >= lo + 32) ? 0xffffffffu : (nk > lo ? ((1u << (nk - lo)) - 1u) : 0u);
+#pragma unroll
+                    for (int b = 0; b < 3; b++) out[b][w] &= below;
                 }
             } else {
 #pragma unroll
@@ -278,6 +342,7 @@ __global__ __launch_bounds__(64) void decompose_kernel(const uint8_t *__restrict
     }
     __syncthreads();
 
+    const u64 t_reduced = tracing ? (u64)wall_clock64() : 0;
     // -- schedule and completion state, built in LDS and copied out with all lanes
     __shared__ StageDesc sst[BZ_MAX_STAGES];
     __shared__ int s_ns, s_complete;
@@ -315,6 +380,20 @@ __global__ __launch_bounds__(64) void decompose_kernel(const uint8_t *__restrict
         res.stage_min[s] = (int)BIG;
         res.stage_count[s] = 0;
         cs->stage_done[s] = 0;
+        if (tracing) {
+            cs->trace[2 + s][0] = ~0ull;
+            cs->trace[2 + s][1] = 0;
+            cs->trace[2 + s][2] = 0;
+            cs->trace[2 + s][3] = 0;
+        }
+    }
+    if (tracing && lane == 0) {
+        cs->trace[0][0] = t_start;
+        cs->trace[0][1] = t_loaded;
+        cs->trace[0][2] = t_reduced;
+        cs->trace[0][3] = (u64)wall_clock64();
+        cs->trace[1][0] = ~0ull;
+        cs->trace[1][1] = 0;
     }
     for (int j = lane; j < m; j += 64) res.ranks[j] = sranks[j];
     if (lane == 0) {
@@ -447,15 +526,14 @@ __device__ __forceinline__ u64 binom_at(const u64 *sbin, const u64 *__restrict__
     return (i < BIN_I) ? sbin[c * BIN_I + i] : gbin[c * 65 + i];
 }
 
-// g = 1 and g = 2: one item per lane (a row, or the lowest row of a pair).
+// g = 1 and g = 2: one item per lane (a row, or a pair of rows).
 // Returns the number of combinations the wavefront evaluated (wave-uniform).
 template <int P, int W, bool HIST>
 __device__ u64 run_small_task(int g, int k, int j, const u32 *__restrict__ rows, u64 task, u32 &lmin, u32 *lh,
                               u32 woff, u32 cap) {
     const int lane = __lane_id();
-    const int nitems = (g == 1) ? k : k - 1;
     const int item = (int)(task * 64) + lane;
-    const bool valid = item < nitems;
+    const bool valid = item < k;
     if (g == 1) {
         if (valid) {
             const Row<W> r = load_row<P, W>(rows, j, item);
@@ -467,24 +545,24 @@ __device__ u64 run_small_task(int g, int k, int j, const u32 *__restrict__ rows,
         }
         return (u64)__popcll(__ballot(valid));
     }
-    // g = 2: the item is the lowest row s itself, with coefficient 1
-    u64 cnt = 0;
-    u32 Q[3][W];
+    // g = 2: the item is a pair s < L; row s has coefficient 1, row L every multiplier
+    const int npairs = k * (k - 1) / 2;
+    const bool pv = (int)(task * 64) + lane < npairs;
+    if (pv) {
+        int s, L;
+        pair_of((int)(task * 64) + lane, k, &s, &L);
+        const Row<W> Rs = load_row<P, W>(rows, j, s);
+        const Row<W> RL = load_row<P, W>(rows, j, L);
+        u32 Pv[1][3][W], A1[1][W];
 #pragma unroll
-    for (int b = 0; b < 3; b++)
+        for (int b = 0; b < 3; b++)
 #pragma unroll
-        for (int w = 0; w < W; w++) Q[b][w] = 0;
-    const int q = valid ? item : k;
-    const int smin = uni(q);
-    for (int s = smin; s < k - 1; s++) {
-        const bool act = valid && s == q;
-        const u64 nact = (u64)__popcll(__ballot(act));
-        if (nact == 0) continue;
-        cnt += nact * (u64)((P - 1) * (k - 1 - s));
-        const Row<W> Rs = load_row<P, W>(rows, j, uni(s));
-        if (act) extend_and_sweep<P, W, 1, HIST>(rows, j, s, k, Q, Rs, lmin, lh, woff, cap);
+            for (int w = 0; w < W; w++) Pv[0][b][w] = Rs.p[b][w];
+#pragma unroll
+        for (int w = 0; w < W; w++) A1[0][w] = Rs.any[w];
+        complete_all<P, W, 1, HIST>(Pv, A1, RL, lmin, lh, woff, cap);
     }
-    return cnt;
+    return (u64)(P - 1) * (u64)__popcll(__ballot(pv));
 }
 
 // g >= 3: one task = (q, chunk of 64 bases, block of rows s); see StageDesc.
@@ -568,6 +646,8 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
     if (cs->res.status != BZ_OK) return;
     const int k = cs->k, n = cs->n;
     const int ns = cs->res.n_table;
+    const bool tracing = (cs->flags & FLAG_TRACE) != 0;
+    if (tracing && threadIdx.x == 0) atomicMin((unsigned long long *)&cs->trace[1][0], (unsigned long long)wall_clock64());
     for (int i = threadIdx.x; i < BZ_MAX_K * BIN_I; i += blockDim.x) sbin[i] = gbin[(i / BIN_I) * 65 + i % BIN_I];
     for (int i = threadIdx.x; i < ns; i += blockDim.x) sdesc[i] = cs->stages[i];
     __syncthreads();
@@ -600,6 +680,10 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
                 __builtin_amdgcn_s_sleep(8);
             }
             s_term = term;
+            if (tracing) {
+                atomicMin((unsigned long long *)&cs->trace[2 + s][0], (unsigned long long)wall_clock64());
+                atomicAdd((unsigned long long *)&cs->trace[2 + s][3], 1ull);
+            }
             s_crit = ctl_checked(st) >= s;  // the earliest unchecked stage: no later stage can wait on it
         }
         if (wid == 0 && sd.g >= 3) wave_qtable(k, sd.g, sd.coef_combos, sd.sweep_cap, gbin, qtab);
@@ -659,10 +743,15 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
             atomicAdd((unsigned long long *)&cs->res.stage_count[s], (unsigned long long)bc);
             const uint32_t done =
                 __hip_atomic_fetch_add(&cs->stage_done[s], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-            if (done == sd.parts) run_checker(cs);
+            if (tracing) atomicMax((unsigned long long *)&cs->trace[2 + s][1], (unsigned long long)wall_clock64());
+            if (done == sd.parts) {
+                run_checker(cs);
+                if (tracing) atomicMax((unsigned long long *)&cs->trace[2 + s][2], (unsigned long long)wall_clock64());
+            }
         }
         __syncthreads();  // qtab and red_* are rewritten by the next stage
     }
+    if (tracing && threadIdx.x == 0) atomicMax((unsigned long long *)&cs->trace[1][1], (unsigned long long)wall_clock64());
 }
 
 // =====================================================================

@@ -24,7 +24,8 @@ constexpr uint64_t DEFAULT_LIMIT = 1ull << 44;
 // One stage (g, j) of Algorithm 6, and how its work is cut into wave tasks
 // (64 lanes each):
 //   g = 1: a task covers 64 rows i (one combination per lane).
-//   g = 2: a task covers 64 lowest rows s; each lane adds every later row.
+//   g = 2: a task covers 64 pairs of rows s < L (colex rank L(L-1)/2 + s), one
+//           pair per lane, with every nonzero multiplier of L.
 //   g >= 3: a combination is  base + h_s R_s + h_L R_L  with a base of g-2 rows
 //           whose top row is q (its lowest row has coefficient 1, the others any
 //           of the (p-1)^(g-3) nonzero choices), then a row s > q with every
@@ -82,10 +83,15 @@ struct CodeState {
     u64 max_codewords;
     // completion tracking: workgroups done with each stage
     uint32_t stage_done[BZ_MAX_STAGES];
+    // wall-clock trace (FLAG_TRACE): row 0 = decomposition start, its phases
+    // (rows loaded, matrices reduced, schedule built); row 1 = enumeration kernel
+    // first start / last end; row 2+s = stage s: first start, last end, checked,
+    // workgroups that took part
+    u64 trace[BZ_MAX_STAGES + 2][4];
     StageDesc stages[BZ_MAX_STAGES];
 };
 
-enum { FLAG_ROUND = 1, FLAG_NO_TERM = 2, FLAG_SKIP = 4, FLAG_HIST = 8 };
+enum { FLAG_ROUND = 1, FLAG_NO_TERM = 2, FLAG_SKIP = 4, FLAG_HIST = 8, FLAG_TRACE = 16 };
 
 // Checker state in one 64-bit word, so that it is read and advanced with a
 // single atomic: stages checked (bits 0-15), terminating stage + 1 (bits
@@ -106,9 +112,8 @@ constexpr uint64_t SMALL_STAGE = 1ull << 22;
 constexpr int LOOKAHEAD = 1;
 
 BZ_HD u64 sat_mul(u64 a, u64 b) {
-    if (a == 0 || b == 0) return 0;
-    if (a > ~0ull / b) return ~0ull;
-    return a * b;
+    u64 r;
+    return __builtin_mul_overflow(a, b, &r) ? ~0ull : r;
 }
 BZ_HD u64 sat_add(u64 a, u64 b) { return a > ~0ull - b ? ~0ull : a + b; }
 
@@ -167,6 +172,18 @@ BZ_HD u64 fill_qtable(int k, int g, u64 M, uint32_t cap, const u64 *binom, QEntr
         first = sat_add(first, sat_mul((bases + 63) / 64, (u64)nb));
     }
     return first;
+}
+
+// The pair s < L of colex rank r (r = L(L-1)/2 + s), r < k(k-1)/2.
+BZ_HD void pair_of(int r, int k, int *s, int *L) {
+    int lo = 1, hi = k - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (mid * (mid - 1) / 2 <= r) lo = mid;
+        else hi = mid - 1;
+    }
+    *L = lo;
+    *s = r - lo * (lo - 1) / 2;
 }
 
 // Locate task t among the q-groups (binary search on .first): returns the
@@ -236,7 +253,7 @@ BZ_HD int build_schedule(int p, int k, int m, const int32_t *ranks, int flags, u
         u64 tasks;
         u64 combos = 1;
         if (g == 1) tasks = ((u64)k + 63) / 64;
-        else if (g == 2) tasks = ((u64)(k - 1) + 63) / 64;
+        else if (g == 2) tasks = ((u64)(k * (k - 1) / 2) + 63) / 64;
         else {
             for (int t = 3; t < g; t++) combos = sat_mul(combos, (u64)(p - 1));
             // without count_tasks the caller fills tasks, tiles and parts of these stages

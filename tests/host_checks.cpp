@@ -229,10 +229,12 @@ static void check_unrank() {
                     } else if (g == 2) {
                         for (u64 t = 0; t < d.tasks; t++)
                             for (int l = 0; l < 64; l++) {
-                                int s = (int)(t * 64) + l;
-                                if (s >= k - 1) continue;
-                                for (int L = s + 1; L < k; L++)
-                                    for (int h = 1; h < P; h++) { add({s, L}, {1, h}); counted++; }
+                                const int r = (int)(t * 64) + l;
+                                if (r >= k * (k - 1) / 2) continue;
+                                int s, L;
+                                pair_of(r, k, &s, &L);
+                                CHECK(0 <= s && s < L && L < k);
+                                for (int h = 1; h < P; h++) { add({s, L}, {1, h}); counted++; }
                             }
                     } else {
                         std::vector<QEntry> tab(BZ_MAX_K);

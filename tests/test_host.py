@@ -59,13 +59,13 @@ def test_struct_layout(bzlib, tmp_path):
         f.write('#include <stdio.h>\n#include <stddef.h>\n#include "bz.h"\n'
                 'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(bz_stage), sizeof(bz_result),'
                 ' offsetof(bz_result, stages), offsetof(bz_result, codewords_total), sizeof(bz_options),'
-                ' offsetof(bz_options, max_codewords), offsetof(bz_options, wait_timeout_s)); return 0;}\n')
+                ' offsetof(bz_options, max_codewords), offsetof(bz_options, trace_out)); return 0;}\n')
     exe = os.path.join(str(tmp_path), "layout")
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
     c_vals = [int(x) for x in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
     py_vals = [ctypes.sizeof(bzlib.bz_stage), ctypes.sizeof(bzlib.bz_result), bzlib.bz_result.stages.offset,
                bzlib.bz_result.codewords_total.offset, ctypes.sizeof(bzlib.bz_options),
-               bzlib.bz_options.max_codewords.offset, bzlib.bz_options.wait_timeout_s.offset]
+               bzlib.bz_options.max_codewords.offset, bzlib.bz_options.trace_out.offset]
     assert c_vals == py_vals
 
 
