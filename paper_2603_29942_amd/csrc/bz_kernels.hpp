@@ -343,48 +343,85 @@ __global__ __launch_bounds__(64) void decompose_kernel(const uint8_t *__restrict
     __syncthreads();
 
     const u64 t_reduced = tracing ? (u64)wall_clock64() : 0;
-    // -- schedule and completion state, built in LDS and copied out with all lanes
-    __shared__ StageDesc sst[BZ_MAX_STAGES];
-    __shared__ int s_ns, s_complete;
-    if (lane == 0) {
-        int complete = 1;
-        int ns = 0;
-        if (status == BZ_OK) {
-            const bool no_term = (flags & FLAG_NO_TERM) != 0;
-            if (no_term || args.U0 > 1)
-                ns = build_schedule(P, k, m, sranks, flags, args.max_codewords, args.grid, W, binom, sst,
-                                    &complete, false);
+    // -- schedule (the stage order of Alg. 6): one round g per lane, a
+    //    saturating scan for the codewords before each round, then one stage per
+    //    lane; the same table as build_schedule
+    __shared__ u64 s_cw[BZ_MAX_K], s_tasks[BZ_MAX_K];
+    __shared__ uint32_t s_combos[BZ_MAX_K];
+    int ns = 0, complete = 1;
+    if (status == BZ_OK && ((flags & FLAG_NO_TERM) != 0 || args.U0 > 1)) {
+        const int g = lane + 1;
+        const bool in = g <= k;
+        const u64 cw = in ? round_codewords(P, k, g, binom) : 0;
+        const u64 combos = round_combos(P, g);
+        const u64 mine = sat_mul(cw, (u64)m);
+        u64 inc = mine;
+        for (int off = 1; off < 64; off <<= 1) {
+            const u64 o = __shfl_up(inc, off);
+            if (lane >= off) inc = sat_add(inc, o);
         }
-        s_ns = ns;
-        s_complete = complete;
-    }
-    __syncthreads();
-    const int ns = s_ns;
-    // task counts of the stages with g >= 3, one wave-parallel pass per round g
-    for (int s = 0; s < ns; s++) {
-        const StageDesc &d = sst[s];
-        if (d.g < 3 || d.j != 1) continue;
-        const u64 tasks = wave_qtable(k, d.g, d.coef_combos, d.sweep_cap, binom, nullptr);
-        const int g = d.g;
-        for (int t = s + lane; t < ns && t < s + BZ_MAX_M; t += 64) {
-            StageDesc &e = sst[t];
-            if (e.g != g) continue;
-            e.tasks = tasks;
-            e.tiles = (tasks + WAVES_PER_GROUP - 1) / WAVES_PER_GROUP;
-            e.parts = (uint32_t)(e.tiles < (u64)args.grid ? e.tiles : (u64)args.grid);
+        u64 before = __shfl_up(inc, 1);  // codewords of the rounds before g
+        if (lane == 0) before = 0;
+        const int js = in ? round_stages(m, before, cw, combos, args.max_codewords) : m;
+        const u64 short_rounds = __ballot(in && js < m);
+        if (short_rounds) {
+            const int g0 = __builtin_ctzll(short_rounds);
+            ns = g0 * m + __shfl(js, g0);
+            complete = 0;
+        } else {
+            ns = k * m;
+        }
+        if (in) {
+            s_cw[lane] = cw;
+            s_combos[lane] = (uint32_t)combos;
+            s_tasks[lane] = (g <= 2) ? small_stage_tasks(k, g) : 0;
+        }
+        __syncthreads();
+        // task counts of the rounds g >= 3 that the table reaches, one wave-parallel pass each
+        const int last_g = (ns + m - 1) / m;
+        for (int gg = 3; gg <= last_g; gg++) {
+            const u64 t = wave_qtable(k, gg, s_combos[gg - 1], sweep_cap_for(P, W), binom, nullptr);
+            if (t >= (1ull << 62)) {
+                ns = min(ns, (gg - 1) * m);
+                complete = 0;
+                break;
+            }
+            if (lane == 0) s_tasks[gg - 1] = t;
+        }
+        if (ns > BZ_MAX_STAGES) {
+            ns = BZ_MAX_STAGES;
+            complete = 0;
         }
         __syncthreads();
     }
-    for (int s = lane; s < ns; s += 64) {
-        cs->stages[s] = sst[s];
-        res.stage_min[s] = (int)BIG;
-        res.stage_count[s] = 0;
-        cs->stage_done[s] = 0;
-        if (tracing) {
-            cs->trace[2 + s][0] = ~0ull;
-            cs->trace[2 + s][1] = 0;
-            cs->trace[2 + s][2] = 0;
-            cs->trace[2 + s][3] = 0;
+    {
+        const uint32_t cap = sweep_cap_for(P, W);
+        for (int s = lane; s < ns; s += 64) {
+            const int g = s / m + 1, j = s % m + 1;
+            int L = 0;
+            for (int i = 1; i <= m; i++) L += bound_c(i <= j ? g : g - 1, k, sranks[i - 1]);
+            StageDesc d;
+            d.g = g;
+            d.j = j;
+            d.L = L;
+            d.check = (flags & FLAG_NO_TERM) ? 0 : ((flags & FLAG_ROUND) ? (j == m) : 1);
+            d.tasks = s_tasks[g - 1];
+            d.tiles = (d.tasks + WAVES_PER_GROUP - 1) / WAVES_PER_GROUP;
+            d.codewords = s_cw[g - 1];
+            d.coef_combos = s_combos[g - 1];
+            d.parts = (uint32_t)(d.tiles < (u64)args.grid ? d.tiles : (u64)args.grid);
+            d.sweep_cap = cap;
+            d.pad = 0;
+            cs->stages[s] = d;
+            res.stage_min[s] = (int)BIG;
+            res.stage_count[s] = 0;
+            cs->stage_done[s] = 0;
+            if (tracing) {
+                cs->trace[2 + s][0] = ~0ull;
+                cs->trace[2 + s][1] = 0;
+                cs->trace[2 + s][2] = 0;
+                cs->trace[2 + s][3] = 0;
+            }
         }
     }
     if (tracing && lane == 0) {
@@ -402,7 +439,7 @@ __global__ __launch_bounds__(64) void decompose_kernel(const uint8_t *__restrict
         res.W = W;
         res.ctl = ctl_make(0, -1, args.U0);
         res.n_table = ns;
-        res.table_complete = s_complete;
+        res.table_complete = complete;
     }
 }
 
@@ -606,25 +643,42 @@ __device__ u64 run_base_task(const StageDesc &sd, int k, int j, const u32 *__res
     return cnt;
 }
 
-// stage-completion check (one thread): advance over every stage whose
-// workgroups are all done, in stage order, applying L_{g,j} >= U
-__device__ void run_checker(CodeState *cs) {
-    const int ns = cs->res.n_table;
+// Stage-completion check, run by one whole wavefront: lane i looks at stage
+// c + i, c being the first unchecked stage.  The stages c, c+1, ... whose
+// workgroups are all done are checked in order (U takes their minima, a
+// prefix minimum over the lanes) and the first with L_{g,j} >= U ends the
+// run; one compare-and-swap publishes the new state.
+__device__ void run_checker(CodeState *cs, const StageDesc *sdesc, int ns) {
+    const int lane = __lane_id();
     for (int guard = 0; guard <= 2 * BZ_MAX_STAGES; guard++) {
-        u64 st = __hip_atomic_load(&cs->res.ctl, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        u64 st = uni64(__hip_atomic_load(&cs->res.ctl, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
         const int c = ctl_checked(st);
         if (c >= ns || ctl_term(st) >= 0) return;
+        const int s = c + lane;
         // every participant published its minimum before its release-increment of done
-        if (__hip_atomic_load(&cs->stage_done[c], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != cs->stages[c].parts)
-            return;
-        const int smin = __hip_atomic_load(&cs->res.stage_min[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const int Uc = min(ctl_U(st), smin);
-        const bool stop = cs->stages[c].check && cs->stages[c].L >= Uc;
-        const u64 nw = stop ? ctl_make(c, c, Uc) : ctl_make(c + 1, -1, Uc);
-        if (__hip_atomic_compare_exchange_strong(&cs->res.ctl, &st, nw, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
-                                                 __HIP_MEMORY_SCOPE_AGENT) &&
-            stop)
-            return;
+        const bool done = s < ns && __hip_atomic_load(&cs->stage_done[s], __ATOMIC_ACQUIRE,
+                                                      __HIP_MEMORY_SCOPE_AGENT) == sdesc[s].parts;
+        const u64 notdone = __ballot(!done);
+        const int nd = notdone ? __builtin_ctzll(notdone) : 64;  // stages c .. c+nd-1 are done
+        if (nd == 0) return;
+        int u = (int)ctl_U(st);
+        if (lane < nd) u = min(u, __hip_atomic_load(&cs->res.stage_min[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        for (int off = 1; off < 64; off <<= 1) {
+            const int o = __shfl_up(u, off);
+            if (lane >= off) u = min(u, o);
+        }
+        const u64 stops = __ballot(lane < nd && sdesc[s].check && sdesc[s].L >= u);
+        const int i = stops ? __builtin_ctzll(stops) : nd - 1;
+        const int ui = __shfl(u, i);
+        const u64 nw = stops ? ctl_make(c + i, c + i, ui) : ctl_make(c + nd, -1, ui);
+        int ok = 0;
+        if (lane == 0)
+            ok = __hip_atomic_compare_exchange_strong(&cs->res.ctl, &st, nw, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+        ok = __shfl(ok, 0);
+        // done: the run ended, or every done stage is checked; another checker
+        // moved the state first: look again
+        if (ok && (stops || nd < 64)) return;
     }
 }
 
@@ -732,21 +786,25 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
         }
         if constexpr (HIST) __threadfence();
         __syncthreads();
-        if (threadIdx.x == 0) {
-            u32 bm = red_min[0];
-            u64 bc = red_cnt[0];
-            for (int w = 1; w < WAVES_PER_GROUP; w++) {
-                bm = min(bm, red_min[w]);
-                bc += red_cnt[w];
+        if (wid == 0) {
+            uint32_t done = 0;
+            if (lane == 0) {
+                u32 bm = red_min[0];
+                u64 bc = red_cnt[0];
+                for (int w = 1; w < WAVES_PER_GROUP; w++) {
+                    bm = min(bm, red_min[w]);
+                    bc += red_cnt[w];
+                }
+                if (bm != BIG) atomicMin(&cs->res.stage_min[s], (int)(bm + woff));
+                atomicAdd((unsigned long long *)&cs->res.stage_count[s], (unsigned long long)bc);
+                done = __hip_atomic_fetch_add(&cs->stage_done[s], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+                if (tracing) atomicMax((unsigned long long *)&cs->trace[2 + s][1], (unsigned long long)wall_clock64());
             }
-            if (bm != BIG) atomicMin(&cs->res.stage_min[s], (int)(bm + woff));
-            atomicAdd((unsigned long long *)&cs->res.stage_count[s], (unsigned long long)bc);
-            const uint32_t done =
-                __hip_atomic_fetch_add(&cs->stage_done[s], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-            if (tracing) atomicMax((unsigned long long *)&cs->trace[2 + s][1], (unsigned long long)wall_clock64());
-            if (done == sd.parts) {
-                run_checker(cs);
-                if (tracing) atomicMax((unsigned long long *)&cs->trace[2 + s][2], (unsigned long long)wall_clock64());
+            // the last workgroup of a stage checks it (and every done stage after it)
+            if (uni(done) == sd.parts) {
+                run_checker(cs, sdesc, ns);
+                if (tracing && lane == 0)
+                    atomicMax((unsigned long long *)&cs->trace[2 + s][2], (unsigned long long)wall_clock64());
             }
         }
         __syncthreads();  // qtab and red_* are rewritten by the next stage

@@ -133,12 +133,15 @@ BZ_HD int bound_c(int g, int k, int kj) {
     return v > 0 ? v : 0;
 }
 
-// Target (s, L) steps per lane in one task: about 3000 VALU operations, from
+// Target (s, L) steps per lane in one task: about BZ_SWEEP_OPS VALU operations, from
 // the per-step cost of the completions (F_3: two prefixes, add and subtract;
 // F_7: six prefixes, three rotations, add and subtract).
+#ifndef BZ_SWEEP_OPS
+#define BZ_SWEEP_OPS 3000u
+#endif
 BZ_HD uint32_t sweep_cap_for(int p, int W) {
     const uint32_t per = (p == 3) ? 2u * (6u * (uint32_t)W + 1u) : 6u * (25u * (uint32_t)W + 3u);
-    const uint32_t cap = 3000u / per;
+    const uint32_t cap = (uint32_t)(BZ_SWEEP_OPS) / per;
     return cap < 4u ? 4u : cap;
 }
 
@@ -233,6 +236,35 @@ BZ_HD void decode_base(int p, int g, int q, u64 M, u64 bi, Bin bin, Visit visit)
     }
 }
 
+// Round g of the schedule (its m stages (g, 1..m) share these): the
+// combinations of one stage, C(k, g) (p-1)^(g-1), and the coefficient
+// combinations (p-1)^(g-3) of one base of g-3 rows (1 for g < 3); saturating.
+BZ_HD u64 round_codewords(int p, int k, int g, const u64 *binom) {
+    u64 pw = 1;
+    for (int t = 1; t < g; t++) pw = sat_mul(pw, (u64)(p - 1));
+    return sat_mul(binom[k * 65 + g], pw);
+}
+BZ_HD u64 round_combos(int p, int g) {
+    u64 c = 1;
+    for (int t = 3; t < g; t++) c = sat_mul(c, (u64)(p - 1));
+    return c;
+}
+// Stages of round g within the codeword limit, given cum = the (saturated)
+// codewords of all earlier rounds: the largest j <= m with
+// sat(cum + j cw) <= max_codewords, or 0 when the coefficient combinations do
+// not fit 32 bits.  The same decision as build_schedule stage by stage.
+BZ_HD int round_stages(int m, u64 cum, u64 cw, u64 combos, u64 max_codewords) {
+    if (combos >= (1ull << 32)) return 0;
+    if (max_codewords == ~0ull) return m;
+    if (cum > max_codewords) return 0;
+    const u64 j = (max_codewords - cum) / cw;
+    return j < (u64)m ? (int)j : m;
+}
+// Tasks of a stage with g = 1 or 2 (one item per lane: a row, or a pair of rows).
+BZ_HD u64 small_stage_tasks(int k, int g) {
+    return g == 1 ? ((u64)k + 63) / 64 : ((u64)(k * (k - 1) / 2) + 63) / 64;
+}
+
 // Build the schedule: stages (g, j) for g = 1..k, j = 1..m in order, while the
 // cumulative combination count stays within max_codewords, at most
 // BZ_MAX_STAGES stages, and every index fits the kernel ((p-1)^(g-3) < 2^32,
@@ -247,15 +279,11 @@ BZ_HD int build_schedule(int p, int k, int m, const int32_t *ranks, int flags, u
     *complete = 1;
     const uint32_t cap = sweep_cap_for(p, W);
     for (int g = 1; g <= k; g++) {
-        u64 pw = 1;  // (p-1)^(g-1)
-        for (int t = 1; t < g; t++) pw = sat_mul(pw, (u64)(p - 1));
-        const u64 cw = sat_mul(binom[k * 65 + g], pw);
+        const u64 cw = round_codewords(p, k, g, binom);
         u64 tasks;
-        u64 combos = 1;
-        if (g == 1) tasks = ((u64)k + 63) / 64;
-        else if (g == 2) tasks = ((u64)(k * (k - 1) / 2) + 63) / 64;
+        const u64 combos = round_combos(p, g);
+        if (g <= 2) tasks = small_stage_tasks(k, g);
         else {
-            for (int t = 3; t < g; t++) combos = sat_mul(combos, (u64)(p - 1));
             // without count_tasks the caller fills tasks, tiles and parts of these stages
             tasks = (combos >= (1ull << 32)) ? ~0ull : count_tasks ? fill_qtable(k, g, combos, cap, binom, nullptr) : 0;
         }

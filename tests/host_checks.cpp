@@ -11,6 +11,8 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstdlib>
+#include <cstring>
+#include <random>
 #include <map>
 #include <set>
 #include <vector>
@@ -194,6 +196,105 @@ static void check_schedule() {
     if (fails == before) std::printf("OK schedule\n");
 }
 
+// The decomposition kernel builds the schedule with one round g per lane (a
+// saturating scan of the codewords of the rounds, then one stage per lane);
+// replayed here, it gives the same table as build_schedule.
+static int lane_parallel_schedule(int p, int k, int m, const int *ranks, int flags, u64 max_cw, uint32_t grid,
+                                  int W, StageDesc *st, int *complete) {
+    u64 cw[64], inc[64], tasks[64];
+    uint32_t combos[64];
+    int js[64];
+    for (int l = 0; l < 64; l++) {
+        const int g = l + 1;
+        const bool in = g <= k;
+        cw[l] = in ? round_codewords(p, k, g, BINOM) : 0;
+        const u64 cb = round_combos(p, g);
+        combos[l] = (uint32_t)cb;
+        const u64 mine = sat_mul(cw[l], (u64)m);
+        inc[l] = l ? sat_add(inc[l - 1], mine) : mine;
+        const u64 before = l ? inc[l - 1] : 0;
+        js[l] = in ? round_stages(m, before, cw[l], cb, max_cw) : m;
+        tasks[l] = (g <= 2) ? small_stage_tasks(k, g) : 0;
+    }
+    int ns = k * m;
+    *complete = 1;
+    for (int l = 0; l < k; l++)
+        if (js[l] < m) {
+            ns = l * m + js[l];
+            *complete = 0;
+            break;
+        }
+    const uint32_t cap = sweep_cap_for(p, W);
+    const int last_g = (ns + m - 1) / m;
+    for (int g = 3; g <= last_g; g++) {
+        const u64 t = fill_qtable(k, g, combos[g - 1], cap, BINOM, nullptr);
+        if (t >= (1ull << 62)) {
+            ns = std::min(ns, (g - 1) * m);
+            *complete = 0;
+            break;
+        }
+        tasks[g - 1] = t;
+    }
+    if (ns > BZ_MAX_STAGES) {
+        ns = BZ_MAX_STAGES;
+        *complete = 0;
+    }
+    for (int s = 0; s < ns; s++) {
+        const int g = s / m + 1, j = s % m + 1;
+        int L = 0;
+        for (int i = 1; i <= m; i++) L += bound_c(i <= j ? g : g - 1, k, ranks[i - 1]);
+        StageDesc &d = st[s];
+        d.g = g;
+        d.j = j;
+        d.L = L;
+        d.check = (flags & FLAG_NO_TERM) ? 0 : ((flags & FLAG_ROUND) ? (j == m) : 1);
+        d.tasks = tasks[g - 1];
+        d.tiles = (d.tasks + WAVES_PER_GROUP - 1) / WAVES_PER_GROUP;
+        d.codewords = cw[g - 1];
+        d.coef_combos = combos[g - 1];
+        d.parts = (uint32_t)(d.tiles < (u64)grid ? d.tiles : (u64)grid);
+        d.sweep_cap = cap;
+        d.pad = 0;
+    }
+    return ns;
+}
+
+static void check_parallel_schedule() {
+    const int before = fails;
+    std::mt19937_64 rng(12345);
+    int cases = 0;
+    for (int it = 0; it < 4000; it++) {
+        const int p = (rng() & 1) ? 3 : 7;
+        const int k = 1 + (int)(rng() % 64);
+        const int m = (it % 10 == 0) ? 1 + (int)(rng() % 128) : 1 + (int)(rng() % 6);
+        std::vector<int> ranks(m);
+        for (int i = 0; i < m; i++) ranks[i] = (int)(rng() % (k + 1));
+        const int flags = (int)(rng() % 3) == 0 ? 0 : (int)(rng() % 3) == 0 ? (int)FLAG_ROUND : (int)FLAG_NO_TERM;
+        u64 max_cw;
+        switch (it % 5) {
+        case 0: max_cw = ~0ull; break;
+        case 1: max_cw = rng() % 100000; break;
+        case 2: max_cw = 1ull << (rng() % 64); break;
+        case 3: max_cw = rng(); break;
+        default: max_cw = (1ull << 44); break;
+        }
+        const uint32_t grid = 1 + (uint32_t)(rng() % 2048);
+        const int W = 1 + (int)(rng() % 4);
+        static StageDesc a[BZ_MAX_STAGES], b[BZ_MAX_STAGES];
+        int ca = -1, cb = -1;
+        const int na = build_schedule(p, k, m, ranks.data(), flags, max_cw, grid, W, BINOM, a, &ca);
+        const int nb = lane_parallel_schedule(p, k, m, ranks.data(), flags, max_cw, grid, W, b, &cb);
+        CHECK(na == nb && ca == cb);
+        if (na != nb) {
+            std::printf("  p=%d k=%d m=%d max=%llu: %d vs %d\n", p, k, m, (unsigned long long)max_cw, na, nb);
+            continue;
+        }
+        for (int s = 0; s < na; s++) CHECK(std::memcmp(&a[s], &b[s], sizeof(StageDesc)) == 0);
+        cases++;
+    }
+    if (fails == before) std::printf("OK parallel schedule (%d cases)\n", cases);
+}
+
 // The kernel's work decomposition, replayed on the host: every g-row
 // combination with lowest coefficient 1 is visited exactly once, and the
 // per-task counts the kernel adds up equal the combinations visited.
@@ -301,6 +402,7 @@ int main() {
         for (int b = 0; b <= 64; b++) CHECK(binom_sat(a, b) == ~0ull || BINOM[a * 65 + b] == binom_sat(a, b));
     check_arith();
     check_schedule();
+    check_parallel_schedule();
     check_unrank();
     return fails ? 1 : 0;
 }

@@ -24,7 +24,8 @@ def test_host_checks(tmp_path):
                    check=True)
     out = subprocess.run([exe], capture_output=True, text=True)
     assert out.returncode == 0, out.stdout
-    assert out.stdout.split() == ["OK", "arith", "OK", "schedule", "OK", "unrank"]
+    lines = out.stdout.splitlines()
+    assert [l.split(" (")[0] for l in lines] == ["OK arith", "OK schedule", "OK parallel schedule", "OK unrank"]
 
 
 def _declared():
