@@ -608,25 +608,27 @@ __device__ u64 run_base_task(const StageDesc &sd, int k, int j, const u32 *__res
                              const u64 *__restrict__ gbin, const QEntry *qtab, int nq, u64 task, u32 &lmin,
                              u32 *lh, u32 woff, u32 cap) {
     const int lane = __lane_id();
-    const int g = sd.g;
-    const u64 M = sd.coef_combos;
+    const int g = uni(sd.g);
+    const u64 M = uni(sd.coef_combos);
     const int qi = uni(qtable_find(qtab, nq, task));
     const int q = g - 3 + qi;
-    const QEntry e = qtab[qi];
-    const u64 local = uni64(task - e.first);
-    const u64 chunk = uni64(local / e.nb);
-    const int block = uni((int)(local - chunk * e.nb));
-    const int s_lo = q + 1 + block * (int)e.B;
-    const int s_hi = min(s_lo + (int)e.B, k - 1);
+    // the q-group's entry as wave-uniform (scalar) values
+    const u64 e_first = uni64(qtab[qi].first), e_bases = uni64(qtab[qi].bases);
+    const uint32_t e_B = uni(qtab[qi].B), e_nb = uni(qtab[qi].nb);
+    const u64 local = task - e_first;
+    const u64 chunk = local / e_nb;
+    const int block = (int)(local - chunk * e_nb);
+    const int s_lo = q + 1 + block * (int)e_B;
+    const int s_hi = min(s_lo + (int)e_B, k - 1);
     const u64 bi = chunk * 64 + (u64)lane;
-    const bool valid = bi < e.bases;
+    const bool valid = bi < e_bases;
     u32 Q[3][W];
 #pragma unroll
     for (int b = 0; b < 3; b++)
 #pragma unroll
         for (int w = 0; w < W; w++) Q[b][w] = 0;
     if (valid) {
-        decode_base(P, g, q, M, bi, [&](int c, int i) { return binom_at(sbin, gbin, c, i); },
+        decode_base<P>(g, q, M, bi, [&](int c, int i) { return binom_at(sbin, gbin, c, i); },
                     [&](int row, int coef) {
                         const Row<W> r = load_row<P, W>(rows, j, row);
                         add_scaled<P, W>(Q, r.p, coef);
@@ -698,8 +700,8 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
     const int wid = threadIdx.x >> 6;
     const uint32_t grid = gridDim.x, b = blockIdx.x;
     if (cs->res.status != BZ_OK) return;
-    const int k = cs->k, n = cs->n;
-    const int ns = cs->res.n_table;
+    const int k = uni(cs->k), n = uni(cs->n);
+    const int ns = uni(cs->res.n_table);
     const bool tracing = (cs->flags & FLAG_TRACE) != 0;
     if (tracing && threadIdx.x == 0) atomicMin((unsigned long long *)&cs->trace[1][0], (unsigned long long)wall_clock64());
     for (int i = threadIdx.x; i < BZ_MAX_K * BIN_I; i += blockDim.x) sbin[i] = gbin[(i / BIN_I) * 65 + i % BIN_I];
@@ -749,28 +751,30 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
         // work on the earliest unchecked stage runs at a higher wave priority than run-ahead work
         if (crit) __builtin_amdgcn_s_setprio(2);
         else __builtin_amdgcn_s_setprio(0);
-        const int nq = k - 2 - (sd.g - 3);
-        const int j = sd.j - 1;
-        const u32 woff = skip ? (u32)sd.g : 0u;
+        const int sg = uni(sd.g);
+        const int nq = k - 2 - (sg - 3);
+        const int j = uni(sd.j - 1);
+        const u64 tiles = uni64(sd.tiles), tasks = uni64(sd.tasks);
+        const u32 woff = skip ? (u32)sg : 0u;
         u32 lmin = BIG;
         u64 cnt = 0;
         for (u64 r = 0;; r++) {
             const u64 tile = tile_of(r, b, grid, s);
-            if (tile >= sd.tiles) break;  // a missing tile only happens in the last round
+            if (tile >= tiles) break;  // a missing tile only happens in the last round
             if (r > 0) {
                 // a later stage after termination is abandoned (its results are never read)
                 const int t2 = uni(lane == 0 ? ctl_term(ld_relaxed(&cs->res.ctl)) : 0);
                 if (t2 >= 0 && s > t2) break;
             }
             const u64 task = tile * WAVES_PER_GROUP + (u64)wid;
-            if (task >= sd.tasks) continue;
+            if (task >= tasks) continue;
             if constexpr (HIST) {
                 for (int w = lane; w <= n; w += 64) lh[w] = 0;
             }
-            if (sd.g >= 3)
+            if (sg >= 3)
                 cnt += run_base_task<P, W, HIST>(sd, k, j, rows, sbin, gbin, qtab, nq, task, lmin, lh, woff, cap);
             else
-                cnt += run_small_task<P, W, HIST>(sd.g, k, j, rows, task, lmin, lh, woff, cap);
+                cnt += run_small_task<P, W, HIST>(sg, k, j, rows, task, lmin, lh, woff, cap);
             if constexpr (HIST) {
                 for (int w = lane; w <= n; w += 64) {
                     const u32 c = lh[w];

@@ -106,10 +106,15 @@ BZ_HD int ctl_U(u64 c) { return (int)((c >> 32) & 0xffff); }
 // Stages with at most this many combinations never wait for earlier stages.
 constexpr uint64_t SMALL_STAGE = 1ull << 22;
 
-// Workgroups start a stage only once every stage more than LOOKAHEAD places
-// before it has been checked (so work on stages after the terminating one is
-// bounded).
-constexpr int LOOKAHEAD = 1;
+// Workgroups start a large stage only once every stage more than LOOKAHEAD
+// places before it has been checked.  0 (the default) runs large stages one at
+// a time: work on a stage beyond the current one competes with it for the
+// vector ALUs and is thrown away when the current stage ends the run, which
+// measured slower than draining each stage first.
+#ifndef BZ_LOOKAHEAD
+#define BZ_LOOKAHEAD 0
+#endif
+constexpr int LOOKAHEAD = BZ_LOOKAHEAD;
 
 BZ_HD u64 sat_mul(u64 a, u64 b) {
     u64 r;
@@ -202,19 +207,32 @@ BZ_HD int qtable_find(const QEntry *tab, int nq, u64 t) {
 }
 
 // Decode base number bi (< bases) of the group with top row q: its lower rows
-// (the (g-3)-subset of {0..q-1} of colex rank bi / M) and the coefficients from
-// the base-(p-1) digits of bi % M.  visit(row, coef) is called for every row
-// of the base, the top row q first.  The lowest row of the base gets
-// coefficient 1.  bin(c, i) returns C(c, i).
-template <typename Bin, typename Visit>
-BZ_HD void decode_base(int p, int g, int q, u64 M, u64 bi, Bin bin, Visit visit) {
-    u64 rho = bi / M;
-    u64 ci = bi - rho * M;
+// (the (g-3)-subset of {0..q-1} of colex rank bi / M, M = (p-1)^(g-3)) and the
+// coefficients from the base-(p-1) digits of bi % M, least significant first.
+// visit(row, coef) is called for every row of the base, the top row q first.
+// The lowest row of the base gets coefficient 1.  bin(c, i) returns C(c, i).
+// M < 2^32 (the schedule guarantees it), so the digits are 32-bit work with a
+// constant divisor; the rank takes a shift (p = 3) or one division by M.
+template <int P, typename Bin, typename Visit>
+BZ_HD void decode_base(int g, int q, u64 M, u64 bi, Bin bin, Visit visit) {
     const int t = g - 3;  // lower rows
+    u64 rho;
+    uint32_t ci;
+    if (P == 3) {
+        rho = bi >> t;
+        ci = (uint32_t)bi & (uint32_t)(M - 1);
+    } else if ((bi >> 32) == 0) {
+        const uint32_t b32 = (uint32_t)bi, r = b32 / (uint32_t)M;
+        rho = r;
+        ci = b32 - r * (uint32_t)M;
+    } else {
+        rho = bi / M;
+        ci = (uint32_t)(bi - rho * M);
+    }
     int coef = 1;
     if (t > 0) {
-        coef = (int)(ci % (u64)(p - 1)) + 1;
-        ci /= (u64)(p - 1);
+        coef = (int)(ci % (uint32_t)(P - 1)) + 1;
+        ci /= (uint32_t)(P - 1);
     }
     visit(q, coef);
     int hi = q - 1;
@@ -229,8 +247,8 @@ BZ_HD void decode_base(int p, int g, int q, u64 M, u64 bi, Bin bin, Visit visit)
         hi = lo - 1;
         int cf = 1;
         if (i > 1) {
-            cf = (int)(ci % (u64)(p - 1)) + 1;
-            ci /= (u64)(p - 1);
+            cf = (int)(ci % (uint32_t)(P - 1)) + 1;
+            ci /= (uint32_t)(P - 1);
         }
         visit(lo, cf);
     }

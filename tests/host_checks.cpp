@@ -363,8 +363,10 @@ static void check_unrank() {
                                 if (bi >= e.bases) continue;
                                 nvalid++;
                                 std::vector<int> rows, coefs;
-                                decode_base(P, g, q, d.coef_combos, bi, [&](int c, int i) { return BINOM[c * 65 + i]; },
-                                            [&](int row, int coef) { rows.push_back(row); coefs.push_back(coef); });
+                                auto bin = [&](int c, int i) { return BINOM[c * 65 + i]; };
+                                auto visit = [&](int row, int coef) { rows.push_back(row); coefs.push_back(coef); };
+                                if (P == 3) decode_base<3>(g, q, d.coef_combos, bi, bin, visit);
+                                else decode_base<7>(g, q, d.coef_combos, bi, bin, visit);
                                 CHECK((int)rows.size() == g - 2);
                                 CHECK(rows[0] == q);
                                 for (size_t i = 1; i < rows.size(); i++) CHECK(rows[i] < rows[i - 1]);
