@@ -107,7 +107,8 @@ typedef struct {
                                  start of the decomposition kernel: row 0 = decomposition
                                  {start, rows loaded, matrices reduced, end}; row 1 =
                                  enumeration kernel {first workgroup start, last workgroup end};
-                                 row 2+s = stage s {first start, last end, checked, workgroups} */
+                                 row 2+s = stage s {first workgroup start, last workgroup
+                                 end, checked, last workgroup start} */
 } bz_options;
 
 /* Fill *o with the defaults above. */

@@ -325,10 +325,8 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, c
         o.trace_out[4] = ns(c->host_trace[1][0]);
         o.trace_out[5] = ns(c->host_trace[1][1]);
         const int nt = c->host_res->n_table;
-        for (int sidx = 0; sidx < nt; sidx++) {
-            for (int i = 0; i < 3; i++) o.trace_out[(2 + sidx) * 4 + i] = ns(c->host_trace[2 + sidx][i]);
-            o.trace_out[(2 + sidx) * 4 + 3] = c->host_trace[2 + sidx][3];
-        }
+        for (int sidx = 0; sidx < nt; sidx++)
+            for (int i = 0; i < 4; i++) o.trace_out[(2 + sidx) * 4 + i] = ns(c->host_trace[2 + sidx][i]);
     }
     if (o.histograms && (st == BZ_OK || st == BZ_ERR_LIMIT)) {
         for (int sidx = 0; sidx < out->n_stages; sidx++)

@@ -33,18 +33,22 @@ __device__ __forceinline__ u64 uni64(u64 x) {
     return ((u64)hi << 32) | lo;
 }
 
+// Run state shared between workgroups.  No release/acquire fences are used
+// (an agent-scope fence writes back or invalidates a whole L2, which costs
+// every wave on the XCD): a workgroup's published minimum and count are
+// atomics that have completed (vmcnt drained) before its done-increment is
+// issued, and the checker reads counters and minima with read-modify-write
+// atomics, which are performed at the single coherence point of their
+// address.  Waiting workgroups poll the control word with plain atomic loads.
 template <typename T>
-__device__ __forceinline__ T ld_acq(T *p) {
-    return __hip_atomic_load(p, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
-}
-template <typename T>
-__device__ __forceinline__ T ld_relaxed(T *p) {
+__device__ __forceinline__ T ld_poll(T *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 template <typename T>
-__device__ __forceinline__ void st_rel(T *p, T v) {
-    __hip_atomic_store(p, v, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ T rd_atomic(T *p) {
+    return __hip_atomic_fetch_or(p, (T)0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ void drain_vmem() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // word q of a small register array, q wave-uniform (no dynamic register indexing)
 template <int N>
@@ -469,6 +473,18 @@ __device__ __forceinline__ Row<W> load_row(const u32 *__restrict__ rows, int j, 
 }
 
 // x = x + h * r (exact, Algorithm 3 / 4 after the scaling of Sec. 4.2)
+// An empty asm that takes the (wave-uniform) words of a row as scalar
+// operands: the loads of a group of rows are all issued before it, so they are
+// not sunk one by one into the conditional blocks that use them.
+template <int P, int W>
+__device__ __forceinline__ void pin_row(const Row<W> &r) {
+#pragma unroll
+    for (int w = 0; w < W; w++) {
+        asm volatile("" ::"s"(r.p[0][w]), "s"(r.p[1][w]));
+        if constexpr (P == 7) asm volatile("" ::"s"(r.p[2][w]), "s"(r.any[w]));
+    }
+}
+
 template <int P, int W>
 __device__ __forceinline__ void add_scaled(u32 (&x)[3][W], const u32 (&r)[3][W], int h) {
 #pragma unroll
@@ -532,8 +548,7 @@ __device__ __forceinline__ void complete_all(const u32 (&Pv)[NA][3][W], const u3
 }
 
 // Prefixes Q + h * Rs for the NA coefficients h = 1..NA of row s, then every
-// last row L = s+1..k-1 for all of them; the next row is loaded while the
-// current one is combined.
+// last row L = s+1..k-1 for all of them.
 template <int P, int W, int NA, bool HIST>
 __device__ __forceinline__ void extend_and_sweep(const u32 *__restrict__ rows, int j, int s, int k,
                                                  const u32 (&Q)[3][W], const Row<W> &Rs, u32 &lmin, u32 *lh,
@@ -549,12 +564,18 @@ __device__ __forceinline__ void extend_and_sweep(const u32 *__restrict__ rows, i
 #pragma unroll
         for (int w = 0; w < W; w++) anyP[a][w] = Pv[a][0][w] | Pv[a][1][w] | Pv[a][2][w];
     }
-    const int L0 = uni(s + 1);
-    Row<W> Rc = load_row<P, W>(rows, j, L0);
-    for (int L = L0; L < k; L++) {
-        const Row<W> Rn = load_row<P, W>(rows, j, min(L + 1, k - 1));
-        complete_all<P, W, NA, HIST>(Pv, anyP, Rc, lmin, lh, woff, cap);
-        Rc = Rn;
+    // UR rows per step, all loads issued before the first is used, so one wait
+    // covers UR rows (rows past k-1 repeat row k-1 and are not combined)
+    constexpr int UR = (W <= 2) ? 4 : 2;
+    for (int L = uni(s + 1); L < k; L += UR) {
+        Row<W> R[UR];
+#pragma unroll
+        for (int u = 0; u < UR; u++) R[u] = load_row<P, W>(rows, j, min(L + u, k - 1));
+#pragma unroll
+        for (int u = 0; u < UR; u++) pin_row<P, W>(R[u]);
+#pragma unroll
+        for (int u = 0; u < UR; u++)
+            if (L + u < k) complete_all<P, W, NA, HIST>(Pv, anyP, R[u], lmin, lh, woff, cap);
     }
 }
 
@@ -653,18 +674,17 @@ __device__ u64 run_base_task(const StageDesc &sd, int k, int j, const u32 *__res
 __device__ void run_checker(CodeState *cs, const StageDesc *sdesc, int ns) {
     const int lane = __lane_id();
     for (int guard = 0; guard <= 2 * BZ_MAX_STAGES; guard++) {
-        u64 st = uni64(__hip_atomic_load(&cs->res.ctl, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+        u64 st = uni64(rd_atomic(&cs->res.ctl));
         const int c = ctl_checked(st);
         if (c >= ns || ctl_term(st) >= 0) return;
         const int s = c + lane;
-        // every participant published its minimum before its release-increment of done
-        const bool done = s < ns && __hip_atomic_load(&cs->stage_done[s], __ATOMIC_ACQUIRE,
-                                                      __HIP_MEMORY_SCOPE_AGENT) == sdesc[s].parts;
+        // every participant's minimum was performed before its increment of done
+        const bool done = s < ns && rd_atomic(&cs->stage_done[s]) == sdesc[s].parts;
         const u64 notdone = __ballot(!done);
         const int nd = notdone ? __builtin_ctzll(notdone) : 64;  // stages c .. c+nd-1 are done
         if (nd == 0) return;
         int u = (int)ctl_U(st);
-        if (lane < nd) u = min(u, __hip_atomic_load(&cs->res.stage_min[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        if (lane < nd) u = min(u, rd_atomic(&cs->res.stage_min[s]));
         for (int off = 1; off < 64; off <<= 1) {
             const int o = __shfl_up(u, off);
             if (lane >= off) u = min(u, o);
@@ -675,7 +695,7 @@ __device__ void run_checker(CodeState *cs, const StageDesc *sdesc, int ns) {
         const u64 nw = stops ? ctl_make(c + i, c + i, ui) : ctl_make(c + nd, -1, ui);
         int ok = 0;
         if (lane == 0)
-            ok = __hip_atomic_compare_exchange_strong(&cs->res.ctl, &st, nw, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE,
+            ok = __hip_atomic_compare_exchange_strong(&cs->res.ctl, &st, nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
         ok = __shfl(ok, 0);
         // done: the run ended, or every done stage is checked; another checker
@@ -716,29 +736,37 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
         if (threadIdx.x == 0) {
             // a large stage waits until every stage before s - lookahead is checked
             // (small ones never wait), or the run ended
-            const long long t0 = wall_clock64();
+            // the clock and the status word are read every 256 polls only: the
+            // real-time counter is one shared unit, slow when a thousand waves read it
+            u64 t0 = 0;
             int term;
             u64 st;
-            for (;;) {
-                st = ld_relaxed(&cs->res.ctl);
+            for (uint32_t it = 0;; it++) {
+                st = ld_poll(&cs->res.ctl);
                 term = ctl_term(st);
                 if (term >= 0 || sd.codewords <= SMALL_STAGE || ctl_checked(st) >= s - lookahead) break;
-                if (ld_relaxed(&cs->res.status) != BZ_OK) {
-                    term = -2;
-                    break;
-                }
-                if ((u64)(wall_clock64() - t0) > timeout_ticks) {
-                    __hip_atomic_store(&cs->res.status, (int)BZ_ERR_DEVICE, __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                    term = -2;
-                    break;
+                if ((it & 255u) == 255u) {
+                    if (ld_poll(&cs->res.status) != BZ_OK) {
+                        term = -2;
+                        break;
+                    }
+                    const u64 now = (u64)wall_clock64();
+                    if (t0 == 0) {
+                        t0 = now;
+                    } else if (now - t0 > timeout_ticks) {
+                        __hip_atomic_store(&cs->res.status, (int)BZ_ERR_DEVICE, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+                        term = -2;
+                        break;
+                    }
                 }
                 __builtin_amdgcn_s_sleep(8);
             }
             s_term = term;
             if (tracing) {
-                atomicMin((unsigned long long *)&cs->trace[2 + s][0], (unsigned long long)wall_clock64());
-                atomicAdd((unsigned long long *)&cs->trace[2 + s][3], 1ull);
+                const unsigned long long now = (unsigned long long)wall_clock64();
+                atomicMin((unsigned long long *)&cs->trace[2 + s][0], now);
+                atomicMax((unsigned long long *)&cs->trace[2 + s][3], now);
             }
             s_crit = ctl_checked(st) >= s;  // the earliest unchecked stage: no later stage can wait on it
         }
@@ -763,7 +791,7 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
             if (tile >= tiles) break;  // a missing tile only happens in the last round
             if (r > 0) {
                 // a later stage after termination is abandoned (its results are never read)
-                const int t2 = uni(lane == 0 ? ctl_term(ld_relaxed(&cs->res.ctl)) : 0);
+                const int t2 = uni(lane == 0 ? ctl_term(ld_poll(&cs->res.ctl)) : 0);
                 if (t2 >= 0 && s > t2) break;
             }
             const u64 task = tile * WAVES_PER_GROUP + (u64)wid;
@@ -788,7 +816,7 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
             red_min[wid] = lmin;
             red_cnt[wid] = cnt;
         }
-        if constexpr (HIST) __threadfence();
+        if constexpr (HIST) drain_vmem();  // this wave's histogram atomics are performed
         __syncthreads();
         if (wid == 0) {
             uint32_t done = 0;
@@ -801,7 +829,8 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
                 }
                 if (bm != BIG) atomicMin(&cs->res.stage_min[s], (int)(bm + woff));
                 atomicAdd((unsigned long long *)&cs->res.stage_count[s], (unsigned long long)bc);
-                done = __hip_atomic_fetch_add(&cs->stage_done[s], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+                drain_vmem();  // minimum and count performed before done counts this workgroup
+                done = __hip_atomic_fetch_add(&cs->stage_done[s], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
                 if (tracing) atomicMax((unsigned long long *)&cs->trace[2 + s][1], (unsigned long long)wall_clock64());
             }
             // the last workgroup of a stage checks it (and every done stage after it)
