@@ -86,7 +86,7 @@ struct CodeState {
     // wall-clock trace (FLAG_TRACE): row 0 = decomposition start, its phases
     // (rows loaded, matrices reduced, schedule built); row 1 = enumeration kernel
     // first start / last end; row 2+s = stage s: first start, last end, checked,
-    // workgroups that took part
+    // last start
     u64 trace[BZ_MAX_STAGES + 2][4];
     StageDesc stages[BZ_MAX_STAGES];
 };
