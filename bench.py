@@ -86,6 +86,88 @@ def cpu_baseline(cfg, gpu_d, budget_s):
             "d_match": match}
 
 
+# The paper's arithmetic benchmark (Sec. 5, Tables 1-2): pairwise addition of
+# two sets of 10,000 vectors of 512 symbols, repeated 10,000 times, and its
+# single-core times on the AMD EPYC 7F52 (context only, another machine).
+MICRO_VARIANTS = [
+    # field, label, encoding, op name, boolean ops per 32-symbol word per addition, EPYC seconds
+    (3, "F_3 natural encoding, Algorithm 3 (HQ)", "natural", "add", 9, 1.04),
+    (3, "F_3 Kawahara et al. encoding, Algorithm 2 (KAT)", "kat", "kat", 6, 0.89),
+    (7, "F_7 natural encoding, Algorithm 4 (HQ)", "natural", "add", 22, 2.30),
+]
+
+
+def micro(nvec=10000, nsym=512, reps=10000, passes=2000):
+    """Sliced exact addition on the GPU at the paper's sizes.  Chain mode: one
+    launch, every thread applies x <- x + b `reps` times to one 32-symbol word
+    in registers (the arithmetic alone).  Streaming mode: `passes` single
+    additions c = a + b over all vectors, each a launch, captured in one HIP
+    graph and replayed (memory and launch bound)."""
+    import numpy as np
+    import torch
+    from paper_2603_29942_amd import bz
+    dev = torch.device("cuda:0")
+    out = []
+    for p, label, enc, opname, ops_word, epyc_s in MICRO_VARIANTS:
+        rng = np.random.default_rng([5, p, len(out)])
+        a = rng.integers(0, p, (nvec, nsym), dtype=np.uint8)
+        b = rng.integers(0, p, (nvec, nsym), dtype=np.uint8)
+        e = bz.ENC_KAT if enc == "kat" else bz.ENC_NATURAL
+        op = bz.OP_KAT_ADD if opname == "kat" else bz.OP_ADD
+        A = bz.bz_sliced_pack(p, torch.from_numpy(a).to(dev), encoding=e)
+        B = bz.bz_sliced_pack(p, torch.from_numpy(b).to(dev), encoding=e)
+        O = torch.empty_like(A)
+        want = (a.astype(np.int64) + reps * b.astype(np.int64)) % p
+        bz.bz_sliced_op(p, op, A, B, nsym, reps=reps, out=O)  # warm-up
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        bz.bz_sliced_op(p, op, A, B, nsym, reps=reps, out=O)
+        e1.record()
+        torch.cuda.synchronize()
+        chain_s = e0.elapsed_time(e1) / 1e3
+        ok_chain = bool(np.array_equal(bz.bz_sliced_unpack(p, O, nsym, encoding=e).cpu().numpy(), want))
+        # streaming: single additions, captured once and replayed
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            for _ in range(3):
+                bz.bz_sliced_op(p, op, A, B, nsym, reps=1, out=O)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            for _ in range(passes):
+                bz.bz_sliced_op(p, op, A, B, nsym, reps=1, out=O)
+        graph.replay()
+        torch.cuda.synchronize()
+        e0.record()
+        graph.replay()
+        e1.record()
+        torch.cuda.synchronize()
+        pass_s = e0.elapsed_time(e1) / 1e3 / passes
+        ok_stream = bool(np.array_equal(bz.bz_sliced_unpack(p, O, nsym, encoding=e).cpu().numpy(),
+                                        (a.astype(np.int64) + b.astype(np.int64)) % p))
+        r = 2 if p == 3 else 3
+        words = nvec * ((nsym + 31) // 32)
+        adds = nvec * nsym * reps
+        stream_bytes = 3 * words * r * 4
+        out.append({
+            "variant": label, "p": p,
+            "chain": {"seconds_for_paper_workload": chain_s, "symbol_additions_per_s": adds / chain_s,
+                      "bool_ops_per_s": words * reps * ops_word / chain_s,
+                      "frac_of_int32_valu_peak": words * reps * ops_word / chain_s / (VALU_PEAK_TOPS * 1e12),
+                      "correct": ok_chain},
+            "streaming": {"us_per_pass": pass_s * 1e6, "seconds_for_paper_workload": pass_s * reps,
+                          "hbm_GBps": stream_bytes / pass_s / 1e9, "frac_of_hbm_peak": stream_bytes / pass_s / 8e12,
+                          "bytes_per_pass": stream_bytes, "correct": ok_stream},
+            "paper_epyc_7f52_1core_s": epyc_s,
+        })
+    return {"metric": "sliced exact additions, the arithmetic benchmark of Tables 1-2",
+            "workload": f"2 x {nvec} vectors x {nsym} symbols, {reps} repeated additions",
+            "dtype": "u32", "data": "synthetic", "results": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +177,8 @@ def main():
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--micro", action="store_true",
+                    help="only run the sliced-arithmetic benchmark (Tables 1-2 sizes) and print its JSON line")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (the known-size copy kernel that "
                          "scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -109,6 +193,9 @@ def main():
     from paper_2603_29942_amd import bz, synth
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.micro:
+        print(json.dumps(micro()), flush=True)
+        return
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20
         a = torch.ones(nbytes, dtype=torch.uint8, device=dev)

@@ -154,8 +154,12 @@ int bz_sliced_pack(int p, int encoding, int nvec, int nsym, const uint8_t *sym, 
  * encoding decodes to 255) */
 int bz_sliced_unpack(int p, int encoding, int nvec, int nsym, const uint32_t *planes, uint8_t *sym,
                      void *stream);
-/* out = op(a, b) for every vector, repeated `reps` times (each repetition
- * recomputes the same result; reps > 1 is for timing). */
+/* out = op applied `reps` times to a with operand b, x <- op(x, b) starting
+ * from x = a: a + reps*b (BZ_OP_ADD, BZ_OP_KAT_ADD), a - reps*b (BZ_OP_SUB),
+ * 2^reps * a (BZ_OP_DOUBLE); the isometric masks need reps = 1.  The chain
+ * runs in registers, so reps > 1 times the arithmetic of Tables 1-2 and
+ * reps = 1 a single pass over memory.  out may alias a.  BZ_ERR_ARG for
+ * p, op or sizes out of range. */
 int bz_sliced_op(int p, int op, int nvec, int nsym, const uint32_t *a, const uint32_t *b,
                  uint32_t *out, int reps, void *stream);
 

@@ -220,6 +220,19 @@ int finish(int p, int n, int k, int flags, u64 max_cw, const CodeResult &r, bz_r
     return BZ_OK;
 }
 
+template <int P>
+void launch_op(int op, int blocks, hipStream_t s, int nvec, int words, const u32 *a, const u32 *b, u32 *out,
+               int reps) {
+    switch (op) {
+    case BZ_OP_ADD: op_kernel<P, BZ_OP_ADD><<<blocks, 256, 0, s>>>(nvec, words, a, b, out, reps); break;
+    case BZ_OP_SUB: op_kernel<P, BZ_OP_SUB><<<blocks, 256, 0, s>>>(nvec, words, a, b, out, reps); break;
+    case BZ_OP_DOUBLE: op_kernel<P, BZ_OP_DOUBLE><<<blocks, 256, 0, s>>>(nvec, words, a, b, out, reps); break;
+    case BZ_OP_ISO_ADD: op_kernel<P, BZ_OP_ISO_ADD><<<blocks, 256, 0, s>>>(nvec, words, a, b, out, reps); break;
+    case BZ_OP_ISO_SUB: op_kernel<P, BZ_OP_ISO_SUB><<<blocks, 256, 0, s>>>(nvec, words, a, b, out, reps); break;
+    default: op_kernel<P, BZ_OP_KAT_ADD><<<blocks, 256, 0, s>>>(nvec, words, a, b, out, reps); break;
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -368,12 +381,14 @@ int bz_sliced_op(int p, int op, int nvec, int nsym, const uint32_t *a, const uin
     if ((p != 3 && p != 7) || nvec < 0 || nsym < 1 || !a || !out || reps < 1) return BZ_ERR_ARG;
     if (op < BZ_OP_ADD || op > BZ_OP_KAT_ADD || (op == BZ_OP_KAT_ADD && p != 3)) return BZ_ERR_ARG;
     if (op != BZ_OP_DOUBLE && !b) return BZ_ERR_ARG;
+    if ((op == BZ_OP_ISO_ADD || op == BZ_OP_ISO_SUB) && reps != 1) return BZ_ERR_ARG;
     const int words = (nsym + 31) / 32;
     const long long total = (long long)nvec * words;
     if (total == 0) return BZ_OK;
+    if (total > (1ll << 40)) return BZ_ERR_ARG;
     const int blocks = (int)((total + 255) / 256);
-    if (p == 3) op_kernel<3><<<blocks, 256, 0, (hipStream_t)stream>>>(op, nvec, words, a, b, out, reps);
-    else op_kernel<7><<<blocks, 256, 0, (hipStream_t)stream>>>(op, nvec, words, a, b, out, reps);
+    if (p == 3) launch_op<3>(op, blocks, (hipStream_t)stream, nvec, words, a, b, out, reps);
+    else launch_op<7>(op, blocks, (hipStream_t)stream, nvec, words, a, b, out, reps);
     return hipGetLastError() == hipSuccess ? BZ_OK : BZ_ERR_DEVICE;
 }
 

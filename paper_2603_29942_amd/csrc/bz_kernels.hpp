@@ -888,50 +888,51 @@ __device__ __forceinline__ void kat_add(u32 a0, u32 a1, u32 b0, u32 b1, u32 &s0,
     s1 = t0 | u1;
 }
 
-template <int P>
-__global__ void op_kernel(int op, int nvec, int words, const u32 *__restrict__ A, const u32 *__restrict__ B,
+// One application of op to x (in place) with operand y.
+template <int P, int OP>
+__device__ __forceinline__ void apply_op(u32 (&x)[3], const u32 (&y)[3]) {
+    if constexpr (P == 3) {
+        if constexpr (OP == BZ_OP_ADD) f3_add(x[0], x[1], y[0], y[1], x[0], x[1]);
+        else if constexpr (OP == BZ_OP_SUB) {
+            u32 n0, n1;
+            f3_neg(y[0], y[1], n0, n1);
+            f3_add(x[0], x[1], n0, n1, x[0], x[1]);
+        } else if constexpr (OP == BZ_OP_DOUBLE) f3_neg(x[0], x[1], x[0], x[1]);
+        else if constexpr (OP == BZ_OP_ISO_ADD) { x[0] = f3_iso_add(x[0], x[1], y[0], y[1]); x[1] = 0; }
+        else if constexpr (OP == BZ_OP_ISO_SUB) { x[0] = f3_iso_sub(x[0], x[1], y[0], y[1]); x[1] = 0; }
+        else kat_add(x[0], x[1], y[0], y[1], x[0], x[1]);
+    } else {
+        if constexpr (OP == BZ_OP_ADD) f7_add(x[0], x[1], x[2], y[0], y[1], y[2], x[0], x[1], x[2]);
+        else if constexpr (OP == BZ_OP_SUB) {
+            u32 n0, n1, n2;
+            f7_neg(y[0], y[1], y[2], n0, n1, n2);
+            f7_add(x[0], x[1], x[2], n0, n1, n2, x[0], x[1], x[2]);
+        } else if constexpr (OP == BZ_OP_DOUBLE) f7_double(x[0], x[1], x[2], x[0], x[1], x[2]);
+        else if constexpr (OP == BZ_OP_ISO_ADD) { x[0] = f7_iso_add(x[0], x[1], x[2], y[0], y[1], y[2]); x[1] = x[2] = 0; }
+        else { x[0] = f7_iso_sub(x[0], x[1], x[2], y[0], y[1], y[2]); x[1] = x[2] = 0; }
+    }
+}
+
+// out = op applied reps times to a with operand b (x <- op(x, b), x = a first):
+// a + reps*b, a - reps*b, 2^reps a; the isometric masks take reps = 1.  One
+// thread per (vector, word); the chain stays in registers, so reps > 1 times
+// the arithmetic itself and reps = 1 one streaming pass over HBM.
+template <int P, int OP>
+__global__ void op_kernel(int nvec, int words, const u32 *__restrict__ A, const u32 *__restrict__ B,
                           u32 *__restrict__ O, int reps) {
     constexpr int R = (P == 3) ? 2 : 3;
     const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long long)nvec * words) return;
     const int v = (int)(idx / words), w = (int)(idx % words);
-    u32 a[3] = {0, 0, 0}, b[3] = {0, 0, 0}, o[3] = {0, 0, 0};
+    u32 x[3] = {0, 0, 0}, y[3] = {0, 0, 0};
+#pragma unroll
     for (int i = 0; i < R; i++) {
-        a[i] = A[((size_t)v * R + i) * words + w];
-        b[i] = B ? B[((size_t)v * R + i) * words + w] : 0u;
+        x[i] = A[((size_t)v * R + i) * words + w];
+        y[i] = B ? B[((size_t)v * R + i) * words + w] : 0u;
     }
-    for (int rep = 0; rep < reps; rep++) {
-        // opaque copies: every repetition recomputes the operation
-        u32 x[3] = {a[0], a[1], a[2]}, y[3] = {b[0], b[1], b[2]};
-        for (int i = 0; i < 3; i++) {
-            asm volatile("" : "+v"(x[i]));
-            asm volatile("" : "+v"(y[i]));
-        }
-        if constexpr (P == 3) {
-            switch (op) {
-            case BZ_OP_ADD: f3_add(x[0], x[1], y[0], y[1], o[0], o[1]); break;
-            case BZ_OP_SUB: { u32 n0, n1; f3_neg(y[0], y[1], n0, n1); f3_add(x[0], x[1], n0, n1, o[0], o[1]); } break;
-            case BZ_OP_DOUBLE: f3_neg(x[0], x[1], o[0], o[1]); break;
-            case BZ_OP_ISO_ADD: o[0] = f3_iso_add(x[0], x[1], y[0], y[1]); o[1] = 0; break;
-            case BZ_OP_ISO_SUB: o[0] = f3_iso_sub(x[0], x[1], y[0], y[1]); o[1] = 0; break;
-            default: kat_add(x[0], x[1], y[0], y[1], o[0], o[1]); break;
-            }
-        } else {
-            switch (op) {
-            case BZ_OP_ADD: f7_add(x[0], x[1], x[2], y[0], y[1], y[2], o[0], o[1], o[2]); break;
-            case BZ_OP_SUB: {
-                u32 n0, n1, n2;
-                f7_neg(y[0], y[1], y[2], n0, n1, n2);
-                f7_add(x[0], x[1], x[2], n0, n1, n2, o[0], o[1], o[2]);
-            } break;
-            case BZ_OP_DOUBLE: f7_double(x[0], x[1], x[2], o[0], o[1], o[2]); break;
-            case BZ_OP_ISO_ADD: o[0] = f7_iso_add(x[0], x[1], x[2], y[0], y[1], y[2]); o[1] = o[2] = 0; break;
-            default: o[0] = f7_iso_sub(x[0], x[1], x[2], y[0], y[1], y[2]); o[1] = o[2] = 0; break;
-            }
-        }
-        for (int i = 0; i < R; i++) asm volatile("" ::"v"(o[i]));
-    }
-    for (int i = 0; i < R; i++) O[((size_t)v * R + i) * words + w] = o[i];
+    for (int rep = 0; rep < reps; rep++) apply_op<P, OP>(x, y);
+#pragma unroll
+    for (int i = 0; i < R; i++) O[((size_t)v * R + i) * words + w] = x[i];
 }
 
 }  // namespace bz

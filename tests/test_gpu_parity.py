@@ -74,10 +74,12 @@ def test_sliced_arithmetic(bz, p, nsym):
     B = bz.bz_sliced_pack(p, torch.from_numpy(b).cuda())
     assert np.array_equal(bz.bz_sliced_unpack(p, A, nsym).cpu().numpy(), a)
     ai, bi = a.astype(int), b.astype(int)
-    expect = {bz.OP_ADD: (ai + bi) % p, bz.OP_SUB: (ai - bi) % p, bz.OP_DOUBLE: (2 * ai) % p}
-    for op, want in expect.items():
-        out = bz.bz_sliced_op(p, op, A, B, nsym, reps=3)
-        assert np.array_equal(bz.bz_sliced_unpack(p, out, nsym).cpu().numpy(), want), op
+    for reps in (1, 3):
+        expect = {bz.OP_ADD: (ai + reps * bi) % p, bz.OP_SUB: (ai - reps * bi) % p,
+                  bz.OP_DOUBLE: (2 ** reps * ai) % p}
+        for op, want in expect.items():
+            out = bz.bz_sliced_op(p, op, A, B, nsym, reps=reps)
+            assert np.array_equal(bz.bz_sliced_unpack(p, out, nsym).cpu().numpy(), want), (op, reps)
     for op, want in [(bz.OP_ISO_ADD, (ai + bi) % p != 0), (bz.OP_ISO_SUB, (ai - bi) % p != 0)]:
         out = bz.bz_sliced_op(p, op, A, B, nsym).cpu().numpy().view(np.uint32)
         bits = np.unpackbits(out[:, 0, :].view(np.uint8), axis=1, bitorder="little")[:, :nsym]
@@ -89,6 +91,37 @@ def test_sliced_arithmetic(bz, p, nsym):
         out = bz.bz_sliced_op(3, bz.OP_KAT_ADD, Ak, Bk, nsym)
         assert np.array_equal(bz.bz_sliced_unpack(3, out, nsym, encoding=bz.ENC_KAT).cpu().numpy(),
                               (ai + bi) % 3)
+
+
+@pytest.mark.parametrize("p,enc", [(3, "natural"), (3, "kat"), (7, "natural")])
+def test_sliced_repeated_addition_benchmark_shape(bz, p, enc):
+    """The arithmetic benchmark's shape (Tables 1-2: 10,000 vectors of 512
+    symbols): a chain of reps additions in registers gives a + reps*b mod p."""
+    import torch
+    say(f"case sliced chain p={p} enc={enc}")
+    rng = np.random.default_rng([11, p])
+    nvec, nsym = 10000, 512
+    a = rng.integers(0, p, (nvec, nsym), dtype=np.uint8)
+    b = rng.integers(0, p, (nvec, nsym), dtype=np.uint8)
+    e = bz.ENC_KAT if enc == "kat" else bz.ENC_NATURAL
+    op = bz.OP_KAT_ADD if enc == "kat" else bz.OP_ADD
+    A = bz.bz_sliced_pack(p, torch.from_numpy(a).cuda(), encoding=e)
+    B = bz.bz_sliced_pack(p, torch.from_numpy(b).cuda(), encoding=e)
+    for reps in (1, 2, 1000, 10001):
+        out = bz.bz_sliced_op(p, op, A, B, nsym, reps=reps)
+        got = bz.bz_sliced_unpack(p, out, nsym, encoding=e).cpu().numpy()
+        assert np.array_equal(got, (a.astype(np.int64) + reps * b.astype(np.int64)) % p), reps
+
+
+def test_sliced_op_errors(bz):
+    import torch
+    x = torch.zeros((1, 2, 1), dtype=torch.int32, device="cuda")
+    with pytest.raises(RuntimeError):
+        bz.bz_sliced_op(3, bz.OP_ISO_ADD, x, x, 20, reps=2)
+    with pytest.raises(RuntimeError):
+        bz.bz_sliced_op(7, bz.OP_KAT_ADD, x, x, 20)
+    with pytest.raises(RuntimeError):
+        bz.bz_sliced_op(3, bz.OP_ADD, x, x, 20, reps=0)
 
 
 def test_sliced_paper_examples(bz):
