@@ -128,6 +128,50 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device,
 const char *bz_status_str(int status);
 
 /* ---------------------------------------------------------------------- */
+/* Batches: many codes of different p, n and k in one call (one decomposition
+ * launch and one persistent enumeration launch for the whole batch).  Each
+ * code's d and stage trace are those of bz_min_distance_ex on that code with
+ * the same options (Algorithm 6 per code; the codes only share the GPU). */
+
+#define BZ_MAX_BATCH 65536
+
+typedef struct {
+    int32_t p, n, k;      /* as for bz_min_distance */
+    int32_t sweep_ops;    /* VALU operations per lane and task (the size of a unit of
+                             work), 0 = default 3000; chosen per (p, words) by the
+                             autotuner; results do not depend on it */
+    uint64_t g_offset;    /* byte offset of this code's k x n row-major generator in G */
+} bz_code;
+
+typedef struct {
+    int32_t check;           /* BZ_CHECK_STAGE (default) or BZ_CHECK_ROUND */
+    int32_t no_termination;  /* 1: every stage of every code (no L >= U exit) */
+    int32_t identity_skip;   /* 1 (default) */
+    int32_t blocks_per_cu;   /* enumeration grid: workgroups per compute unit; 0 = default */
+    uint64_t max_codewords;  /* per-code work limit; 0 = default (2^44) */
+    void *hip_stream;        /* NULL = library stream */
+    int32_t device;
+    int32_t wait_timeout_s;  /* the launch gives up (BZ_ERR_DEVICE) if no work appears for this
+                                long while codes remain; 0 = default (120) */
+    int32_t timing;          /* 1: fill the two fields below (HIP events on the stream) */
+    float decompose_ms;      /* out: decomposition launch */
+    float enum_ms;           /* out: enumeration launch */
+} bz_batch_options;
+
+void bz_default_batch_options(bz_batch_options *o);
+
+/* Minimum distance of ncodes codes.  G holds all generators (g_bytes bytes,
+ * host memory, or device memory when G_is_device); code i reads its k x n
+ * bytes at codes[i].g_offset.  out[i] and status_out[i] receive each code's
+ * result and status (the values bz_min_distance_ex returns: BZ_OK, VALUE,
+ * RANK, LIMIT).  Returns BZ_OK when the batch ran, BZ_ERR_ARG for an invalid
+ * batch or code descriptor (nothing runs), BZ_ERR_NOMEM, or BZ_ERR_DEVICE.
+ * The library keeps a batch workspace per device that grows to the largest
+ * batch seen (about 28 KB per code plus the packed rows). */
+int bz_min_distance_batch(int ncodes, const bz_code *codes, const uint8_t *G, uint64_t g_bytes, int G_is_device,
+                          bz_batch_options *o, bz_result *out, int32_t *status_out);
+
+/* ---------------------------------------------------------------------- */
 /* Bit-sliced F_p vector arithmetic on the device (Sec. 2; Tables 1-2 of the
  * paper time these additions).  Vectors of nsym symbols are stored sliced:
  * planes[v][b][w], b < r planes (r = 2 for F_3, 3 for F_7), w < ceil(nsym/32)

@@ -24,6 +24,7 @@ OP_ADD, OP_SUB, OP_DOUBLE, OP_ISO_ADD, OP_ISO_SUB, OP_KAT_ADD = range(6)
 ENC_NATURAL, ENC_KAT = 0, 1
 
 EXPORTS = ("bz_default_options", "bz_min_distance", "bz_min_distance_ex", "bz_status_str",
+           "bz_default_batch_options", "bz_min_distance_batch",
            "bz_sliced_pack", "bz_sliced_unpack", "bz_sliced_op")
 
 
@@ -47,6 +48,19 @@ class bz_options(ctypes.Structure):
                 ("hip_stream", ctypes.c_void_p), ("device", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("wait_timeout_s", ctypes.c_int32), ("trace_out", ctypes.POINTER(ctypes.c_uint64))]
+
+
+class bz_code(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int32), ("n", ctypes.c_int32), ("k", ctypes.c_int32),
+                ("sweep_ops", ctypes.c_int32), ("g_offset", ctypes.c_uint64)]
+
+
+class bz_batch_options(ctypes.Structure):
+    _fields_ = [("check", ctypes.c_int32), ("no_termination", ctypes.c_int32),
+                ("identity_skip", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("max_codewords", ctypes.c_uint64), ("hip_stream", ctypes.c_void_p),
+                ("device", ctypes.c_int32), ("wait_timeout_s", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("decompose_ms", ctypes.c_float), ("enum_ms", ctypes.c_float)]
 
 
 _lib = None
@@ -77,6 +91,11 @@ def lib():
         L.bz_sliced_op.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp,
                                    ctypes.c_int, vp]
         del u8p, u32p
+        L.bz_default_batch_options.argtypes = [ctypes.POINTER(bz_batch_options)]
+        L.bz_default_batch_options.restype = None
+        L.bz_min_distance_batch.argtypes = [ctypes.c_int, ctypes.POINTER(bz_code), vp, ctypes.c_uint64,
+                                            ctypes.c_int, ctypes.POINTER(bz_batch_options),
+                                            ctypes.POINTER(bz_result), ctypes.POINTER(ctypes.c_int32)]
         _lib = L
     return _lib
 
@@ -160,6 +179,85 @@ def min_distance(p, G, *, check="stage", no_termination=False, identity_skip=Tru
     out = result_dict(st, r, hist)
     if trace:
         out["trace"] = tr[:2 + r.n_stages].copy()
+    return out
+
+
+# ---------------------------------------------------------------- batches
+def bz_default_batch_options():
+    o = bz_batch_options()
+    lib().bz_default_batch_options(ctypes.byref(o))
+    return o
+
+
+def pack_batch(codes, device=None, align=16):
+    """codes: list of (p, G), G (k, n) uint8.  Returns (buffer, descriptors):
+    one contiguous uint8 buffer holding every generator at a 16-byte aligned
+    offset (a torch CUDA tensor when device is given, else numpy) and the
+    bz_code array (sweep_ops 0)."""
+    offs, total = [], 0
+    for _, G in codes:
+        offs.append(total)
+        total += -(-int(np.prod(G.shape)) // align) * align
+    host = np.zeros(max(total, align), dtype=np.uint8)
+    descs = (bz_code * len(codes))()
+    for i, ((p, G), off) in enumerate(zip(codes, offs)):
+        Gh = G.cpu().numpy() if hasattr(G, "cpu") else np.asarray(G, dtype=np.uint8)
+        k, n = Gh.shape
+        host[off:off + k * n] = Gh.reshape(-1)
+        descs[i].p, descs[i].n, descs[i].k, descs[i].sweep_ops, descs[i].g_offset = int(p), n, k, 0, off
+    if device is None:
+        return host, descs
+    import torch
+    return torch.from_numpy(host).to(device), descs
+
+
+def bz_min_distance_batch(buf, descs, options=None):
+    """Run a packed batch (see pack_batch).  Returns (status, [(status_i, bz_result_i)], options)."""
+    o = options if options is not None else bz_default_batch_options()
+    nc = len(descs)
+    out = (bz_result * max(nc, 1))()
+    sts = (ctypes.c_int32 * max(nc, 1))()
+    if hasattr(buf, "is_cuda") and buf.is_cuda:
+        if o.hip_stream is None:
+            o.hip_stream = _stream_of(buf)
+        o.device = buf.device.index or 0
+        st = lib().bz_min_distance_batch(nc, descs, ctypes.c_void_p(buf.data_ptr()), buf.numel(), 1,
+                                         ctypes.byref(o), out, sts)
+    else:
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        st = lib().bz_min_distance_batch(nc, descs, buf.ctypes.data_as(ctypes.c_void_p), buf.size, 0,
+                                         ctypes.byref(o), out, sts)
+    return st, [(int(sts[i]), out[i]) for i in range(nc)], o
+
+
+def min_distance_batch(codes, *, check="stage", no_termination=False, identity_skip=True, max_codewords=0,
+                       blocks_per_cu=0, sweep_ops=None, device=None, timing=False, wait_timeout_s=0):
+    """Convenience wrapper: one result dict per code (same keys as
+    min_distance).  sweep_ops: None, an int for every code, or a function
+    (p, W) -> int (e.g. the autotuner's table)."""
+    buf, descs = pack_batch(codes, device=device)
+    for i in range(len(codes)):
+        if sweep_ops is None:
+            continue
+        if callable(sweep_ops):
+            W = (descs[i].n - descs[i].k + 31) // 32 if identity_skip else (descs[i].n + 31) // 32
+            descs[i].sweep_ops = int(sweep_ops(descs[i].p, max(W, 1)))
+        else:
+            descs[i].sweep_ops = int(sweep_ops)
+    o = bz_default_batch_options()
+    o.check = CHECK_ROUND if check == "round" else CHECK_STAGE
+    o.no_termination = int(bool(no_termination))
+    o.identity_skip = int(bool(identity_skip))
+    o.max_codewords = int(max_codewords)
+    o.blocks_per_cu = int(blocks_per_cu)
+    o.timing = int(bool(timing))
+    o.wait_timeout_s = int(wait_timeout_s)
+    st, res, o = bz_min_distance_batch(buf, descs, o)
+    if st != OK:
+        raise RuntimeError(f"bz_min_distance_batch: {bz_status_str(st)}")
+    out = [result_dict(s_i, r_i) for s_i, r_i in res]
+    if timing:
+        return out, {"decompose_ms": o.decompose_ms, "enum_ms": o.enum_ms}
     return out
 
 

@@ -10,6 +10,7 @@
 
 #include <cstring>
 #include <mutex>
+#include <vector>
 
 #include "bz_kernels.hpp"
 
@@ -33,6 +34,15 @@ struct DevCtx {
     u64 *host_hist = nullptr;
     u64 (*host_trace)[4] = nullptr;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    // batch workspace, grown on demand and kept
+    size_t b_codes_cap = 0, b_rows_cap = 0, b_g_cap = 0;
+    CodeState *b_cs = nullptr;
+    BatchCode *b_codes = nullptr;
+    u32 *b_rows = nullptr;
+    uint8_t *b_g = nullptr;
+    BatchState *b_state = nullptr;
+    CodeResult *b_host_res = nullptr;
+    BatchState *b_host_state = nullptr;
     std::mutex mu;
 };
 
@@ -178,7 +188,8 @@ int check_args(int p, int n, int k, const void *G, const void *out) {
 }
 
 // Rebuild the trace from the per-stage minima and counts; returns the status.
-int finish(int p, int n, int k, int flags, u64 max_cw, const CodeResult &r, bz_result *out) {
+int finish(int p, int n, int k, int flags, u64 max_cw, const CodeResult &r, bz_result *out,
+           uint32_t sweep_ops = DEFAULT_SWEEP_OPS) {
     std::memset(out, 0, sizeof *out);
     out->m = r.m;
     for (int j = 0; j < r.m && j < BZ_MAX_M; j++) out->ranks[j] = r.ranks[j];
@@ -189,7 +200,7 @@ int finish(int p, int n, int k, int flags, u64 max_cw, const CodeResult &r, bz_r
     const int U0 = n - k + 1;
     if ((flags & FLAG_NO_TERM) || U0 > 1)
         ns = build_schedule(p, k, r.m, r.ranks, flags, max_cw ? max_cw : DEFAULT_LIMIT, 1, r.W, host_binom(), st,
-                            &complete);
+                            &complete, true, sweep_ops);
     if (ns != r.n_table) return BZ_ERR_DEVICE;
     int U = U0, term = -1;
     out->terminated_by = 2;
@@ -231,6 +242,73 @@ void launch_op(int op, int blocks, hipStream_t s, int nvec, int words, const u32
     case BZ_OP_ISO_SUB: op_kernel<P, BZ_OP_ISO_SUB><<<blocks, 256, 0, s>>>(nvec, words, a, b, out, reps); break;
     default: op_kernel<P, BZ_OP_KAT_ADD><<<blocks, 256, 0, s>>>(nvec, words, a, b, out, reps); break;
     }
+}
+
+// ---- batches
+template <int WMAX>
+int batch_grid_w(int cu, int bpc) {
+    static int max_bpc = -1;
+    if (max_bpc < 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, enum_batch_kernel<WMAX>, 256, 0) != hipSuccess ||
+            nb < 1)
+            return -1;
+        max_bpc = nb;
+    }
+    return cu * (bpc < max_bpc ? bpc : max_bpc);
+}
+
+int batch_grid(int wmax, int cu, int bpc) {
+    return wmax <= 2 ? batch_grid_w<2>(cu, bpc) : batch_grid_w<4>(cu, bpc);
+}
+
+// rows of one code: at most min(BZ_MAX_M, n - k + 1) information sets (each
+// after the first takes at least one new column), 64 row slots each
+u64 batch_row_words(int n, int k) {
+    const int m = n - k + 1 < BZ_MAX_M ? n - k + 1 : BZ_MAX_M;
+    return (u64)m * 64 * ROW_WORDS;
+}
+
+int grow_batch(DevCtx &c, size_t ncodes, size_t row_words, size_t g_bytes) {
+    if (ncodes > c.b_codes_cap) {
+        if (c.b_cs) {
+            hipFree(c.b_cs);
+            hipFree(c.b_codes);
+            hipHostFree(c.b_host_res);
+        }
+        c.b_cs = nullptr;
+        c.b_codes_cap = 0;
+        if (hipMalloc(&c.b_cs, sizeof(CodeState) * ncodes) != hipSuccess) return BZ_ERR_NOMEM;
+        if (hipMalloc(&c.b_codes, sizeof(BatchCode) * ncodes) != hipSuccess) return BZ_ERR_NOMEM;
+        if (hipHostMalloc(&c.b_host_res, sizeof(CodeResult) * ncodes, hipHostMallocDefault) != hipSuccess)
+            return BZ_ERR_NOMEM;
+        c.b_codes_cap = ncodes;
+    }
+    if (row_words > c.b_rows_cap) {
+        if (c.b_rows) hipFree(c.b_rows);
+        c.b_rows = nullptr;
+        c.b_rows_cap = 0;
+        if (hipMalloc(&c.b_rows, sizeof(u32) * row_words) != hipSuccess) return BZ_ERR_NOMEM;
+        c.b_rows_cap = row_words;
+    }
+    if (g_bytes > c.b_g_cap) {
+        if (c.b_g) hipFree(c.b_g);
+        c.b_g = nullptr;
+        c.b_g_cap = 0;
+        if (hipMalloc(&c.b_g, g_bytes) != hipSuccess) return BZ_ERR_NOMEM;
+        c.b_g_cap = g_bytes;
+    }
+    if (!c.b_state) {
+        if (hipMalloc(&c.b_state, sizeof(BatchState)) != hipSuccess) return BZ_ERR_NOMEM;
+        if (hipHostMalloc(&c.b_host_state, sizeof(BatchState), hipHostMallocDefault) != hipSuccess)
+            return BZ_ERR_NOMEM;
+    }
+    return BZ_OK;
+}
+
+__global__ void zero_batch_state(BatchState *bs) {
+    bs->remaining = 0;
+    bs->status = BZ_OK;
 }
 
 }  // namespace
@@ -302,7 +380,7 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, c
     a.U0 = n - k + 1;
     a.max_codewords = max_cw;
     a.grid = (uint32_t)grid;
-    a.lookahead = LOOKAHEAD;
+    a.sweep_ops = DEFAULT_SWEEP_OPS;
     a.timeout_ticks = timeout;
     if (o.timing) HIP_OK(hipEventRecord(c->ev[0], s));
     HIP_OK(p == 3 ? launch_decompose<3>(WF, Gd, c->cs, c->rows, a, s)
@@ -354,6 +432,109 @@ int bz_min_distance(int p, int n, int k, const uint8_t *G, bz_result *out) {
 }
 
 // ---------------------------------------------------------------- sliced ops
+void bz_default_batch_options(bz_batch_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->check = BZ_CHECK_STAGE;
+    o->identity_skip = 1;
+}
+
+int bz_min_distance_batch(int ncodes, const bz_code *codes, const uint8_t *G, uint64_t g_bytes, int G_is_device,
+                          bz_batch_options *opt, bz_result *out, int32_t *status_out) {
+    if (ncodes < 0 || ncodes > BZ_MAX_BATCH || (ncodes > 0 && (!codes || !G || !out || !status_out)))
+        return BZ_ERR_ARG;
+    bz_batch_options o;
+    if (opt) o = *opt;
+    else bz_default_batch_options(&o);
+    if (o.check != BZ_CHECK_STAGE && o.check != BZ_CHECK_ROUND) return BZ_ERR_ARG;
+    if (o.blocks_per_cu < 0 || o.blocks_per_cu > 64) return BZ_ERR_ARG;
+    if (ncodes == 0) return BZ_OK;
+    const int flags = (o.check == BZ_CHECK_ROUND ? FLAG_ROUND : 0) | (o.no_termination ? FLAG_NO_TERM : 0) |
+                      (o.identity_skip ? FLAG_SKIP : 0);
+    const u64 max_cw = o.max_codewords ? o.max_codewords : DEFAULT_LIMIT;
+    // validate every code and lay out its rows
+    std::vector<BatchCode> bc((size_t)ncodes);
+    u64 row_words = 0;
+    int wmax = 1;
+    for (int i = 0; i < ncodes; i++) {
+        const bz_code &cd = codes[i];
+        if (check_args(cd.p, cd.n, cd.k, G, out) != BZ_OK || cd.sweep_ops < 0) return BZ_ERR_ARG;
+        if (cd.g_offset > g_bytes || (u64)cd.k * (u64)cd.n > g_bytes - cd.g_offset) return BZ_ERR_ARG;
+        BatchCode &b = bc[(size_t)i];
+        b.g_offset = cd.g_offset;
+        b.row_offset = row_words;
+        b.max_codewords = max_cw;
+        b.p = cd.p;
+        b.n = cd.n;
+        b.k = cd.k;
+        b.flags = flags;
+        b.U0 = cd.n - cd.k + 1;
+        b.WF = (cd.n + 31) / 32;
+        b.W = o.identity_skip ? (cd.n - cd.k + 31) / 32 : b.WF;
+        if (b.W < 1) b.W = 1;
+        b.sweep_ops = cd.sweep_ops > 0 ? (uint32_t)cd.sweep_ops : DEFAULT_SWEEP_OPS;
+        if (b.W > wmax) wmax = b.W;
+        row_words += batch_row_words(cd.n, cd.k);
+    }
+    DevCtx *c = nullptr;
+    int st = get_ctx(o.device, &c);
+    if (st != BZ_OK) return st;
+    std::lock_guard<std::mutex> lk(c->mu);
+    HIP_OK(hipSetDevice(o.device));
+    hipStream_t s = o.hip_stream ? (hipStream_t)o.hip_stream : c->stream;
+    st = grow_batch(*c, (size_t)ncodes, (size_t)row_words, G_is_device ? 0 : (size_t)g_bytes);
+    if (st != BZ_OK) return st;
+    const int bpc = o.blocks_per_cu ? o.blocks_per_cu : 4;
+    const int grid = batch_grid(wmax, c->cu, bpc);
+    if (grid < 1) return BZ_ERR_DEVICE;
+    const u64 timeout = c->ticks_per_s * (u64)(o.wait_timeout_s > 0 ? o.wait_timeout_s : 120);
+    const uint8_t *Gd = G;
+    if (!G_is_device) {
+        HIP_OK(hipMemcpyAsync(c->b_g, G, (size_t)g_bytes, hipMemcpyHostToDevice, s));
+        Gd = c->b_g;
+    }
+    HIP_OK(hipMemcpyAsync(c->b_codes, bc.data(), sizeof(BatchCode) * (size_t)ncodes, hipMemcpyHostToDevice, s));
+    zero_batch_state<<<1, 1, 0, s>>>(c->b_state);
+    HIP_OK(hipGetLastError());
+    if (o.timing) HIP_OK(hipEventRecord(c->ev[0], s));
+    decompose_batch_kernel<<<ncodes, 64, 0, s>>>(Gd, c->b_codes, c->b_cs, c->b_rows, (uint32_t)grid, c->b_state);
+    HIP_OK(hipGetLastError());
+    if (o.timing) HIP_OK(hipEventRecord(c->ev[1], s));
+    {
+        CodeState *css = c->b_cs;
+        const BatchCode *cds = c->b_codes;
+        int nc = ncodes;
+        const u32 *rows = c->b_rows;
+        const u64 *bin = c->binom;
+        BatchState *bs = c->b_state;
+        u64 to = timeout;
+        void *args[] = {&css, &cds, &nc, &rows, &bin, &bs, &to};
+        if (wmax <= 2)
+            HIP_OK(hipLaunchCooperativeKernel((const void *)enum_batch_kernel<2>, dim3(grid), dim3(256), args, 0, s));
+        else
+            HIP_OK(hipLaunchCooperativeKernel((const void *)enum_batch_kernel<4>, dim3(grid), dim3(256), args, 0, s));
+    }
+    if (o.timing) HIP_OK(hipEventRecord(c->ev[2], s));
+    HIP_OK(hipMemcpy2DAsync(c->b_host_res, sizeof(CodeResult), &c->b_cs->res, sizeof(CodeState),
+                            sizeof(CodeResult), (size_t)ncodes, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipMemcpyAsync(c->b_host_state, c->b_state, sizeof(BatchState), hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    if (c->b_host_state->status != BZ_OK) return BZ_ERR_DEVICE;
+    for (int i = 0; i < ncodes; i++) {
+        const bz_code &cd = codes[i];
+        status_out[i] = finish(cd.p, cd.n, cd.k, flags, max_cw, c->b_host_res[i], &out[i], bc[(size_t)i].sweep_ops);
+    }
+    if (o.timing) {
+        HIP_OK(hipEventElapsedTime(&o.decompose_ms, c->ev[0], c->ev[1]));
+        HIP_OK(hipEventElapsedTime(&o.enum_ms, c->ev[1], c->ev[2]));
+        if (opt) {
+            opt->decompose_ms = o.decompose_ms;
+            opt->enum_ms = o.enum_ms;
+        }
+    }
+    return BZ_OK;
+}
+
 int bz_sliced_pack(int p, int enc, int nvec, int nsym, const uint8_t *sym, uint32_t *planes, void *stream) {
     if ((p != 3 && p != 7) || nvec < 0 || nsym < 1 || !sym || !planes) return BZ_ERR_ARG;
     if (enc != BZ_ENC_NATURAL && !(enc == BZ_ENC_KAT && p == 3)) return BZ_ERR_ARG;

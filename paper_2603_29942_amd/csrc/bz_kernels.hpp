@@ -62,9 +62,9 @@ __device__ __forceinline__ u32 pick(const u32 (&a)[N], int q) {
 struct RunArgs {
     int32_t n, k, flags, U0;
     u64 max_codewords;
-    uint32_t grid;  // workgroups of the enumeration launch
-    int32_t lookahead;
-    u64 timeout_ticks;  // wall_clock64() ticks a workgroup may wait for earlier stages
+    uint32_t grid;       // workgroups of the enumeration launch
+    uint32_t sweep_ops;  // VALU operations per lane and task (sizes the blocks of rows s)
+    u64 timeout_ticks;   // wall_clock64() ticks a workgroup may wait for earlier stages
 };
 
 // q-groups of a stage with g >= 3 computed by the 64 lanes of a wavefront
@@ -100,13 +100,24 @@ __device__ __forceinline__ u64 wave_qtable(int k, int g, u64 M, uint32_t cap, co
 // =====================================================================
 // Decomposition: one wavefront per code, lane i holds row i.
 // =====================================================================
+// LDS of one decomposition (a kernel declares it once and passes it down, so
+// that one kernel can hold several instantiations of decompose_code)
+struct DecompLDS {
+    __align__(16) uint8_t gl[BZ_MAX_K * BZ_MAX_N];
+    u64 binom[(BZ_MAX_K + 1) * 65];  // C(c, i) at [c * 65 + i], rows c <= k
+    int32_t sranks[BZ_MAX_M];
+    u64 s_cw[BZ_MAX_K], s_tasks[BZ_MAX_K];
+    uint32_t s_combos[BZ_MAX_K];
+};
+
+// One code on one wavefront (threads 0..63 of the workgroup).
 template <int P, int WF>
-__global__ __launch_bounds__(64) void decompose_kernel(const uint8_t *__restrict__ G, CodeState *cs,
-                                                       u32 *__restrict__ rows, RunArgs args) {
+__device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32 *__restrict__ rows,
+                               const RunArgs args, DecompLDS &lds) {
     constexpr int R = (P == 3) ? 2 : 3;
-    __shared__ __align__(16) uint8_t gl[BZ_MAX_K * BZ_MAX_N];
-    __shared__ u64 binom[(BZ_MAX_K + 1) * 65];  // C(c, i) at [c * 65 + i], rows c <= k
-    __shared__ int32_t sranks[BZ_MAX_M];
+    uint8_t *gl = lds.gl;
+    u64 *binom = lds.binom;
+    int32_t *sranks = lds.sranks;
     const int lane = threadIdx.x;
     const int n = args.n, k = args.k, flags = args.flags;
     CodeResult &res = cs->res;
@@ -350,8 +361,8 @@ __global__ __launch_bounds__(64) void decompose_kernel(const uint8_t *__restrict
     // -- schedule (the stage order of Alg. 6): one round g per lane, a
     //    saturating scan for the codewords before each round, then one stage per
     //    lane; the same table as build_schedule
-    __shared__ u64 s_cw[BZ_MAX_K], s_tasks[BZ_MAX_K];
-    __shared__ uint32_t s_combos[BZ_MAX_K];
+    u64 *s_cw = lds.s_cw, *s_tasks = lds.s_tasks;
+    uint32_t *s_combos = lds.s_combos;
     int ns = 0, complete = 1;
     if (status == BZ_OK && ((flags & FLAG_NO_TERM) != 0 || args.U0 > 1)) {
         const int g = lane + 1;
@@ -384,7 +395,7 @@ __global__ __launch_bounds__(64) void decompose_kernel(const uint8_t *__restrict
         // task counts of the rounds g >= 3 that the table reaches, one wave-parallel pass each
         const int last_g = (ns + m - 1) / m;
         for (int gg = 3; gg <= last_g; gg++) {
-            const u64 t = wave_qtable(k, gg, s_combos[gg - 1], sweep_cap_for(P, W), binom, nullptr);
+            const u64 t = wave_qtable(k, gg, s_combos[gg - 1], sweep_cap_for(P, W, args.sweep_ops), binom, nullptr);
             if (t >= (1ull << 62)) {
                 ns = min(ns, (gg - 1) * m);
                 complete = 0;
@@ -399,7 +410,7 @@ __global__ __launch_bounds__(64) void decompose_kernel(const uint8_t *__restrict
         __syncthreads();
     }
     {
-        const uint32_t cap = sweep_cap_for(P, W);
+        const uint32_t cap = sweep_cap_for(P, W, args.sweep_ops);
         for (int s = lane; s < ns; s += 64) {
             const int g = s / m + 1, j = s % m + 1;
             int L = 0;
@@ -445,6 +456,13 @@ __global__ __launch_bounds__(64) void decompose_kernel(const uint8_t *__restrict
         res.n_table = ns;
         res.table_complete = complete;
     }
+}
+
+template <int P, int WF>
+__global__ __launch_bounds__(64) void decompose_kernel(const uint8_t *__restrict__ G, CodeState *cs,
+                                                       u32 *__restrict__ rows, RunArgs args) {
+    __shared__ DecompLDS lds;
+    decompose_code<P, WF>(G, cs, rows, args, lds);
 }
 
 // =====================================================================
@@ -674,7 +692,9 @@ __device__ u64 run_base_task(const StageDesc &sd, int k, int j, const u32 *__res
 __device__ void run_checker(CodeState *cs, const StageDesc *sdesc, int ns) {
     const int lane = __lane_id();
     for (int guard = 0; guard <= 2 * BZ_MAX_STAGES; guard++) {
-        u64 st = uni64(rd_atomic(&cs->res.ctl));
+        u64 st = 0;
+        if (lane == 0) st = rd_atomic(&cs->res.ctl);
+        st = uni64(st);
         const int c = ctl_checked(st);
         if (c >= ns || ctl_term(st) >= 0) return;
         const int s = c + lane;
@@ -843,6 +863,232 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
         __syncthreads();  // qtab and red_* are rewritten by the next stage
     }
     if (tracing && threadIdx.x == 0) atomicMax((unsigned long long *)&cs->trace[1][1], (unsigned long long)wall_clock64());
+}
+
+// =====================================================================
+// Batches: many codes of different p, n, k in one decomposition launch and
+// one persistent enumeration launch
+// =====================================================================
+
+// One workgroup (one wavefront) per code.  Also publishes the code's first
+// claim word and counts it in BatchState::remaining.
+__global__ __launch_bounds__(64) void decompose_batch_kernel(const uint8_t *__restrict__ G,
+                                                             const BatchCode *__restrict__ codes, CodeState *css,
+                                                             u32 *__restrict__ rows, uint32_t grid, BatchState *bs) {
+    __shared__ DecompLDS lds;
+    const BatchCode bc = codes[blockIdx.x];
+    CodeState *cs = css + blockIdx.x;
+    RunArgs a;
+    a.n = bc.n;
+    a.k = bc.k;
+    a.flags = bc.flags;
+    a.U0 = bc.U0;
+    a.max_codewords = bc.max_codewords;
+    a.grid = grid;
+    a.sweep_ops = bc.sweep_ops;
+    a.timeout_ticks = 0;
+    const uint8_t *g = G + bc.g_offset;
+    u32 *r = rows + bc.row_offset;
+    if (bc.p == 3) {
+        switch (bc.WF) {
+        case 1: decompose_code<3, 1>(g, cs, r, a, lds); break;
+        case 2: decompose_code<3, 2>(g, cs, r, a, lds); break;
+        case 3: decompose_code<3, 3>(g, cs, r, a, lds); break;
+        default: decompose_code<3, 4>(g, cs, r, a, lds); break;
+        }
+    } else {
+        switch (bc.WF) {
+        case 1: decompose_code<7, 1>(g, cs, r, a, lds); break;
+        case 2: decompose_code<7, 2>(g, cs, r, a, lds); break;
+        case 3: decompose_code<7, 3>(g, cs, r, a, lds); break;
+        default: decompose_code<7, 4>(g, cs, r, a, lds); break;
+        }
+    }
+    if (threadIdx.x == 0) {
+        // lane 0 wrote the status, the table size and stage 0 itself
+        const bool work = cs->res.status == BZ_OK && cs->res.n_table > 0;
+        cs->claim = work ? claim_make(0, cs->stages[0].parts) : 0ull;
+        if (work) atomicAdd(&bs->remaining, 1u);
+    }
+}
+
+// The tiles of one part of a stage: tile_of(r, part, parts, s) for r = 0, 1, ...
+template <int P, int W>
+__device__ u64 run_part(const StageDesc &sd, int s, uint32_t part, int k, const u32 *__restrict__ rows,
+                        const u64 *sbin, const u64 *__restrict__ gbin, const QEntry *qtab, u32 woff, u32 cap,
+                        u32 &lmin) {
+    const int wid = threadIdx.x >> 6;
+    const int g = uni(sd.g), j = uni(sd.j - 1), nq = k - 2 - (g - 3);
+    const u64 tiles = uni64(sd.tiles), tasks = uni64(sd.tasks);
+    const uint32_t parts = uni(sd.parts);
+    u64 cnt = 0;
+    for (u64 r = 0;; r++) {
+        const u64 tile = tile_of(r, part, parts, s);
+        if (tile >= tiles) break;
+        const u64 task = tile * WAVES_PER_GROUP + (u64)wid;
+        if (task >= tasks) continue;
+        if (g >= 3)
+            cnt += run_base_task<P, W, false>(sd, k, j, rows, sbin, gbin, qtab, nq, task, lmin, nullptr, woff, cap);
+        else
+            cnt += run_small_task<P, W, false>(g, k, j, rows, task, lmin, nullptr, woff, cap);
+    }
+    return cnt;
+}
+
+// After the last part of stage s of a code: U takes the stage minimum, the
+// L >= U test (Alg. 6) ends the code or publishes the next stage's claim word.
+// Run by one whole wavefront; only lane 0 touches memory.
+__device__ void batch_check(CodeState *cs, int s, const StageDesc &sd, BatchState *bs) {
+    if (__lane_id() != 0) return;
+    const u64 st = rd_atomic(&cs->res.ctl);
+    const int U = min((int)ctl_U(st), rd_atomic(&cs->res.stage_min[s]));
+    const int ns = cs->res.n_table;
+    const bool stop = sd.check && sd.L >= U;
+    const bool last = stop || s + 1 >= ns;
+    __hip_atomic_exchange(&cs->res.ctl, stop ? ctl_make(s, s, U) : ctl_make(s + 1, -1, U), __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_AGENT);
+    drain_vmem();  // U is in place before the next stage can be claimed and checked
+    __hip_atomic_exchange(&cs->claim, last ? 0ull : claim_make(s + 1, cs->stages[s + 1].parts), __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_AGENT);
+    if (last) __hip_atomic_fetch_sub(&bs->remaining, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Persistent, cooperative: every workgroup repeatedly claims one part of the
+// current stage of some code (wave 0 scans 64 codes per step for an open claim
+// word, starting after the code it took last), runs it, reports minimum and
+// count, and the workgroup that finishes a stage's last part checks it.  Exits
+// when no code has stages left.  Codes of every (p, W <= WMAX) share the launch.
+template <int WMAX>
+__global__ __launch_bounds__(256) void enum_batch_kernel(CodeState *css, const BatchCode *__restrict__ codes,
+                                                         int ncodes, const u32 *__restrict__ rows,
+                                                         const u64 *__restrict__ gbin, BatchState *bs,
+                                                         u64 timeout_ticks) {
+    __shared__ u64 sbin[BZ_MAX_K * BIN_I];
+    __shared__ QEntry qtab[BZ_MAX_K];
+    __shared__ u32 red_min[WAVES_PER_GROUP];
+    __shared__ u64 red_cnt[WAVES_PER_GROUP];
+    __shared__ int s_code, s_stage;
+    __shared__ uint32_t s_part;
+    const int lane = __lane_id();
+    const int wid = threadIdx.x >> 6;
+    for (int i = threadIdx.x; i < BZ_MAX_K * BIN_I; i += blockDim.x) sbin[i] = gbin[(i / BIN_I) * 65 + i % BIN_I];
+    uint32_t scan = (uint32_t)((u64)blockIdx.x * (u64)ncodes / gridDim.x);
+    __syncthreads();
+    for (;;) {
+        if (wid == 0) {
+            int code = -1, stage = 0;
+            uint32_t part = 0;
+            u64 t0 = 0;
+            for (uint32_t it = 0;; it++) {
+                int rem = 0, bst = 0;
+                if (lane == 0) {
+                    rem = (int)ld_poll(&bs->remaining);
+                    bst = ld_poll(&bs->status);
+                }
+                if (uni(rem) == 0 || uni(bst) != BZ_OK) break;
+                bool got = false;
+                for (int base = 0; base < ncodes && !got; base += 64) {
+                    const bool in = base + lane < ncodes;
+                    const int c = (int)((scan + (uint32_t)(base + lane)) % (uint32_t)ncodes);
+                    bool open = false;
+                    if (in) {
+                        const u64 cw = ld_poll(&css[c].claim);
+                        open = claim_stage(cw) >= 0 && claim_next(cw) < claim_parts(cw);
+                    }
+                    u64 cands = __ballot(open);
+                    while (cands) {
+                        const int l = __builtin_ctzll(cands);
+                        cands &= cands - 1;
+                        const int cc = __shfl(c, l);
+                        u64 old = 0;
+                        if (lane == 0)
+                            old = __hip_atomic_fetch_add(&css[cc].claim, 1ull, __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                        old = uni64(old);
+                        if (claim_stage(old) >= 0 && claim_next(old) < claim_parts(old)) {
+                            code = cc;
+                            stage = claim_stage(old);
+                            part = claim_next(old);
+                            got = true;
+                            break;
+                        }
+                    }
+                }
+                if (got) break;
+                if ((it & 255u) == 255u) {
+                    u64 now = 0;
+                    if (lane == 0) now = (u64)wall_clock64();
+                    now = uni64(now);
+                    if (t0 == 0) {
+                        t0 = now;
+                    } else if (now - t0 > timeout_ticks) {
+                        if (lane == 0)
+                            __hip_atomic_store(&bs->status, (int)BZ_ERR_DEVICE, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                        break;
+                    }
+                }
+                __builtin_amdgcn_s_sleep(8);
+            }
+            if (code >= 0) scan = (uint32_t)code + 1u;
+            if (lane == 0) {
+                s_code = code;
+                s_stage = stage;
+                s_part = part;
+            }
+        }
+        __syncthreads();
+        const int code = s_code;
+        if (code < 0) break;
+        const int s = s_stage;
+        const uint32_t part = s_part;
+        CodeState *cs = css + code;
+        const int p = uni(codes[code].p), W = uni(codes[code].W), k = uni(codes[code].k);
+        const int n = uni(codes[code].n);
+        const u64 row_off = uni64(codes[code].row_offset);
+        const StageDesc sd = cs->stages[s];
+        if (wid == 0 && sd.g >= 3) wave_qtable(k, sd.g, sd.coef_combos, sd.sweep_cap, gbin, qtab);
+        __syncthreads();
+        const u32 woff = (cs->flags & FLAG_SKIP) ? (u32)sd.g : 0u;
+        const u32 cap = (u32)n;
+        const u32 *r = rows + row_off;
+        u32 lmin = BIG;
+        u64 cnt = 0;
+        if (p == 3) {
+            if (W == 1) cnt = run_part<3, 1>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin);
+            if constexpr (WMAX >= 2) if (W == 2) cnt = run_part<3, 2>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin);
+            if constexpr (WMAX >= 3) if (W == 3) cnt = run_part<3, 3>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin);
+            if constexpr (WMAX >= 4) if (W == 4) cnt = run_part<3, 4>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin);
+        } else {
+            if (W == 1) cnt = run_part<7, 1>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin);
+            if constexpr (WMAX >= 2) if (W == 2) cnt = run_part<7, 2>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin);
+            if constexpr (WMAX >= 3) if (W == 3) cnt = run_part<7, 3>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin);
+            if constexpr (WMAX >= 4) if (W == 4) cnt = run_part<7, 4>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin);
+        }
+        for (int off = 32; off >= 1; off >>= 1) lmin = min(lmin, (u32)__shfl_xor((int)lmin, off));
+        if (lane == 0) {
+            red_min[wid] = lmin;
+            red_cnt[wid] = cnt;
+        }
+        __syncthreads();
+        if (wid == 0) {
+            uint32_t done = 0;
+            if (lane == 0) {
+                u32 bm = red_min[0];
+                u64 bc = red_cnt[0];
+                for (int w = 1; w < WAVES_PER_GROUP; w++) {
+                    bm = min(bm, red_min[w]);
+                    bc += red_cnt[w];
+                }
+                if (bm != BIG) atomicMin(&cs->res.stage_min[s], (int)(bm + woff));
+                atomicAdd((unsigned long long *)&cs->res.stage_count[s], (unsigned long long)bc);
+                drain_vmem();  // minimum and count performed before done counts this part
+                done = __hip_atomic_fetch_add(&cs->stage_done[s], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+            }
+            if (uni(done) == sd.parts) batch_check(cs, s, sd, bs);
+        }
+        __syncthreads();  // qtab, red_* and s_* are rewritten by the next claim
+    }
 }
 
 // =====================================================================

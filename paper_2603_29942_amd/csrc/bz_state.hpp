@@ -89,6 +89,32 @@ struct CodeState {
     // last start
     u64 trace[BZ_MAX_STAGES + 2][4];
     StageDesc stages[BZ_MAX_STAGES];
+    // batched runs: the stage whose parts workgroups claim (see claim_make)
+    u64 claim;
+};
+
+// Claim word of a code in a batch: stage + 1 (bits 48-63, 0 = nothing to
+// claim), parts of that stage (bits 24-47) and the next part to hand out
+// (bits 0-23, advanced by atomic add; values >= parts are failed claims).
+BZ_HD u64 claim_make(int stage, uint32_t parts) { return ((u64)(uint32_t)(stage + 1) << 48) | ((u64)parts << 24); }
+BZ_HD int claim_stage(u64 c) { return (int)(c >> 48) - 1; }
+BZ_HD uint32_t claim_parts(u64 c) { return (uint32_t)(c >> 24) & 0xffffffu; }
+BZ_HD uint32_t claim_next(u64 c) { return (uint32_t)c & 0xffffffu; }
+
+// One code of a batch, filled by the host.
+struct BatchCode {
+    u64 g_offset;    // byte offset of its k x n generator in the batch's G
+    u64 row_offset;  // word offset of its packed rows
+    u64 max_codewords;
+    int32_t p, n, k, flags;
+    int32_t U0, WF, W;    // words per plane of G, and processed per combination
+    uint32_t sweep_ops;  // VALU operations per lane and task
+};
+
+// Batch-wide state: codes with stages left, and the error flag of a time-out.
+struct BatchState {
+    uint32_t remaining;
+    int32_t status;
 };
 
 enum { FLAG_ROUND = 1, FLAG_NO_TERM = 2, FLAG_SKIP = 4, FLAG_HIST = 8, FLAG_TRACE = 16 };
@@ -138,15 +164,13 @@ BZ_HD int bound_c(int g, int k, int kj) {
     return v > 0 ? v : 0;
 }
 
-// Target (s, L) steps per lane in one task: about BZ_SWEEP_OPS VALU operations, from
+// Target (s, L) steps per lane in one task: about `ops` VALU operations, from
 // the per-step cost of the completions (F_3: two prefixes, add and subtract;
 // F_7: six prefixes, three rotations, add and subtract).
-#ifndef BZ_SWEEP_OPS
-#define BZ_SWEEP_OPS 3000u
-#endif
-BZ_HD uint32_t sweep_cap_for(int p, int W) {
+constexpr uint32_t DEFAULT_SWEEP_OPS = 3000;
+BZ_HD uint32_t sweep_cap_for(int p, int W, uint32_t ops = DEFAULT_SWEEP_OPS) {
     const uint32_t per = (p == 3) ? 2u * (6u * (uint32_t)W + 1u) : 6u * (25u * (uint32_t)W + 3u);
-    const uint32_t cap = (uint32_t)(BZ_SWEEP_OPS) / per;
+    const uint32_t cap = (ops ? ops : DEFAULT_SWEEP_OPS) / per;
     return cap < 4u ? 4u : cap;
 }
 
@@ -291,11 +315,11 @@ BZ_HD u64 small_stage_tasks(int k, int g) {
 // the schedule reaches (k, m).  binom[c*65+i] = C(c, i) for c, i <= 64.
 BZ_HD int build_schedule(int p, int k, int m, const int32_t *ranks, int flags, u64 max_codewords,
                          uint32_t grid, int W, const u64 *binom, StageDesc *st, int *complete,
-                         bool count_tasks = true) {
+                         bool count_tasks = true, uint32_t sweep_ops = DEFAULT_SWEEP_OPS) {
     int ns = 0;
     u64 cum = 0;
     *complete = 1;
-    const uint32_t cap = sweep_cap_for(p, W);
+    const uint32_t cap = sweep_cap_for(p, W, sweep_ops);
     for (int g = 1; g <= k; g++) {
         const u64 cw = round_codewords(p, k, g, binom);
         u64 tasks;

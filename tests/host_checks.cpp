@@ -200,7 +200,7 @@ static void check_schedule() {
 // saturating scan of the codewords of the rounds, then one stage per lane);
 // replayed here, it gives the same table as build_schedule.
 static int lane_parallel_schedule(int p, int k, int m, const int *ranks, int flags, u64 max_cw, uint32_t grid,
-                                  int W, StageDesc *st, int *complete) {
+                                  int W, StageDesc *st, int *complete, uint32_t sweep_ops) {
     u64 cw[64], inc[64], tasks[64];
     uint32_t combos[64];
     int js[64];
@@ -224,7 +224,7 @@ static int lane_parallel_schedule(int p, int k, int m, const int *ranks, int fla
             *complete = 0;
             break;
         }
-    const uint32_t cap = sweep_cap_for(p, W);
+    const uint32_t cap = sweep_cap_for(p, W, sweep_ops);
     const int last_g = (ns + m - 1) / m;
     for (int g = 3; g <= last_g; g++) {
         const u64 t = fill_qtable(k, g, combos[g - 1], cap, BINOM, nullptr);
@@ -282,8 +282,9 @@ static void check_parallel_schedule() {
         const int W = 1 + (int)(rng() % 4);
         static StageDesc a[BZ_MAX_STAGES], b[BZ_MAX_STAGES];
         int ca = -1, cb = -1;
-        const int na = build_schedule(p, k, m, ranks.data(), flags, max_cw, grid, W, BINOM, a, &ca);
-        const int nb = lane_parallel_schedule(p, k, m, ranks.data(), flags, max_cw, grid, W, b, &cb);
+        const uint32_t ops = (it % 3 == 0) ? DEFAULT_SWEEP_OPS : 500u + (uint32_t)(rng() % 20000);
+        const int na = build_schedule(p, k, m, ranks.data(), flags, max_cw, grid, W, BINOM, a, &ca, true, ops);
+        const int nb = lane_parallel_schedule(p, k, m, ranks.data(), flags, max_cw, grid, W, b, &cb, ops);
         CHECK(na == nb && ca == cb);
         if (na != nb) {
             std::printf("  p=%d k=%d m=%d max=%llu: %d vs %d\n", p, k, m, (unsigned long long)max_cw, na, nb);

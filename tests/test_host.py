@@ -58,15 +58,19 @@ def test_struct_layout(bzlib, tmp_path):
     src = os.path.join(str(tmp_path), "layout.c")
     with open(src, "w") as f:
         f.write('#include <stdio.h>\n#include <stddef.h>\n#include "bz.h"\n'
-                'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(bz_stage), sizeof(bz_result),'
-                ' offsetof(bz_result, stages), offsetof(bz_result, codewords_total), sizeof(bz_options),'
-                ' offsetof(bz_options, max_codewords), offsetof(bz_options, trace_out)); return 0;}\n')
+                'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\\n", sizeof(bz_stage),'
+                ' sizeof(bz_result), offsetof(bz_result, stages), offsetof(bz_result, codewords_total),'
+                ' sizeof(bz_options), offsetof(bz_options, max_codewords), offsetof(bz_options, trace_out),'
+                ' sizeof(bz_code), offsetof(bz_code, g_offset), sizeof(bz_batch_options),'
+                ' offsetof(bz_batch_options, hip_stream), offsetof(bz_batch_options, enum_ms)); return 0;}\n')
     exe = os.path.join(str(tmp_path), "layout")
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
     c_vals = [int(x) for x in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
     py_vals = [ctypes.sizeof(bzlib.bz_stage), ctypes.sizeof(bzlib.bz_result), bzlib.bz_result.stages.offset,
                bzlib.bz_result.codewords_total.offset, ctypes.sizeof(bzlib.bz_options),
-               bzlib.bz_options.max_codewords.offset, bzlib.bz_options.trace_out.offset]
+               bzlib.bz_options.max_codewords.offset, bzlib.bz_options.trace_out.offset,
+               ctypes.sizeof(bzlib.bz_code), bzlib.bz_code.g_offset.offset, ctypes.sizeof(bzlib.bz_batch_options),
+               bzlib.bz_batch_options.hip_stream.offset, bzlib.bz_batch_options.enum_ms.offset]
     assert c_vals == py_vals
 
 
@@ -88,6 +92,28 @@ def test_argument_errors_need_no_device(bzlib):
     o.check = 5
     st, _ = bzlib.bz_min_distance_ex(3, G, o)
     assert st == bzlib.ERR_ARG
+
+
+def test_batch_argument_errors_need_no_device(bzlib):
+    """An invalid code descriptor rejects the whole batch before any device work."""
+    G = np.zeros((4, 10), dtype=np.uint8)
+    ok = [(3, G), (7, G)]
+    for bad in [(5, G), (3, np.zeros((11, 10), dtype=np.uint8)), (7, np.zeros((65, 70), dtype=np.uint8))]:
+        buf, descs = bzlib.pack_batch(ok + [bad])
+        st, _, _ = bzlib.bz_min_distance_batch(buf, descs)
+        assert st == bzlib.ERR_ARG
+    buf, descs = bzlib.pack_batch(ok)
+    descs[1].g_offset = buf.size - 8  # generator runs past the buffer
+    st, _, _ = bzlib.bz_min_distance_batch(buf, descs)
+    assert st == bzlib.ERR_ARG
+    buf, descs = bzlib.pack_batch(ok)
+    o = bzlib.bz_default_batch_options()
+    assert (o.check, o.no_termination, o.identity_skip, o.max_codewords) == (0, 0, 1, 0)
+    o.check = 9
+    st, _, _ = bzlib.bz_min_distance_batch(buf, descs, o)
+    assert st == bzlib.ERR_ARG
+    st, res, _ = bzlib.bz_min_distance_batch(buf, (bzlib.bz_code * 0)())
+    assert st == bzlib.OK and res == []
     o = bzlib.bz_default_options()
     o.histograms = 1  # without a buffer
     st, _ = bzlib.bz_min_distance_ex(3, G, o)
