@@ -128,3 +128,21 @@ def test_batch_workspace_reuse(bz):
         same(r1[i], r3[i], f"code {i} repeat")
     for i in range(len(small)):
         same(r2[i], r1[10 + i], f"code {10 + i} in the small batch")
+
+
+def test_autotuner_table(bz, tmp_path):
+    """The autotuner picks one candidate per (p, W) group and a grid shape;
+    running with its table gives the same results as the defaults."""
+    import json
+    from paper_2603_29942_amd import autotune
+    cs = synth.batch_codes(7, count=24)
+    t = autotune.tune(cs, reps=1, sweep_candidates=(1500, 6000), bpc_candidates=(2, 4), log=say)
+    assert t["sweep_ops"] and set(t["sweep_ops"].values()) <= {1500, 6000}
+    assert t["blocks_per_cu"] in (2, 4)
+    path = tmp_path / "table.json"
+    path.write_text(json.dumps(t))
+    fn, bpc = autotune.load(str(path))
+    tuned = bz.min_distance_batch(cs, sweep_ops=fn, blocks_per_cu=bpc, wait_timeout_s=30)
+    plain = bz.min_distance_batch(cs, wait_timeout_s=30)
+    for i, (a, b) in enumerate(zip(tuned, plain)):
+        same(a, b, f"code {i} tuned")
