@@ -172,6 +172,32 @@ int bz_min_distance_batch(int ncodes, const bz_code *codes, const uint8_t *G, ui
                           bz_batch_options *o, bz_result *out, int32_t *status_out);
 
 /* ---------------------------------------------------------------------- */
+/* Work predictor: a 4 -> 64 -> 64 -> 1 FP32 multilayer perceptron with ReLU
+ * hidden layers that maps features of a code to log10 of the combinations the
+ * method evaluates on it.  It is only used to order and admit work (the
+ * stage-by-stage L >= U test still decides d).  Not from the paper.
+ *
+ * Parameters: BZ_MLP_PARAMS floats, W1[64][4], b1[64], W2[64][64], b2[64],
+ * w3[64], b3 (row-major).  x: n x 4 features, row-major.  All pointers are
+ * device pointers; calls are asynchronous on `stream`.  Sums run in a fixed
+ * order, so results are reproducible bit for bit.  BZ_ERR_ARG for NULL or
+ * negative sizes. */
+#define BZ_MLP_PARAMS 4545
+
+/* y[n] = network(x); cache (n x 128 floats, or NULL) receives the hidden
+ * activations the backward pass needs. */
+int bz_mlp_forward(const float *params, const float *x, int n, float *y, float *cache, void *stream);
+/* Gradient of L = mean_i (y_i - target_i)^2 with respect to the parameters
+ * (grad[BZ_MLP_PARAMS]), from y and cache of bz_mlp_forward; dz is scratch of
+ * n x 129 floats; loss (1 float, or NULL) receives L. */
+int bz_mlp_backward(const float *params, const float *x, const float *target, int n, const float *y,
+                    const float *cache, float *dz, float *grad, float *loss, void *stream);
+/* One Adam step (bias-corrected, step >= 1) on params with moment buffers m, v
+ * (BZ_MLP_PARAMS floats each, zero before step 1). */
+int bz_mlp_adam(float *params, const float *grad, float *m, float *v, int step, float lr, float beta1, float beta2,
+                float eps, void *stream);
+
+/* ---------------------------------------------------------------------- */
 /* Bit-sliced F_p vector arithmetic on the device (Sec. 2; Tables 1-2 of the
  * paper time these additions).  Vectors of nsym symbols are stored sliced:
  * planes[v][b][w], b < r planes (r = 2 for F_3, 3 for F_7), w < ceil(nsym/32)

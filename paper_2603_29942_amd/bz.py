@@ -25,6 +25,7 @@ ENC_NATURAL, ENC_KAT = 0, 1
 
 EXPORTS = ("bz_default_options", "bz_min_distance", "bz_min_distance_ex", "bz_status_str",
            "bz_default_batch_options", "bz_min_distance_batch",
+           "bz_mlp_forward", "bz_mlp_backward", "bz_mlp_adam",
            "bz_sliced_pack", "bz_sliced_unpack", "bz_sliced_op")
 
 
@@ -96,6 +97,11 @@ def lib():
         L.bz_min_distance_batch.argtypes = [ctypes.c_int, ctypes.POINTER(bz_code), vp, ctypes.c_uint64,
                                             ctypes.c_int, ctypes.POINTER(bz_batch_options),
                                             ctypes.POINTER(bz_result), ctypes.POINTER(ctypes.c_int32)]
+        fp = ctypes.c_void_p
+        L.bz_mlp_forward.argtypes = [fp, fp, ctypes.c_int, fp, fp, vp]
+        L.bz_mlp_backward.argtypes = [fp, fp, fp, ctypes.c_int, fp, fp, fp, fp, fp, vp]
+        L.bz_mlp_adam.argtypes = [fp, fp, fp, fp, ctypes.c_int, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                                  ctypes.c_float, vp]
         _lib = L
     return _lib
 
@@ -259,6 +265,35 @@ def min_distance_batch(codes, *, check="stage", no_termination=False, identity_s
     if timing:
         return out, {"decompose_ms": o.decompose_ms, "enum_ms": o.enum_ms}
     return out
+
+
+# ---------------------------------------------------------------- work predictor network
+MLP_PARAMS = 4545
+
+
+def _check(st, name):
+    if st != OK:
+        raise RuntimeError(f"{name}: {bz_status_str(st)}")
+
+
+def bz_mlp_forward(params, x, cache=None):
+    """params: float32 CUDA tensor (4545,); x: (n, 4) float32 CUDA tensor.
+    Returns y (n,); fills cache (n, 128) when given."""
+    import torch
+    n = x.shape[0]
+    y = torch.empty(n, dtype=torch.float32, device=x.device)
+    _check(lib().bz_mlp_forward(_ptr(params), _ptr(x), n, _ptr(y), _ptr(cache), _stream_of(x)), "bz_mlp_forward")
+    return y
+
+
+def bz_mlp_backward(params, x, t, y, cache, dz, grad, loss=None):
+    _check(lib().bz_mlp_backward(_ptr(params), _ptr(x), _ptr(t), x.shape[0], _ptr(y), _ptr(cache), _ptr(dz),
+                                 _ptr(grad), _ptr(loss), _stream_of(x)), "bz_mlp_backward")
+
+
+def bz_mlp_adam(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(lib().bz_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(step), float(lr), float(beta1),
+                             float(beta2), float(eps), _stream_of(params)), "bz_mlp_adam")
 
 
 # ---------------------------------------------------------------- sliced vectors

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "bz_kernels.hpp"
+#include "bz_mlp.hpp"
 
 using namespace bz;
 
@@ -533,6 +534,31 @@ int bz_min_distance_batch(int ncodes, const bz_code *codes, const uint8_t *G, ui
         }
     }
     return BZ_OK;
+}
+
+int bz_mlp_forward(const float *params, const float *x, int n, float *y, float *cache, void *stream) {
+    if (!params || n < 0 || (n > 0 && (!x || !y))) return BZ_ERR_ARG;
+    if (n == 0) return BZ_OK;
+    mlp_forward_kernel<<<(n + 255) / 256, 256, 0, (hipStream_t)stream>>>(params, x, n, y, cache);
+    return hipGetLastError() == hipSuccess ? BZ_OK : BZ_ERR_DEVICE;
+}
+
+int bz_mlp_backward(const float *params, const float *x, const float *target, int n, const float *y,
+                    const float *cache, float *dz, float *grad, float *loss, void *stream) {
+    if (!params || !x || !target || n < 1 || !y || !cache || !dz || !grad) return BZ_ERR_ARG;
+    hipStream_t s = (hipStream_t)stream;
+    mlp_delta_kernel<<<(n + 255) / 256, 256, 0, s>>>(params, target, n, y, cache, dz);
+    mlp_grad_kernel<<<(MLP_NPARAM + 255) / 256, 256, 0, s>>>(x, n, cache, dz, grad);
+    if (loss) mlp_loss_kernel<<<1, 64, 0, s>>>(y, target, n, loss);
+    return hipGetLastError() == hipSuccess ? BZ_OK : BZ_ERR_DEVICE;
+}
+
+int bz_mlp_adam(float *params, const float *grad, float *m, float *v, int step, float lr, float beta1, float beta2,
+                float eps, void *stream) {
+    if (!params || !grad || !m || !v || step < 1) return BZ_ERR_ARG;
+    mlp_adam_kernel<<<(MLP_NPARAM + 255) / 256, 256, 0, (hipStream_t)stream>>>(params, grad, m, v, step, lr, beta1,
+                                                                              beta2, eps);
+    return hipGetLastError() == hipSuccess ? BZ_OK : BZ_ERR_DEVICE;
 }
 
 int bz_sliced_pack(int p, int enc, int nvec, int nsym, const uint8_t *sym, uint32_t *planes, void *stream) {
