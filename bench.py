@@ -173,8 +173,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4],
-                    help="1-3: one code per step (plain path); 4: the 512-code mixed batch per step")
+    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5],
+                    help="1-3: one code per step (plain path); 4: the 512-code mixed batch per step; "
+                         "5: serving under Poisson arrivals")
+    ap.add_argument("--requests", type=int, default=2000, help="config 5: requests per policy")
     ap.add_argument("--blocks-per-cu", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -209,6 +211,9 @@ def main():
     cfg = args.config
     if cfg == 4:
         print(json.dumps(bench_batch(args)), flush=True)
+        return
+    if cfg == 5:
+        print(json.dumps(bench_serve(args)), flush=True)
         return
     p, n, k = synth.CONFIGS[cfg]
     K, Wm = args.steps, args.warmup
@@ -308,6 +313,69 @@ def main():
 def autotune_table():
     from paper_2603_29942_amd import autotune
     return autotune.load()
+
+
+def bench_serve(args):
+    """Serving: Poisson arrivals of random F_3 / F_7 codes (k uniform in
+    [10, 40], F_7 k <= 28, n = 2k) at 0.7 x the measured batched capacity
+    (jobs/s, frozen before the run), through the continuous-batching server,
+    once in arrival order and once shortest-predicted-work first.  Latency is
+    arrival to result as seen by the polling loop."""
+    import numpy as np
+    import torch
+    from paper_2603_29942_amd import bz, predictor, synth
+    dev = torch.device("cuda:0")
+    # capacity: the batched path on 256 codes of the same distribution
+    cal = [(p, G) for _, p, G in synth.serving_requests(99, 256, 1.0)]
+    bz.min_distance_batch(cal[:32], device=dev)
+    torch.cuda.synchronize()
+    tc = time.perf_counter()
+    bz.min_distance_batch(cal, device=dev)
+    cap = len(cal) / (time.perf_counter() - tc)
+    lam = 0.7 * cap
+    N = args.requests
+    reqs = synth.serving_requests(0, N, lam)
+    params = predictor.load()[0]
+    out = {}
+    ds = {}
+    for policy in ("fifo", "predicted"):
+        srv = bz.Server(policy=policy, mlp_params=params if policy == "predicted" else None, slots=1024, max_n=80)
+        for t, (_, p, G) in enumerate(synth.serving_requests(98, 16, 1.0)):
+            srv.submit(p, G, 10 ** 9 + t)
+        got = 0
+        while got < 16:
+            got += len(srv.poll())
+        lat, cw, dvals = np.zeros(N), 0, [0] * N
+        t0 = time.perf_counter()
+        i, done = 0, 0
+        while done < N:
+            now = time.perf_counter() - t0
+            while i < N and reqs[i][0] <= now:
+                srv.submit(reqs[i][1], reqs[i][2], i)
+                i += 1
+            for tag, r in srv.poll():
+                lat[tag] = time.perf_counter() - t0 - reqs[tag][0]
+                cw += r["codewords_total"]
+                dvals[tag] = r["d"]
+                done += 1
+        span = time.perf_counter() - t0
+        st = srv.stats()
+        srv.stop()
+        ds[policy] = dvals
+        out[policy] = {"latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
+                                      "p99": float(np.percentile(lat, 99) * 1e3),
+                                      "mean": float(lat.mean() * 1e3)},
+                       "jobs_per_s": N / span, "codewords_per_s": cw / span, "seconds": span, **st}
+    return {
+        "metric": "time-to-d under Poisson arrivals (continuous batching), p50/p99",
+        "value": out["predicted"]["latency_ms"]["p50"], "unit": "ms", "n_gpus": 1, "steps": N, "warmup": 16,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
+        "config": {"workload": f"{N} requests, Poisson arrivals at {lam:.1f}/s = 0.7 x measured batched capacity "
+                               f"{cap:.1f} jobs/s; p uniform in {{3,7}}, k uniform in [10,40] (F_7 k <= 28), n = 2k",
+                   "slots": 1024, "arrival_rate_per_s": lam, "capacity_jobs_per_s": cap},
+        "policies": out,
+        "d_equal_between_policies": ds["fifo"] == ds["predicted"],
+    }
 
 
 def bench_batch(args):

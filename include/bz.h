@@ -172,6 +172,53 @@ int bz_min_distance_batch(int ncodes, const bz_code *codes, const uint8_t *G, ui
                           bz_batch_options *o, bz_result *out, int32_t *status_out);
 
 /* ---------------------------------------------------------------------- */
+/* Serving with continuous batching.  Requests (one code each) are queued by
+ * bz_server_submit and run by bz_server_poll, which the caller calls in its
+ * loop: a round admits queued requests into free slots (the device memory of
+ * one code each: admission by memory), decomposes them, orders all active
+ * codes (arrival order, or shortest predicted work first with the predictor
+ * network) and runs them together in one persistent launch.  Requests that
+ * arrive while a round runs make it yield at the next part boundary and join
+ * the next round with the unfinished codes, which keep their progress.  Codes
+ * that end are returned by the next poll, also while their round runs.  Each
+ * result equals bz_min_distance_ex's on that code with the same options
+ * (Algorithm 6 per code; the ordering only changes when it ends).  One server
+ * per thread of control: calls on one server must not overlap. */
+
+typedef struct bz_server bz_server;
+enum { BZ_SERVE_FIFO = 0, BZ_SERVE_PREDICTED = 1 };
+
+typedef struct {
+    int32_t slots;            /* codes resident on the device at once, 0 -> 1024 */
+    int32_t policy;           /* BZ_SERVE_FIFO or BZ_SERVE_PREDICTED */
+    const float *mlp_params;  /* host, BZ_MLP_PARAMS floats: the network for BZ_SERVE_PREDICTED */
+    int32_t check;            /* BZ_CHECK_STAGE (default) or BZ_CHECK_ROUND */
+    int32_t identity_skip;    /* 1 (default) */
+    uint64_t max_codewords;   /* per-code work limit, 0 = default (2^44) */
+    int32_t blocks_per_cu;    /* persistent launch: workgroups per compute unit, 0 = default */
+    int32_t device;
+    int32_t wait_timeout_s;   /* as in bz_batch_options */
+    int32_t max_n;            /* largest n accepted, 0 = 128; sizes each slot */
+} bz_server_options;
+
+void bz_default_server_options(bz_server_options *o);
+/* Allocates the slots (about 28 KB + 4 KB x min(128, max_n) + 64 max_n bytes each). */
+int bz_server_start(const bz_server_options *o, bz_server **out);
+/* Queues one code (G: host, k x n row-major, copied); tag is returned with its result.
+ * BZ_ERR_ARG for an invalid shape or n > max_n; the code's own errors (VALUE,
+ * RANK, LIMIT) come back as its status. */
+int bz_server_submit(bz_server *s, int p, int n, int k, const uint8_t *G, uint64_t tag);
+/* Progresses the server without blocking on running work; returns up to
+ * max_out finished codes (tags, results, statuses, *n_out) and, in
+ * *in_flight (may be NULL), the requests queued or running. */
+int bz_server_poll(bz_server *s, int max_out, uint64_t *tags, bz_result *results, int32_t *statuses, int *n_out,
+                   int *in_flight);
+/* Rounds launched and rounds asked to yield so far. */
+int bz_server_stats(bz_server *s, uint64_t *rounds, uint64_t *yields);
+/* Ends the running round at its next part boundary, waits for it and frees everything. */
+int bz_server_stop(bz_server *s);
+
+/* ---------------------------------------------------------------------- */
 /* Work predictor: a 4 -> 64 -> 64 -> 1 FP32 multilayer perceptron with ReLU
  * hidden layers that maps features of a code to log10 of the combinations the
  * method evaluates on it.  It is only used to order and admit work (the

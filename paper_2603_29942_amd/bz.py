@@ -26,6 +26,7 @@ ENC_NATURAL, ENC_KAT = 0, 1
 EXPORTS = ("bz_default_options", "bz_min_distance", "bz_min_distance_ex", "bz_status_str",
            "bz_default_batch_options", "bz_min_distance_batch",
            "bz_mlp_forward", "bz_mlp_backward", "bz_mlp_adam",
+           "bz_default_server_options", "bz_server_start", "bz_server_submit", "bz_server_poll", "bz_server_stats", "bz_server_stop",
            "bz_sliced_pack", "bz_sliced_unpack", "bz_sliced_op")
 
 
@@ -63,6 +64,15 @@ class bz_batch_options(ctypes.Structure):
                 ("device", ctypes.c_int32), ("wait_timeout_s", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("decompose_ms", ctypes.c_float), ("enum_ms", ctypes.c_float)]
 
+
+class bz_server_options(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int32), ("policy", ctypes.c_int32), ("mlp_params", ctypes.c_void_p),
+                ("check", ctypes.c_int32), ("identity_skip", ctypes.c_int32), ("max_codewords", ctypes.c_uint64),
+                ("blocks_per_cu", ctypes.c_int32), ("device", ctypes.c_int32), ("wait_timeout_s", ctypes.c_int32),
+                ("max_n", ctypes.c_int32)]
+
+
+SERVE_FIFO, SERVE_PREDICTED = 0, 1
 
 _lib = None
 
@@ -102,6 +112,15 @@ def lib():
         L.bz_mlp_backward.argtypes = [fp, fp, fp, ctypes.c_int, fp, fp, fp, fp, fp, vp]
         L.bz_mlp_adam.argtypes = [fp, fp, fp, fp, ctypes.c_int, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                                   ctypes.c_float, vp]
+        L.bz_default_server_options.argtypes = [ctypes.POINTER(bz_server_options)]
+        L.bz_default_server_options.restype = None
+        L.bz_server_start.argtypes = [ctypes.POINTER(bz_server_options), ctypes.POINTER(ctypes.c_void_p)]
+        L.bz_server_submit.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_uint64]
+        L.bz_server_poll.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(bz_result),
+                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int),
+                                     ctypes.POINTER(ctypes.c_int)]
+        L.bz_server_stop.argtypes = [vp]
+        L.bz_server_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
         _lib = L
     return _lib
 
@@ -265,6 +284,67 @@ def min_distance_batch(codes, *, check="stage", no_termination=False, identity_s
     if timing:
         return out, {"decompose_ms": o.decompose_ms, "enum_ms": o.enum_ms}
     return out
+
+
+# ---------------------------------------------------------------- serving
+class Server:
+    """Continuous-batching server (see bz_server_* in include/bz.h).
+
+    submit(p, G, tag) queues a code (host numpy uint8 (k, n)); poll() advances
+    the server and returns [(tag, result dict)] of the codes that finished."""
+
+    def __init__(self, policy="fifo", mlp_params=None, slots=1024, max_n=0, check="stage", identity_skip=True,
+                 max_codewords=0, blocks_per_cu=0, wait_timeout_s=0, max_out=1024):
+        o = bz_server_options()
+        lib().bz_default_server_options(ctypes.byref(o))
+        o.slots = int(slots)
+        o.policy = SERVE_PREDICTED if policy == "predicted" else SERVE_FIFO
+        self._mlp = None
+        if mlp_params is not None:
+            self._mlp = np.ascontiguousarray(mlp_params, dtype=np.float32)
+            o.mlp_params = self._mlp.ctypes.data_as(ctypes.c_void_p)
+        o.check = CHECK_ROUND if check == "round" else CHECK_STAGE
+        o.identity_skip = int(bool(identity_skip))
+        o.max_codewords = int(max_codewords)
+        o.blocks_per_cu = int(blocks_per_cu)
+        o.wait_timeout_s = int(wait_timeout_s)
+        o.max_n = int(max_n)
+        h = ctypes.c_void_p()
+        _check(lib().bz_server_start(ctypes.byref(o), ctypes.byref(h)), "bz_server_start")
+        self._h = h
+        self._max = int(max_out)
+        self._tags = (ctypes.c_uint64 * self._max)()
+        self._res = (bz_result * self._max)()
+        self._sts = (ctypes.c_int32 * self._max)()
+
+    def submit(self, p, G, tag):
+        G = np.ascontiguousarray(G, dtype=np.uint8)
+        k, n = G.shape
+        _check(lib().bz_server_submit(self._h, int(p), n, k, G.ctypes.data_as(ctypes.c_void_p), int(tag)),
+               "bz_server_submit")
+
+    def poll(self):
+        n_out, in_flight = ctypes.c_int(), ctypes.c_int()
+        _check(lib().bz_server_poll(self._h, self._max, self._tags, self._res, self._sts, ctypes.byref(n_out),
+                                    ctypes.byref(in_flight)), "bz_server_poll")
+        self.in_flight = in_flight.value
+        return [(int(self._tags[i]), result_dict(int(self._sts[i]), self._res[i])) for i in range(n_out.value)]
+
+    def stats(self):
+        r, y = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().bz_server_stats(self._h, ctypes.byref(r), ctypes.byref(y)), "bz_server_stats")
+        return {"rounds": r.value, "yields": y.value}
+
+    def stop(self):
+        if self._h:
+            lib().bz_server_stop(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.stop()
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------- work predictor network

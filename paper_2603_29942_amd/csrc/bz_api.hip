@@ -8,7 +8,9 @@
 // compact result block back and rebuilds the stage trace from it.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
+#include <deque>
 #include <mutex>
 #include <vector>
 
@@ -498,7 +500,8 @@ int bz_min_distance_batch(int ncodes, const bz_code *codes, const uint8_t *G, ui
     zero_batch_state<<<1, 1, 0, s>>>(c->b_state);
     HIP_OK(hipGetLastError());
     if (o.timing) HIP_OK(hipEventRecord(c->ev[0], s));
-    decompose_batch_kernel<<<ncodes, 64, 0, s>>>(Gd, c->b_codes, c->b_cs, c->b_rows, (uint32_t)grid, c->b_state);
+    decompose_batch_kernel<<<ncodes, 64, 0, s>>>(Gd, c->b_codes, c->b_cs, c->b_rows, (uint32_t)grid, c->b_state,
+                                                nullptr, nullptr);
     HIP_OK(hipGetLastError());
     if (o.timing) HIP_OK(hipEventRecord(c->ev[1], s));
     {
@@ -509,7 +512,10 @@ int bz_min_distance_batch(int ncodes, const bz_code *codes, const uint8_t *G, ui
         const u64 *bin = c->binom;
         BatchState *bs = c->b_state;
         u64 to = timeout;
-        void *args[] = {&css, &cds, &nc, &rows, &bin, &bs, &to};
+        const int32_t *order = nullptr;
+        const uint32_t *yield = nullptr;
+        uint32_t *done = nullptr;
+        void *args[] = {&css, &cds, &nc, &rows, &bin, &bs, &to, &order, &yield, &done};
         if (wmax <= 2)
             HIP_OK(hipLaunchCooperativeKernel((const void *)enum_batch_kernel<2>, dim3(grid), dim3(256), args, 0, s));
         else
@@ -597,6 +603,367 @@ int bz_sliced_op(int p, int op, int nvec, int nsym, const uint32_t *a, const uin
     if (p == 3) launch_op<3>(op, blocks, (hipStream_t)stream, nvec, words, a, b, out, reps);
     else launch_op<7>(op, blocks, (hipStream_t)stream, nvec, words, a, b, out, reps);
     return hipGetLastError() == hipSuccess ? BZ_OK : BZ_ERR_DEVICE;
+}
+
+}  // extern "C"
+
+// =====================================================================
+// Serving: continuous batching over a yielding persistent launch
+// =====================================================================
+//
+// Requests queue on the host.  Each round the host admits queued requests
+// into free slots (memory: one CodeState, packed rows and a generator per
+// slot), decomposes the new slots, orders every active slot (arrival order, or
+// shortest predicted work first with the work-predictor network) and launches
+// the persistent enumeration over them.  Codes that end raise a flag in mapped
+// host memory, so their results are collected while the launch runs.  When new
+// requests wait, the host raises the yield flag: workgroups finish the part
+// they hold and exit, every code keeping its progress in its claim word, and
+// the next round continues all of them together with the new ones.  All data
+// that a launch reads was written before it started (kernel boundaries), and
+// during a launch only atomics cross workgroups.
+
+struct bz_server {
+    int dev = 0;
+    DevCtx *c = nullptr;
+    hipStream_t run = nullptr, copy = nullptr;  // the launches; result copies beside them
+    hipEvent_t round_done = nullptr;
+    bz_server_options o{};
+    int slots = 0, grid = 0, decomp_grid = 0, flags = 0;
+    u64 max_cw = 0, timeout = 0, rows_per_slot = 0, g_per_slot = 0;
+    // device
+    CodeState *cs = nullptr;
+    BatchCode *codes = nullptr;
+    u32 *rows = nullptr;
+    uint8_t *g = nullptr;
+    BatchState *bs = nullptr;
+    int32_t *order_d = nullptr, *new_d = nullptr;
+    float *feat_d = nullptr, *pred_d = nullptr, *mlp_d = nullptr;
+    // pinned host
+    BatchCode *codes_h = nullptr;
+    uint8_t *g_h = nullptr;
+    uint32_t *yield_h = nullptr, *done_h = nullptr;  // mapped host memory
+    uint32_t *yield_dev = nullptr, *done_dev = nullptr;  // the same, as device addresses
+    CodeResult *res_h = nullptr;
+    int32_t *order_h = nullptr, *new_h = nullptr;
+    float *pred_h = nullptr;
+    // bookkeeping
+    struct Req {
+        int p, n, k;
+        u64 tag;
+        std::vector<uint8_t> G;
+    };
+    std::deque<Req> queue;
+    struct Slot {
+        int state = 0;  // 0 free, 1 active
+        int p = 0, n = 0, k = 0;
+        u64 tag = 0;
+        float prio = 0;
+        u64 seq = 0;
+    };
+    std::vector<Slot> slot;
+    u64 seq = 0;
+    u64 rounds = 0, yields = 0;
+    bool running = false;
+    int wmax = 2;
+    std::mutex mu;
+};
+
+namespace {
+
+void server_free(bz_server *s) {
+    if (s->run) hipStreamSynchronize(s->run);
+    if (s->copy) hipStreamSynchronize(s->copy);
+    for (void *p : {(void *)s->cs, (void *)s->codes, (void *)s->rows, (void *)s->g, (void *)s->bs,
+                    (void *)s->order_d, (void *)s->new_d, (void *)s->feat_d, (void *)s->pred_d, (void *)s->mlp_d})
+        if (p) hipFree(p);
+    for (void *p : {(void *)s->codes_h, (void *)s->g_h, (void *)s->yield_h, (void *)s->done_h, (void *)s->res_h,
+                    (void *)s->order_h, (void *)s->new_h, (void *)s->pred_h})
+        if (p) hipHostFree(p);
+    if (s->round_done) hipEventDestroy(s->round_done);
+    if (s->run) hipStreamDestroy(s->run);
+    if (s->copy) hipStreamDestroy(s->copy);
+    delete s;
+}
+
+// Harvest codes that ended: copy their result blocks back and rebuild their traces.
+int server_harvest(bz_server *s, int max_out, uint64_t *tags, bz_result *results, int32_t *statuses, int *n_out) {
+    std::vector<int> done;
+    for (int i = 0; i < s->slots && (int)done.size() < max_out - *n_out; i++)
+        if (s->slot[(size_t)i].state == 1 && __atomic_load_n(&s->done_h[i], __ATOMIC_ACQUIRE) != 0) done.push_back(i);
+    if (done.empty()) return BZ_OK;
+    for (int i : done)
+        HIP_OK(hipMemcpyAsync(&s->res_h[i], &s->cs[i].res, sizeof(CodeResult), hipMemcpyDeviceToHost, s->copy));
+    HIP_OK(hipStreamSynchronize(s->copy));
+    for (int i : done) {
+        bz_server::Slot &sl = s->slot[(size_t)i];
+        const int k = *n_out;
+        tags[k] = sl.tag;
+        statuses[k] = finish(sl.p, sl.n, sl.k, s->flags, s->max_cw, s->res_h[i], &results[k],
+                             s->codes_h[i].sweep_ops);
+        (*n_out)++;
+        sl.state = 0;
+        __atomic_store_n(&s->done_h[i], 0u, __ATOMIC_RELEASE);
+    }
+    return BZ_OK;
+}
+
+template <int WMAX>
+hipError_t server_launch(bz_server *s, int nactive) {
+    CodeState *css = s->cs;
+    const BatchCode *cds = s->codes;
+    int nc = nactive;
+    const u32 *rows = s->rows;
+    const u64 *bin = s->c->binom;
+    BatchState *bs = s->bs;
+    u64 to = s->timeout;
+    const int32_t *order = s->order_d;
+    const uint32_t *yield = s->yield_dev;
+    uint32_t *done = s->done_dev;
+    void *args[] = {&css, &cds, &nc, &rows, &bin, &bs, &to, &order, &yield, &done};
+    return hipLaunchCooperativeKernel((const void *)enum_batch_kernel<WMAX>, dim3(s->grid), dim3(256), args, 0,
+                                      s->run);
+}
+
+// Admit queued requests into free slots, decompose them, order the active
+// slots and start the next round.
+int server_round(bz_server *s) {
+    std::vector<int> fresh;
+    for (int i = 0; i < s->slots && !s->queue.empty(); i++) {
+        bz_server::Slot &sl = s->slot[(size_t)i];
+        if (sl.state != 0) continue;
+        bz_server::Req r = std::move(s->queue.front());
+        s->queue.pop_front();
+        sl.state = 1;
+        sl.p = r.p;
+        sl.n = r.n;
+        sl.k = r.k;
+        sl.tag = r.tag;
+        sl.seq = s->seq++;
+        std::memcpy(s->g_h + (size_t)i * s->g_per_slot, r.G.data(), r.G.size());
+        BatchCode &b = s->codes_h[i];
+        b.g_offset = (u64)i * s->g_per_slot;
+        b.row_offset = (u64)i * s->rows_per_slot;
+        b.max_codewords = s->max_cw;
+        b.p = r.p;
+        b.n = r.n;
+        b.k = r.k;
+        b.flags = s->flags;
+        b.U0 = r.n - r.k + 1;
+        b.WF = (r.n + 31) / 32;
+        b.W = s->o.identity_skip ? (r.n - r.k + 31) / 32 : b.WF;
+        if (b.W < 1) b.W = 1;
+        b.sweep_ops = DEFAULT_SWEEP_OPS;
+        s->new_h[fresh.size()] = i;
+        fresh.push_back(i);
+    }
+    if (!fresh.empty()) {
+        const int nf = (int)fresh.size();
+        for (int i : fresh)
+            HIP_OK(hipMemcpyAsync(s->g + (size_t)i * s->g_per_slot, s->g_h + (size_t)i * s->g_per_slot,
+                                  (size_t)s->codes_h[i].n * s->codes_h[i].k, hipMemcpyHostToDevice, s->run));
+        HIP_OK(hipMemcpyAsync(s->codes, s->codes_h, sizeof(BatchCode) * (size_t)s->slots, hipMemcpyHostToDevice,
+                              s->run));
+        HIP_OK(hipMemcpyAsync(s->new_d, s->new_h, sizeof(int32_t) * (size_t)nf, hipMemcpyHostToDevice, s->run));
+        decompose_batch_kernel<<<nf, 64, 0, s->run>>>(s->g, s->codes, s->cs, s->rows, (uint32_t)s->decomp_grid, s->bs,
+                                                      s->new_d, s->done_dev);
+        HIP_OK(hipGetLastError());
+        if (s->o.policy == BZ_SERVE_PREDICTED) {
+            features_kernel<<<(nf + 63) / 64, 64, 0, s->run>>>(s->cs, s->new_d, nf, s->feat_d);
+            mlp_forward_kernel<<<(nf + 255) / 256, 256, 0, s->run>>>(s->mlp_d, s->feat_d, nf, s->pred_d, nullptr);
+            HIP_OK(hipGetLastError());
+            HIP_OK(hipMemcpyAsync(s->pred_h, s->pred_d, sizeof(float) * (size_t)nf, hipMemcpyDeviceToHost, s->run));
+            HIP_OK(hipStreamSynchronize(s->run));
+            for (int j = 0; j < nf; j++) s->slot[(size_t)fresh[(size_t)j]].prio = s->pred_h[j];
+        }
+    }
+    // active slots in priority order; the predictor only orders work
+    std::vector<int> act;
+    int wmax = 1;
+    for (int i = 0; i < s->slots; i++)
+        if (s->slot[(size_t)i].state == 1) {
+            act.push_back(i);
+            if (s->codes_h[i].W > wmax) wmax = s->codes_h[i].W;
+        }
+    if (act.empty()) return BZ_OK;
+    if (s->o.policy == BZ_SERVE_PREDICTED)
+        std::stable_sort(act.begin(), act.end(), [&](int a, int b) {
+            return s->slot[(size_t)a].prio < s->slot[(size_t)b].prio;
+        });
+    else
+        std::stable_sort(act.begin(), act.end(),
+                         [&](int a, int b) { return s->slot[(size_t)a].seq < s->slot[(size_t)b].seq; });
+    for (size_t j = 0; j < act.size(); j++) s->order_h[j] = act[j];
+    HIP_OK(hipMemcpyAsync(s->order_d, s->order_h, sizeof(int32_t) * act.size(), hipMemcpyHostToDevice, s->run));
+    __atomic_store_n(s->yield_h, 0u, __ATOMIC_RELEASE);
+    HIP_OK(wmax <= 2 && s->wmax <= 2 ? server_launch<2>(s, (int)act.size()) : server_launch<4>(s, (int)act.size()));
+    HIP_OK(hipEventRecord(s->round_done, s->run));
+    s->running = true;
+    s->rounds++;
+    return BZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void bz_default_server_options(bz_server_options *o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof *o);
+    o->slots = 1024;
+    o->check = BZ_CHECK_STAGE;
+    o->identity_skip = 1;
+}
+
+int bz_server_start(const bz_server_options *opt, bz_server **out) {
+    if (!out) return BZ_ERR_ARG;
+    *out = nullptr;
+    bz_server_options o;
+    if (opt) o = *opt;
+    else bz_default_server_options(&o);
+    if (o.slots == 0) o.slots = 1024;
+    if (o.slots < 1 || o.slots > BZ_MAX_BATCH || (o.policy != BZ_SERVE_FIFO && o.policy != BZ_SERVE_PREDICTED))
+        return BZ_ERR_ARG;
+    if (o.policy == BZ_SERVE_PREDICTED && !o.mlp_params) return BZ_ERR_ARG;
+    if (o.check != BZ_CHECK_STAGE && o.check != BZ_CHECK_ROUND) return BZ_ERR_ARG;
+    if (o.blocks_per_cu < 0 || o.blocks_per_cu > 64 || o.max_n < 0 || o.max_n > BZ_MAX_N) return BZ_ERR_ARG;
+    DevCtx *c = nullptr;
+    int st = get_ctx(o.device, &c);
+    if (st != BZ_OK) return st;
+    HIP_OK(hipSetDevice(o.device));
+    bz_server *s = new bz_server();
+    s->dev = o.device;
+    s->c = c;
+    s->o = o;
+    s->slots = o.slots;
+    s->flags = (o.check == BZ_CHECK_ROUND ? FLAG_ROUND : 0) | (o.identity_skip ? FLAG_SKIP : 0);
+    s->max_cw = o.max_codewords ? o.max_codewords : DEFAULT_LIMIT;
+    s->timeout = c->ticks_per_s * (u64)(o.wait_timeout_s > 0 ? o.wait_timeout_s : 120);
+    const int max_n = o.max_n ? o.max_n : BZ_MAX_N;
+    s->wmax = (max_n + 31) / 32 <= 2 ? 2 : 4;
+    s->rows_per_slot = batch_row_words(max_n, 1);
+    s->g_per_slot = (u64)(((max_n * BZ_MAX_K) + 255) / 256 * 256);
+    s->grid = batch_grid(s->wmax, c->cu, o.blocks_per_cu ? o.blocks_per_cu : 4);
+    s->decomp_grid = s->grid * 8;  // smaller parts: a yield waits for at most one short part
+    s->slot.resize((size_t)s->slots);
+    const size_t ns = (size_t)s->slots;
+    bool ok = s->grid > 0 && hipStreamCreateWithFlags(&s->run, hipStreamNonBlocking) == hipSuccess &&
+              hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&s->round_done, hipEventDisableTiming) == hipSuccess &&
+              hipMalloc(&s->cs, sizeof(CodeState) * ns) == hipSuccess &&
+              hipMalloc(&s->codes, sizeof(BatchCode) * ns) == hipSuccess &&
+              hipMalloc(&s->rows, sizeof(u32) * s->rows_per_slot * ns) == hipSuccess &&
+              hipMalloc(&s->g, s->g_per_slot * ns) == hipSuccess && hipMalloc(&s->bs, sizeof(BatchState)) == hipSuccess &&
+              hipMalloc(&s->order_d, sizeof(int32_t) * ns) == hipSuccess &&
+              hipMalloc(&s->new_d, sizeof(int32_t) * ns) == hipSuccess &&
+              hipMalloc(&s->feat_d, sizeof(float) * 4 * ns) == hipSuccess &&
+              hipMalloc(&s->pred_d, sizeof(float) * ns) == hipSuccess &&
+              hipMalloc(&s->mlp_d, sizeof(float) * MLP_NPARAM) == hipSuccess &&
+              hipHostMalloc(&s->codes_h, sizeof(BatchCode) * ns, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&s->g_h, s->g_per_slot * ns, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&s->yield_h, sizeof(uint32_t), hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
+              hipHostMalloc(&s->done_h, sizeof(uint32_t) * ns, hipHostMallocMapped | hipHostMallocCoherent) ==
+                  hipSuccess &&
+              hipHostMalloc(&s->res_h, sizeof(CodeResult) * ns, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&s->order_h, sizeof(int32_t) * ns, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&s->new_h, sizeof(int32_t) * ns, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&s->pred_h, sizeof(float) * ns, hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
+        server_free(s);
+        return BZ_ERR_NOMEM;
+    }
+    if (hipHostGetDevicePointer((void **)&s->yield_dev, s->yield_h, 0) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&s->done_dev, s->done_h, 0) != hipSuccess) {
+        server_free(s);
+        return BZ_ERR_DEVICE;
+    }
+    *s->yield_h = 0;
+    std::memset(s->done_h, 0, sizeof(uint32_t) * ns);
+    zero_batch_state<<<1, 1, 0, s->run>>>(s->bs);
+    if (o.mlp_params &&
+        hipMemcpyAsync(s->mlp_d, o.mlp_params, sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice, s->run) != hipSuccess) {
+        server_free(s);
+        return BZ_ERR_DEVICE;
+    }
+    if (hipStreamSynchronize(s->run) != hipSuccess) {
+        server_free(s);
+        return BZ_ERR_DEVICE;
+    }
+    *out = s;
+    return BZ_OK;
+}
+
+int bz_server_submit(bz_server *s, int p, int n, int k, const uint8_t *G, uint64_t tag) {
+    if (!s) return BZ_ERR_ARG;
+    const int st = check_args(p, n, k, G, G);
+    if (st != BZ_OK) return st;
+    const int max_n = s->o.max_n ? s->o.max_n : BZ_MAX_N;
+    if (n > max_n) return BZ_ERR_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    bz_server::Req r;
+    r.p = p;
+    r.n = n;
+    r.k = k;
+    r.tag = tag;
+    r.G.assign(G, G + (size_t)n * k);
+    s->queue.push_back(std::move(r));
+    return BZ_OK;
+}
+
+int bz_server_poll(bz_server *s, int max_out, uint64_t *tags, bz_result *results, int32_t *statuses, int *n_out,
+                   int *in_flight) {
+    if (!s || max_out < 0 || !n_out || (max_out > 0 && (!tags || !results || !statuses))) return BZ_ERR_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    HIP_OK(hipSetDevice(s->dev));
+    *n_out = 0;
+    int st = server_harvest(s, max_out, tags, results, statuses, n_out);
+    if (st != BZ_OK) return st;
+    if (s->running) {
+        const hipError_t q = hipEventQuery(s->round_done);
+        if (q == hipSuccess) {
+            s->running = false;
+        } else if (q != hipErrorNotReady) {
+            return BZ_ERR_DEVICE;
+        } else if (!s->queue.empty()) {
+            bool free_slot = false;
+            for (const auto &sl : s->slot) free_slot |= sl.state == 0;
+            // new work is waiting and fits: let the round end at the next part boundary
+            if (free_slot && __atomic_exchange_n(s->yield_h, 1u, __ATOMIC_ACQ_REL) == 0u) s->yields++;
+        }
+    }
+    if (!s->running) {
+        BatchState bsh;
+        HIP_OK(hipMemcpy(&bsh, s->bs, sizeof bsh, hipMemcpyDeviceToHost));
+        if (bsh.status != BZ_OK) return BZ_ERR_DEVICE;
+        st = server_harvest(s, max_out, tags, results, statuses, n_out);
+        if (st != BZ_OK) return st;
+        st = server_round(s);
+        if (st != BZ_OK) return st;
+    }
+    if (in_flight) {
+        int act = 0;
+        for (const auto &sl : s->slot) act += sl.state;
+        *in_flight = act + (int)s->queue.size();
+    }
+    return BZ_OK;
+}
+
+int bz_server_stats(bz_server *s, uint64_t *rounds, uint64_t *yields) {
+    if (!s) return BZ_ERR_ARG;
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (rounds) *rounds = s->rounds;
+    if (yields) *yields = s->yields;
+    return BZ_OK;
+}
+
+int bz_server_stop(bz_server *s) {
+    if (!s) return BZ_ERR_ARG;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->yield_h) __atomic_store_n(s->yield_h, 1u, __ATOMIC_RELEASE);
+    }
+    server_free(s);
+    return BZ_OK;
 }
 
 }  // extern "C"

@@ -870,14 +870,17 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
 // one persistent enumeration launch
 // =====================================================================
 
-// One workgroup (one wavefront) per code.  Also publishes the code's first
-// claim word and counts it in BatchState::remaining.
+// One workgroup (one wavefront) per code (or per listed slot).  Also
+// publishes the code's first claim word and counts it in
+// BatchState::remaining.
 __global__ __launch_bounds__(64) void decompose_batch_kernel(const uint8_t *__restrict__ G,
                                                              const BatchCode *__restrict__ codes, CodeState *css,
-                                                             u32 *__restrict__ rows, uint32_t grid, BatchState *bs) {
+                                                             u32 *__restrict__ rows, uint32_t grid, BatchState *bs,
+                                                             const int32_t *__restrict__ slots, uint32_t *done_flags) {
     __shared__ DecompLDS lds;
-    const BatchCode bc = codes[blockIdx.x];
-    CodeState *cs = css + blockIdx.x;
+    const int c = slots ? slots[blockIdx.x] : (int)blockIdx.x;  // a list of slots, or every code
+    const BatchCode bc = codes[c];
+    CodeState *cs = css + c;
     RunArgs a;
     a.n = bc.n;
     a.k = bc.k;
@@ -909,7 +912,25 @@ __global__ __launch_bounds__(64) void decompose_batch_kernel(const uint8_t *__re
         const bool work = cs->res.status == BZ_OK && cs->res.n_table > 0;
         cs->claim = work ? claim_make(0, cs->stages[0].parts) : 0ull;
         if (work) atomicAdd(&bs->remaining, 1u);
+        // serving: a code with nothing to enumerate is done at once
+        else if (done_flags) __hip_atomic_store(done_flags + c, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     }
+}
+
+// Serving: the predictor's inputs for the listed slots, from their
+// decomposition (field, length, dimension, rank deficit of the last
+// information set), normalised as the network was trained.
+__global__ void features_kernel(const CodeState *__restrict__ css, const int32_t *__restrict__ slots, int n,
+                                float *__restrict__ feat) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const CodeState &cs = css[slots[i]];
+    const int m = cs.res.m;
+    const int km = m > 0 ? cs.res.ranks[m - 1] : cs.k;
+    feat[i * 4 + 0] = ((float)cs.p - 5.0f) / 2.0f;
+    feat[i * 4 + 1] = ((float)cs.n - 60.0f) / 30.0f;
+    feat[i * 4 + 2] = ((float)cs.k - 25.0f) / 15.0f;
+    feat[i * 4 + 3] = (float)(cs.k - km) / 8.0f;
 }
 
 // The tiles of one part of a stage: tile_of(r, part, parts, s) for r = 0, 1, ...
@@ -937,8 +958,9 @@ __device__ u64 run_part(const StageDesc &sd, int s, uint32_t part, int k, const 
 
 // After the last part of stage s of a code: U takes the stage minimum, the
 // L >= U test (Alg. 6) ends the code or publishes the next stage's claim word.
-// Run by one whole wavefront; only lane 0 touches memory.
-__device__ void batch_check(CodeState *cs, int s, const StageDesc &sd, BatchState *bs) {
+// Run by one whole wavefront; only lane 0 touches memory.  done_flag (or
+// NULL) is raised when the code ends.
+__device__ void batch_check(CodeState *cs, int s, const StageDesc &sd, BatchState *bs, uint32_t *done_flag) {
     if (__lane_id() != 0) return;
     const u64 st = rd_atomic(&cs->res.ctl);
     const int U = min((int)ctl_U(st), rd_atomic(&cs->res.stage_min[s]));
@@ -950,7 +972,12 @@ __device__ void batch_check(CodeState *cs, int s, const StageDesc &sd, BatchStat
     drain_vmem();  // U is in place before the next stage can be claimed and checked
     __hip_atomic_exchange(&cs->claim, last ? 0ull : claim_make(s + 1, cs->stages[s + 1].parts), __ATOMIC_RELAXED,
                           __HIP_MEMORY_SCOPE_AGENT);
-    if (last) __hip_atomic_fetch_sub(&bs->remaining, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (last) {
+        __hip_atomic_fetch_sub(&bs->remaining, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // serving: tell the host (mapped host memory); the release makes the
+        // code's result block visible to a copy the host then issues
+        if (done_flag) __hip_atomic_store(done_flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
 }
 
 // Persistent, cooperative: every workgroup repeatedly claims one part of the
@@ -958,11 +985,17 @@ __device__ void batch_check(CodeState *cs, int s, const StageDesc &sd, BatchStat
 // word, starting after the code it took last), runs it, reports minimum and
 // count, and the workgroup that finishes a stage's last part checks it.  Exits
 // when no code has stages left.  Codes of every (p, W <= WMAX) share the launch.
+// Serving adds three optional arrays: order (codes scanned in this priority
+// order, always from the front), yield (mapped host flag: once set, workgroups
+// stop claiming and exit after their current part; every code keeps its
+// progress in its claim word for the next launch) and done_flags (mapped host
+// flags raised as codes end).
 template <int WMAX>
 __global__ __launch_bounds__(256) void enum_batch_kernel(CodeState *css, const BatchCode *__restrict__ codes,
                                                          int ncodes, const u32 *__restrict__ rows,
                                                          const u64 *__restrict__ gbin, BatchState *bs,
-                                                         u64 timeout_ticks) {
+                                                         u64 timeout_ticks, const int32_t *__restrict__ order,
+                                                         const uint32_t *yield, uint32_t *done_flags) {
     __shared__ u64 sbin[BZ_MAX_K * BIN_I];
     __shared__ QEntry qtab[BZ_MAX_K];
     __shared__ u32 red_min[WAVES_PER_GROUP];
@@ -980,16 +1013,20 @@ __global__ __launch_bounds__(256) void enum_batch_kernel(CodeState *css, const B
             uint32_t part = 0;
             u64 t0 = 0;
             for (uint32_t it = 0;; it++) {
-                int rem = 0, bst = 0;
+                int rem = 0, bst = 0, yl = 0;
                 if (lane == 0) {
                     rem = (int)ld_poll(&bs->remaining);
                     bst = ld_poll(&bs->status);
+                    // host memory: read when a scan starts, then every 16th idle step
+                    if (yield && (it & 15u) == 0u)
+                        yl = (int)__hip_atomic_load(yield, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 }
-                if (uni(rem) == 0 || uni(bst) != BZ_OK) break;
+                if (uni(rem) == 0 || uni(bst) != BZ_OK || uni(yl) != 0) break;
                 bool got = false;
                 for (int base = 0; base < ncodes && !got; base += 64) {
                     const bool in = base + lane < ncodes;
-                    const int c = (int)((scan + (uint32_t)(base + lane)) % (uint32_t)ncodes);
+                    const int c = order ? (in ? order[base + lane] : 0)
+                                        : (int)((scan + (uint32_t)(base + lane)) % (uint32_t)ncodes);
                     bool open = false;
                     if (in) {
                         const u64 cw = ld_poll(&css[c].claim);
@@ -1085,7 +1122,7 @@ __global__ __launch_bounds__(256) void enum_batch_kernel(CodeState *css, const B
                 drain_vmem();  // minimum and count performed before done counts this part
                 done = __hip_atomic_fetch_add(&cs->stage_done[s], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
             }
-            if (uni(done) == sd.parts) batch_check(cs, s, sd, bs);
+            if (uni(done) == sd.parts) batch_check(cs, s, sd, bs, done_flags ? done_flags + code : nullptr);
         }
         __syncthreads();  // qtab, red_* and s_* are rewritten by the next claim
     }

@@ -62,7 +62,9 @@ def test_struct_layout(bzlib, tmp_path):
                 ' sizeof(bz_result), offsetof(bz_result, stages), offsetof(bz_result, codewords_total),'
                 ' sizeof(bz_options), offsetof(bz_options, max_codewords), offsetof(bz_options, trace_out),'
                 ' sizeof(bz_code), offsetof(bz_code, g_offset), sizeof(bz_batch_options),'
-                ' offsetof(bz_batch_options, hip_stream), offsetof(bz_batch_options, enum_ms)); return 0;}\n')
+                ' offsetof(bz_batch_options, hip_stream), offsetof(bz_batch_options, enum_ms));'
+                ' printf("%zu %zu %zu\\n", sizeof(bz_server_options), offsetof(bz_server_options, max_codewords),'
+                ' offsetof(bz_server_options, max_n)); return 0;}\n')
     exe = os.path.join(str(tmp_path), "layout")
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
     c_vals = [int(x) for x in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
@@ -70,7 +72,9 @@ def test_struct_layout(bzlib, tmp_path):
                bzlib.bz_result.codewords_total.offset, ctypes.sizeof(bzlib.bz_options),
                bzlib.bz_options.max_codewords.offset, bzlib.bz_options.trace_out.offset,
                ctypes.sizeof(bzlib.bz_code), bzlib.bz_code.g_offset.offset, ctypes.sizeof(bzlib.bz_batch_options),
-               bzlib.bz_batch_options.hip_stream.offset, bzlib.bz_batch_options.enum_ms.offset]
+               bzlib.bz_batch_options.hip_stream.offset, bzlib.bz_batch_options.enum_ms.offset,
+               ctypes.sizeof(bzlib.bz_server_options), bzlib.bz_server_options.max_codewords.offset,
+               bzlib.bz_server_options.max_n.offset]
     assert c_vals == py_vals
 
 
@@ -122,3 +126,17 @@ def test_batch_argument_errors_need_no_device(bzlib):
     assert L.bz_sliced_op(7, bzlib.OP_KAT_ADD, 1, 32, ctypes.c_void_p(8), ctypes.c_void_p(8),
                           ctypes.c_void_p(8), 1, None) == bzlib.ERR_ARG
     assert L.bz_sliced_pack(5, 0, 1, 32, ctypes.c_void_p(8), ctypes.c_void_p(8), None) == bzlib.ERR_ARG
+
+
+def test_server_option_errors_need_no_device(bzlib):
+    import ctypes
+    o = bzlib.bz_server_options()
+    bzlib.lib().bz_default_server_options(ctypes.byref(o))
+    assert (o.slots, o.policy, o.check, o.identity_skip) == (1024, 0, 0, 1)
+    h = ctypes.c_void_p()
+    for field, value in [("policy", 1), ("slots", -1), ("check", 7), ("max_n", 129), ("blocks_per_cu", -1)]:
+        bad = bzlib.bz_server_options()
+        ctypes.pointer(bad)[0] = o
+        setattr(bad, field, value)  # policy 1 needs the network's parameters
+        assert bzlib.lib().bz_server_start(ctypes.byref(bad), ctypes.byref(h)) == bzlib.ERR_ARG
+    assert bzlib.lib().bz_server_submit(None, 3, 10, 4, None, 0) == bzlib.ERR_ARG
