@@ -129,29 +129,29 @@ hipError_t launch_decompose(int WF, const uint8_t *G, CodeState *cs, u32 *rows, 
 // is resident at once, which its waits for earlier stages rely on.  The grid
 // (see enum_grid) is clamped to the kernel's occupancy.
 template <int P, int W, bool H>
-hipError_t launch_enum_one(int grid, CodeState *cs, const u32 *rows, const u64 *binom, u64 *hist, int lookahead,
-                           u64 timeout, hipStream_t s) {
-    void *args[] = {&cs, &rows, &binom, &hist, &lookahead, &timeout};
+hipError_t launch_enum_one(int grid, CodeState *cs, const u32 *rows, const u64 *binom, u64 *hist, EnumArgs ea,
+                           hipStream_t s) {
+    void *args[] = {&cs, &rows, &binom, &hist, &ea};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(enum_kernel<P, W, H>), dim3(grid), dim3(256),
                                       args, 0, s);
 }
 
 template <int P, bool H>
-hipError_t launch_enum_h(int W, int grid, CodeState *cs, const u32 *rows, const u64 *binom, u64 *hist, int la,
-                         u64 to, hipStream_t s) {
+hipError_t launch_enum_h(int W, int grid, CodeState *cs, const u32 *rows, const u64 *binom, u64 *hist, EnumArgs ea,
+                         hipStream_t s) {
     switch (W) {
-    case 1: return launch_enum_one<P, 1, H>(grid, cs, rows, binom, hist, la, to, s);
-    case 2: return launch_enum_one<P, 2, H>(grid, cs, rows, binom, hist, la, to, s);
-    case 3: return launch_enum_one<P, 3, H>(grid, cs, rows, binom, hist, la, to, s);
-    default: return launch_enum_one<P, 4, H>(grid, cs, rows, binom, hist, la, to, s);
+    case 1: return launch_enum_one<P, 1, H>(grid, cs, rows, binom, hist, ea, s);
+    case 2: return launch_enum_one<P, 2, H>(grid, cs, rows, binom, hist, ea, s);
+    case 3: return launch_enum_one<P, 3, H>(grid, cs, rows, binom, hist, ea, s);
+    default: return launch_enum_one<P, 4, H>(grid, cs, rows, binom, hist, ea, s);
     }
 }
 
 template <int P>
 hipError_t launch_enum(bool hist_mode, int W, int grid, CodeState *cs, const u32 *rows, const u64 *binom, u64 *hist,
-                       int la, u64 to, hipStream_t s) {
-    return hist_mode ? launch_enum_h<P, true>(W, grid, cs, rows, binom, hist, la, to, s)
-                     : launch_enum_h<P, false>(W, grid, cs, rows, binom, hist, la, to, s);
+                       EnumArgs ea, hipStream_t s) {
+    return hist_mode ? launch_enum_h<P, true>(W, grid, cs, rows, binom, hist, ea, s)
+                     : launch_enum_h<P, false>(W, grid, cs, rows, binom, hist, ea, s);
 }
 
 // Largest grid the enumeration kernel may get for (p, W, histograms): the
@@ -389,10 +389,14 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, c
     HIP_OK(p == 3 ? launch_decompose<3>(WF, Gd, c->cs, c->rows, a, s)
                   : launch_decompose<7>(WF, Gd, c->cs, c->rows, a, s));
     if (o.timing) HIP_OK(hipEventRecord(c->ev[1], s));
-    HIP_OK(p == 3 ? launch_enum<3>(o.histograms != 0, W, grid, c->cs, c->rows, c->binom, c->hist, LOOKAHEAD,
-                                   timeout, s)
-                  : launch_enum<7>(o.histograms != 0, W, grid, c->cs, c->rows, c->binom, c->hist, LOOKAHEAD,
-                                   timeout, s));
+    EnumArgs ea;
+    ea.k = k;
+    ea.n = n;
+    ea.flags = flags;
+    ea.lookahead = LOOKAHEAD;
+    ea.timeout_ticks = timeout;
+    HIP_OK(p == 3 ? launch_enum<3>(o.histograms != 0, W, grid, c->cs, c->rows, c->binom, c->hist, ea, s)
+                  : launch_enum<7>(o.histograms != 0, W, grid, c->cs, c->rows, c->binom, c->hist, ea, s));
     if (o.timing) HIP_OK(hipEventRecord(c->ev[2], s));
     HIP_OK(hipMemcpyAsync(c->host_res, &c->cs->res, sizeof(CodeResult), hipMemcpyDeviceToHost, s));
     if (o.histograms)

@@ -59,6 +59,12 @@ __device__ __forceinline__ u32 pick(const u32 (&a)[N], int q) {
     return v;
 }
 
+// Launch arguments of the enumeration kernel (known to the host up front).
+struct EnumArgs {
+    int32_t k, n, flags, lookahead;
+    u64 timeout_ticks;
+};
+
 struct RunArgs {
     int32_t n, k, flags, U0;
     u64 max_codewords;
@@ -389,12 +395,12 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
         if (in) {
             s_cw[lane] = cw;
             s_combos[lane] = (uint32_t)combos;
-            s_tasks[lane] = (g <= 2) ? small_stage_tasks(k, g) : 0;
+            s_tasks[lane] = (g <= SUBSET_G) ? small_stage_tasks(k, g) : 0;
         }
         __syncthreads();
         // task counts of the rounds g >= 3 that the table reaches, one wave-parallel pass each
         const int last_g = (ns + m - 1) / m;
-        for (int gg = 3; gg <= last_g; gg++) {
+        for (int gg = SUBSET_G + 1; gg <= last_g; gg++) {
             const u64 t = wave_qtable(k, gg, s_combos[gg - 1], sweep_cap_for(P, W, args.sweep_ops), binom, nullptr);
             if (t >= (1ull << 62)) {
                 ns = min(ns, (gg - 1) * m);
@@ -597,22 +603,89 @@ __device__ __forceinline__ void extend_and_sweep(const u32 *__restrict__ rows, i
     }
 }
 
+// C(c, i) for i < BIN_I into LDS: every load of a thread is issued before
+// its first store (a loop that stores each value before the next load waits
+// for one memory round trip per element).  blockDim.x = 256.
+__device__ __forceinline__ void stage_binomials(u64 *sbin, const u64 *__restrict__ gbin) {
+    constexpr int N = BZ_MAX_K * BIN_I, PER = (N + 255) / 256;
+    u64 v[PER];
+#pragma unroll
+    for (int r = 0; r < PER; r++) {
+        const int i = threadIdx.x + r * 256;
+        v[r] = i < N ? gbin[(i / BIN_I) * 65 + i % BIN_I] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < PER; r++) {
+        const int i = threadIdx.x + r * 256;
+        if (i < N) sbin[i] = v[r];
+    }
+}
+
 // binomial C(c, i): LDS for small i, global memory otherwise
 __device__ __forceinline__ u64 binom_at(const u64 *sbin, const u64 *__restrict__ gbin, int c, int i) {
     return (i < BIN_I) ? sbin[c * BIN_I + i] : gbin[c * 65 + i];
 }
 
-// g = 1 and g = 2: one item per lane (a row, or a pair of rows).
-// Returns the number of combinations the wavefront evaluated (wave-uniform).
+// Prefixes Q + a R for a = a0 .. a0+NA-1 and their nonzero masks, then every
+// multiple of the last row T through complete_all.
+template <int P, int W, int NA, bool HIST>
+__device__ __forceinline__ void prefixes_then_complete(const u32 (&Q)[3][W], const Row<W> &R, int a0, const Row<W> &T,
+                                                       u32 &lmin, u32 *lh, u32 woff, u32 cap) {
+    u32 Pv[NA][3][W], anyP[NA][W];
+#pragma unroll
+    for (int a = 0; a < NA; a++) {
+#pragma unroll
+        for (int b = 0; b < 3; b++)
+#pragma unroll
+            for (int w = 0; w < W; w++) Pv[a][b][w] = Q[b][w];
+        add_scaled<P, W>(Pv[a], R.p, a0 + a);
+#pragma unroll
+        for (int w = 0; w < W; w++) anyP[a][w] = Pv[a][0][w] | Pv[a][1][w] | Pv[a][2][w];
+    }
+    complete_all<P, W, NA, HIST>(Pv, anyP, T, lmin, lh, woff, cap);
+}
+
+// G = 3, 4: the lane's subset rows r[0] < ... < r[G-1]; r[0] has coefficient
+// 1, the middle rows every multiplier (exact prefixes, two at a time to keep
+// the registers of F_7 in check), the top row every multiplier through
+// complete_all.
+template <int P, int W, int G, bool HIST>
+__device__ __forceinline__ void run_subset(const u32 *__restrict__ rows, int j, const int (&r)[G], u32 &lmin,
+                                           u32 *lh, u32 woff, u32 cap) {
+    constexpr int NA = 2;  // P - 1 is a multiple of 2
+    const Row<W> R0 = load_row<P, W>(rows, j, r[0]);
+    const Row<W> R1 = load_row<P, W>(rows, j, r[1]);
+    const Row<W> R2 = load_row<P, W>(rows, j, r[2]);
+    if constexpr (G == 3) {
+        for (int a0 = 1; a0 < P; a0 += NA)
+            prefixes_then_complete<P, W, NA, HIST>(R0.p, R1, a0, R2, lmin, lh, woff, cap);
+    } else {
+        const Row<W> R3 = load_row<P, W>(rows, j, r[3]);
+        for (int h = 1; h < P; h++) {
+            u32 Q[3][W];
+#pragma unroll
+            for (int b = 0; b < 3; b++)
+#pragma unroll
+                for (int w = 0; w < W; w++) Q[b][w] = R0.p[b][w];
+            add_scaled<P, W>(Q, R1.p, h);
+            for (int a0 = 1; a0 < P; a0 += NA)
+                prefixes_then_complete<P, W, NA, HIST>(Q, R2, a0, R3, lmin, lh, woff, cap);
+        }
+    }
+}
+
+// g <= SUBSET_G: one item per lane (a row, a pair of rows, a triple, a
+// quadruple; colex rank task * 64 + lane).  Returns the number of
+// combinations the wavefront evaluated (wave-uniform).
 template <int P, int W, bool HIST>
-__device__ u64 run_small_task(int g, int k, int j, const u32 *__restrict__ rows, u64 task, u32 &lmin, u32 *lh,
-                              u32 woff, u32 cap) {
+__device__ u64 run_small_task(int g, int k, int j, const u32 *__restrict__ rows, const u64 *sbin,
+                              const u64 *__restrict__ gbin, u64 task, u32 &lmin, u32 *lh, u32 woff, u32 cap) {
     const int lane = __lane_id();
-    const int item = (int)(task * 64) + lane;
-    const bool valid = item < k;
+    const u64 item = task * 64 + (u64)lane;
     if (g == 1) {
+        const bool valid = item < (u64)k;
         if (valid) {
-            const Row<W> r = load_row<P, W>(rows, j, item);
+            const Row<W> r = load_row<P, W>(rows, j, (int)item);
             u32 wt = 0;
 #pragma unroll
             for (int w = 0; w < W; w++) wt += __builtin_popcount(r.any[w]);
@@ -621,27 +694,44 @@ __device__ u64 run_small_task(int g, int k, int j, const u32 *__restrict__ rows,
         }
         return (u64)__popcll(__ballot(valid));
     }
-    // g = 2: the item is a pair s < L; row s has coefficient 1, row L every multiplier
-    const int npairs = k * (k - 1) / 2;
-    const bool pv = (int)(task * 64) + lane < npairs;
-    if (pv) {
-        int s, L;
-        pair_of((int)(task * 64) + lane, k, &s, &L);
-        const Row<W> Rs = load_row<P, W>(rows, j, s);
-        const Row<W> RL = load_row<P, W>(rows, j, L);
-        u32 Pv[1][3][W], A1[1][W];
+    if (g == 2) {
+        // a pair s < L; row s has coefficient 1, row L every multiplier
+        const bool pv = item < (u64)(k * (k - 1) / 2);
+        if (pv) {
+            int s, L;
+            pair_of((int)item, k, &s, &L);
+            const Row<W> Rs = load_row<P, W>(rows, j, s);
+            const Row<W> RL = load_row<P, W>(rows, j, L);
+            u32 Pv[1][3][W], A1[1][W];
 #pragma unroll
-        for (int b = 0; b < 3; b++)
+            for (int b = 0; b < 3; b++)
 #pragma unroll
-            for (int w = 0; w < W; w++) Pv[0][b][w] = Rs.p[b][w];
+                for (int w = 0; w < W; w++) Pv[0][b][w] = Rs.p[b][w];
 #pragma unroll
-        for (int w = 0; w < W; w++) A1[0][w] = Rs.any[w];
-        complete_all<P, W, 1, HIST>(Pv, A1, RL, lmin, lh, woff, cap);
+            for (int w = 0; w < W; w++) A1[0][w] = Rs.any[w];
+            complete_all<P, W, 1, HIST>(Pv, A1, RL, lmin, lh, woff, cap);
+        }
+        return (u64)(P - 1) * (u64)__popcll(__ballot(pv));
     }
-    return (u64)(P - 1) * (u64)__popcll(__ballot(pv));
+    auto bin = [&](int c, int i) { return binom_at(sbin, gbin, c, i); };
+    const bool valid = item < binom_sat(k, g);
+    if (g == 3) {
+        if (valid) {
+            int r[3];
+            decode_subset<3>(item, k, bin, r);
+            run_subset<P, W, 3, HIST>(rows, j, r, lmin, lh, woff, cap);
+        }
+        return (u64)((P - 1) * (P - 1)) * (u64)__popcll(__ballot(valid));
+    }
+    if (valid) {
+        int r[4];
+        decode_subset<4>(item, k, bin, r);
+        run_subset<P, W, 4, HIST>(rows, j, r, lmin, lh, woff, cap);
+    }
+    return (u64)((P - 1) * (P - 1) * (P - 1)) * (u64)__popcll(__ballot(valid));
 }
 
-// g >= 3: one task = (q, chunk of 64 bases, block of rows s); see StageDesc.
+// g > SUBSET_G: one task = (q, chunk of 64 bases, block of rows s); see StageDesc.
 template <int P, int W, bool HIST>
 __device__ u64 run_base_task(const StageDesc &sd, int k, int j, const u32 *__restrict__ rows, const u64 *sbin,
                              const u64 *__restrict__ gbin, const QEntry *qtab, int nq, u64 task, u32 &lmin,
@@ -727,7 +817,9 @@ __device__ void run_checker(CodeState *cs, const StageDesc *sdesc, int ns) {
 template <int P, int W, bool HIST>
 __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__restrict__ rows,
                                                    const u64 *__restrict__ gbin, u64 *__restrict__ hist,
-                                                   int lookahead, u64 timeout_ticks) {
+                                                   EnumArgs ea) {
+    const int lookahead = ea.lookahead;
+    const u64 timeout_ticks = ea.timeout_ticks;
     __shared__ u64 sbin[BZ_MAX_K * BIN_I];
     __shared__ StageDesc sdesc[BZ_MAX_STAGES];
     __shared__ QEntry qtab[BZ_MAX_K];
@@ -739,15 +831,22 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
     const int lane = __lane_id();
     const int wid = threadIdx.x >> 6;
     const uint32_t grid = gridDim.x, b = blockIdx.x;
-    if (cs->res.status != BZ_OK) return;
-    const int k = uni(cs->k), n = uni(cs->n);
-    const int ns = uni(cs->res.n_table);
-    const bool tracing = (cs->flags & FLAG_TRACE) != 0;
+    const int k = ea.k, n = ea.n;
+    const bool tracing = (ea.flags & FLAG_TRACE) != 0;
     if (tracing && threadIdx.x == 0) atomicMin((unsigned long long *)&cs->trace[1][0], (unsigned long long)wall_clock64());
-    for (int i = threadIdx.x; i < BZ_MAX_K * BIN_I; i += blockDim.x) sbin[i] = gbin[(i / BIN_I) * 65 + i % BIN_I];
-    for (int i = threadIdx.x; i < ns; i += blockDim.x) sdesc[i] = cs->stages[i];
+    // one round of independent loads: the decomposition's status and table
+    // size, one stage descriptor per thread (ns <= BZ_MAX_STAGES = blockDim.x)
+    // and the binomials
+    static_assert(BZ_MAX_STAGES == 256, "one stage descriptor per thread");
+    const int status0 = cs->res.status, ns0 = cs->res.n_table;
+    constexpr int EARLY = 32;  // descriptors loaded before the table size is known
+    if (threadIdx.x < EARLY) sdesc[threadIdx.x] = cs->stages[threadIdx.x];
+    stage_binomials(sbin, gbin);
+    if (threadIdx.x >= EARLY && (int)threadIdx.x < ns0) sdesc[threadIdx.x] = cs->stages[threadIdx.x];
     __syncthreads();
-    const bool skip = (cs->flags & FLAG_SKIP) != 0;
+    if (uni(status0) != BZ_OK) return;
+    const int ns = uni(ns0);
+    const bool skip = (ea.flags & FLAG_SKIP) != 0;
     u32 *lh = HIST ? &lhist[wid * (BZ_MAX_N + 1)] : nullptr;
     const u32 cap = (u32)n;
     for (int s = 0; s < ns; s++) {
@@ -790,7 +889,7 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
             }
             s_crit = ctl_checked(st) >= s;  // the earliest unchecked stage: no later stage can wait on it
         }
-        if (wid == 0 && sd.g >= 3) wave_qtable(k, sd.g, sd.coef_combos, sd.sweep_cap, gbin, qtab);
+        if (wid == 0 && sd.g > SUBSET_G) wave_qtable(k, sd.g, sd.coef_combos, sd.sweep_cap, gbin, qtab);
         __syncthreads();
         const int term = s_term;
         const bool crit = s_crit != 0;
@@ -819,10 +918,10 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
             if constexpr (HIST) {
                 for (int w = lane; w <= n; w += 64) lh[w] = 0;
             }
-            if (sg >= 3)
+            if (sg > SUBSET_G)
                 cnt += run_base_task<P, W, HIST>(sd, k, j, rows, sbin, gbin, qtab, nq, task, lmin, lh, woff, cap);
             else
-                cnt += run_small_task<P, W, HIST>(sg, k, j, rows, task, lmin, lh, woff, cap);
+                cnt += run_small_task<P, W, HIST>(sg, k, j, rows, sbin, gbin, task, lmin, lh, woff, cap);
             if constexpr (HIST) {
                 for (int w = lane; w <= n; w += 64) {
                     const u32 c = lh[w];
@@ -948,10 +1047,10 @@ __device__ u64 run_part(const StageDesc &sd, int s, uint32_t part, int k, const 
         if (tile >= tiles) break;
         const u64 task = tile * WAVES_PER_GROUP + (u64)wid;
         if (task >= tasks) continue;
-        if (g >= 3)
+        if (g > SUBSET_G)
             cnt += run_base_task<P, W, false>(sd, k, j, rows, sbin, gbin, qtab, nq, task, lmin, nullptr, woff, cap);
         else
-            cnt += run_small_task<P, W, false>(g, k, j, rows, task, lmin, nullptr, woff, cap);
+            cnt += run_small_task<P, W, false>(g, k, j, rows, sbin, gbin, task, lmin, nullptr, woff, cap);
     }
     return cnt;
 }
@@ -1004,7 +1103,7 @@ __global__ __launch_bounds__(256) void enum_batch_kernel(CodeState *css, const B
     __shared__ uint32_t s_part;
     const int lane = __lane_id();
     const int wid = threadIdx.x >> 6;
-    for (int i = threadIdx.x; i < BZ_MAX_K * BIN_I; i += blockDim.x) sbin[i] = gbin[(i / BIN_I) * 65 + i % BIN_I];
+    stage_binomials(sbin, gbin);
     uint32_t scan = (uint32_t)((u64)blockIdx.x * (u64)ncodes / gridDim.x);
     __syncthreads();
     for (;;) {
@@ -1084,9 +1183,9 @@ __global__ __launch_bounds__(256) void enum_batch_kernel(CodeState *css, const B
         const int n = uni(codes[code].n);
         const u64 row_off = uni64(codes[code].row_offset);
         const StageDesc sd = cs->stages[s];
-        if (wid == 0 && sd.g >= 3) wave_qtable(k, sd.g, sd.coef_combos, sd.sweep_cap, gbin, qtab);
+        if (wid == 0 && sd.g > SUBSET_G) wave_qtable(k, sd.g, sd.coef_combos, sd.sweep_cap, gbin, qtab);
         __syncthreads();
-        const u32 woff = (cs->flags & FLAG_SKIP) ? (u32)sd.g : 0u;
+        const u32 woff = (uni(codes[code].flags) & FLAG_SKIP) ? (u32)sd.g : 0u;
         const u32 cap = (u32)n;
         const u32 *r = rows + row_off;
         u32 lmin = BIG;

@@ -302,9 +302,31 @@ BZ_HD int round_stages(int m, u64 cum, u64 cw, u64 combos, u64 max_codewords) {
     const u64 j = (max_codewords - cum) / cw;
     return j < (u64)m ? (int)j : m;
 }
-// Tasks of a stage with g = 1 or 2 (one item per lane: a row, or a pair of rows).
-BZ_HD u64 small_stage_tasks(int k, int g) {
-    return g == 1 ? ((u64)k + 63) / 64 : ((u64)(k * (k - 1) / 2) + 63) / 64;
+// Rounds g <= SUBSET_G give each lane one g-subset of the rows (all its
+// coefficient vectors); larger rounds give it a base of g-2 rows and sweep the
+// last two rows (see StageDesc).
+constexpr int SUBSET_G = 4;
+
+// Tasks of a stage with g <= SUBSET_G: 64 subsets per task.
+BZ_HD u64 small_stage_tasks(int k, int g) { return (binom_sat(k, g) + 63) / 64; }
+
+// The g-subset of the rows 0..k-1 of colex rank r (r < C(k, g)), ascending in
+// rows[0..g-1]: the top row is the largest c with C(c, g) <= r, and so on down.
+template <int G, typename Bin>
+BZ_HD void decode_subset(u64 r, int k, Bin bin, int (&rows)[G]) {
+    int hi = k - 1;
+#pragma unroll
+    for (int t = G; t >= 1; t--) {
+        int lo = t - 1, h = hi;
+        while (lo < h) {
+            const int mid = (lo + h + 1) >> 1;
+            if (bin(mid, t) <= r) lo = mid;
+            else h = mid - 1;
+        }
+        rows[t - 1] = lo;
+        r -= bin(lo, t);
+        hi = lo - 1;
+    }
 }
 
 // Build the schedule: stages (g, j) for g = 1..k, j = 1..m in order, while the
@@ -324,7 +346,7 @@ BZ_HD int build_schedule(int p, int k, int m, const int32_t *ranks, int flags, u
         const u64 cw = round_codewords(p, k, g, binom);
         u64 tasks;
         const u64 combos = round_combos(p, g);
-        if (g <= 2) tasks = small_stage_tasks(k, g);
+        if (g <= SUBSET_G) tasks = small_stage_tasks(k, g);
         else {
             // without count_tasks the caller fills tasks, tiles and parts of these stages
             tasks = (combos >= (1ull << 32)) ? ~0ull : count_tasks ? fill_qtable(k, g, combos, cap, binom, nullptr) : 0;

@@ -11,6 +11,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstdlib>
+#include <cmath>
 #include <cstring>
 #include <random>
 #include <map>
@@ -214,7 +215,7 @@ static int lane_parallel_schedule(int p, int k, int m, const int *ranks, int fla
         inc[l] = l ? sat_add(inc[l - 1], mine) : mine;
         const u64 before = l ? inc[l - 1] : 0;
         js[l] = in ? round_stages(m, before, cw[l], cb, max_cw) : m;
-        tasks[l] = (g <= 2) ? small_stage_tasks(k, g) : 0;
+        tasks[l] = (g <= SUBSET_G) ? small_stage_tasks(k, g) : 0;
     }
     int ns = k * m;
     *complete = 1;
@@ -226,7 +227,7 @@ static int lane_parallel_schedule(int p, int k, int m, const int *ranks, int fla
         }
     const uint32_t cap = sweep_cap_for(p, W, sweep_ops);
     const int last_g = (ns + m - 1) / m;
-    for (int g = 3; g <= last_g; g++) {
+    for (int g = SUBSET_G + 1; g <= last_g; g++) {
         const u64 t = fill_qtable(k, g, combos[g - 1], cap, BINOM, nullptr);
         if (t >= (1ull << 62)) {
             ns = std::min(ns, (g - 1) * m);
@@ -337,6 +338,35 @@ static void check_unrank() {
                                 pair_of(r, k, &s, &L);
                                 CHECK(0 <= s && s < L && L < k);
                                 for (int h = 1; h < P; h++) { add({s, L}, {1, h}); counted++; }
+                            }
+                    } else if (g <= SUBSET_G) {
+                        // one subset per lane, every coefficient vector with the lowest row's 1
+                        CHECK(d.tasks == (C(k, g) + 63) / 64);
+                        auto bin = [&](int c, int i) { return BINOM[c * 65 + i]; };
+                        for (u64 t = 0; t < d.tasks; t++)
+                            for (int l = 0; l < 64; l++) {
+                                const u64 r = t * 64 + (u64)l;
+                                if (r >= C(k, g)) continue;
+                                std::vector<int> rows(g);
+                                if (g == 3) {
+                                    int rr[3];
+                                    decode_subset<3>(r, k, bin, rr);
+                                    rows.assign(rr, rr + 3);
+                                } else {
+                                    int rr[4];
+                                    decode_subset<4>(r, k, bin, rr);
+                                    rows.assign(rr, rr + 4);
+                                }
+                                for (int i = 0; i + 1 < g; i++) CHECK(rows[i] < rows[i + 1]);
+                                CHECK(rows[0] >= 0 && rows[g - 1] < k);
+                                std::vector<int> coefs(g, 1);
+                                // coefficients of rows 1..g-1 in 1..P-1, as a counter
+                                for (u64 cv = 0; cv < (u64)std::pow(P - 1, g - 1); cv++) {
+                                    u64 x = cv;
+                                    for (int i = 1; i < g; i++) { coefs[i] = (int)(x % (P - 1)) + 1; x /= (P - 1); }
+                                    add(rows, coefs);
+                                    counted++;
+                                }
                             }
                     } else {
                         std::vector<QEntry> tab(BZ_MAX_K);
