@@ -108,7 +108,10 @@ typedef struct {
                                  {start, rows loaded, matrices reduced, end}; row 1 =
                                  enumeration kernel {first workgroup start, last workgroup end};
                                  row 2+s = stage s {first workgroup start, last workgroup
-                                 end, checked, last workgroup start} */
+                                 end, checked, last workgroup start}.  Workgroup times
+                                 are those of every seventh workgroup (the device's one
+                                 real-time counter slows down when a thousand workgroups
+                                 read it at once); "checked" is exact */
 } bz_options;
 
 /* Fill *o with the defaults above. */

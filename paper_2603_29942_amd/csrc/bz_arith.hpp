@@ -107,6 +107,39 @@ BZ_HD void scale<7>(int h, const u32 *x, u32 *y) {
     else { y[0] = r0; y[1] = r1; y[2] = r2; }
 }
 
+// ---------------------------------------------------------------- compress
+// The bits of x selected by a mask m, packed in order into the low bits: the
+// parallel-suffix compress of Hacker's Delight (sec. 7-4).  The five move
+// masks depend on m alone, so a mask shared by many words is planned once.
+struct Compress32 {
+    u32 mv[5];
+};
+BZ_HD Compress32 compress_plan(u32 m) {
+    Compress32 c;
+    u32 mk = ~m << 1;  // zeros of m to the right of each position, counted in parallel
+    for (int i = 0; i < 5; i++) {
+        u32 mp = mk ^ (mk << 1);
+        mp ^= mp << 2;
+        mp ^= mp << 4;
+        mp ^= mp << 8;
+        mp ^= mp << 16;  // parity of the zeros below each bit, per bit of the count
+        const u32 mv = mp & m;
+        c.mv[i] = mv;
+        m = (m ^ mv) | (mv >> (1 << i));
+        mk &= ~mp;
+    }
+    return c;
+}
+BZ_HD u32 compress_apply(u32 x, u32 m, const Compress32 &c) {
+    x &= m;
+#pragma unroll
+    for (int i = 0; i < 5; i++) {
+        const u32 t = x & c.mv[i];
+        x = (x ^ t) | (t >> (1 << i));
+    }
+    return x;
+}
+
 // modular inverse in F_p^* (small tables)
 BZ_HD int inv_mod(int P, int x) {
     if (P == 3) return x;  // 1 -> 1, 2 -> 2

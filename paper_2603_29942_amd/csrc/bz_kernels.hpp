@@ -85,7 +85,7 @@ __device__ __forceinline__ u64 wave_qtable(int k, int g, u64 M, uint32_t cap, co
     uint32_t B = 1, nb = 0;
     if (in) {
         qgroup(k, g, M, cap, binom, q, &bases, &B, &nb);
-        val = sat_mul((bases + 63) / 64, (u64)nb);
+        val = ceil64(bases) * (u64)nb;  // <= 2^58 * 62: no overflow
     }
     // inclusive scan of val over the lanes (saturating)
     u64 inc = val;
@@ -109,23 +109,76 @@ __device__ __forceinline__ u64 wave_qtable(int k, int g, u64 M, uint32_t cap, co
 // LDS of one decomposition (a kernel declares it once and passes it down, so
 // that one kernel can hold several instantiations of decompose_code)
 struct DecompLDS {
-    __align__(16) uint8_t gl[BZ_MAX_K * BZ_MAX_N];
     u64 binom[(BZ_MAX_K + 1) * 65];  // C(c, i) at [c * 65 + i], rows c <= k
     int32_t sranks[BZ_MAX_M];
     u64 s_cw[BZ_MAX_K], s_tasks[BZ_MAX_K];
+    u64 s_tbefore[BZ_MAX_K];  // tiles of the rounds before round g, at [g - 1]
     uint32_t s_combos[BZ_MAX_K];
+    uint32_t s_nb[BZ_MAX_K];  // blocks of rows s of the q-group with top row q, at [q]
 };
+
+// One Gauss-Jordan step on the rows held one per lane: row pl (pivot value
+// pv in the pivot column) becomes pv^-1 times itself, every other row i
+// becomes row_i - v_i pv^-1 row_pl (v_i = its entry in the pivot column).
+// Branch-free per lane: the multiplier h of the raw pivot row is
+// h = pv^-1 on the pivot lane and -v pv^-1 elsewhere, and h * row is a
+// rotation and a negation of its planes (F_3: 2 = -1 swaps the planes; F_7:
+// every nonzero h is +-2^e, times 2 rotates the three planes, negation is the
+// complement on the nonzero positions, Sec. 4.2).
+template <int P, int WF>
+__device__ __forceinline__ void eliminate(u32 (&x)[3][4], int v, int pl, int pv) {
+    const int lane = __lane_id();
+    const bool me = lane == pl;
+    const u32 keep = me ? 0u : ~0u;                     // pivot lane: replaced, others: added to
+    const u32 live = (me || v != 0) ? ~0u : 0u;         // rows with v = 0 are unchanged
+    if constexpr (P == 3) {
+        // h = pv on the pivot lane, -v pv elsewhere: h = 2 (a swap) iff pv = 2,
+        // resp. iff v = pv
+        const bool sw = me ? (pv == 2) : (v == pv);
+#pragma unroll
+        for (int w = 0; w < WF; w++) {
+            const u32 a0 = __builtin_amdgcn_readlane(x[0][w], pl), a1 = __builtin_amdgcn_readlane(x[1][w], pl);
+            const u32 s0 = (sw ? a1 : a0) & live, s1 = (sw ? a0 : a1) & live;
+            f3_add(x[0][w] & keep, x[1][w] & keep, s0, s1, x[0][w], x[1][w]);
+        }
+    } else {
+        // h = (-1)^neg 2^e; tables over v = 0..6 packed in constants:
+        // e(v) two bits at 2v, neg(v) one bit at v (1, 2, 4 = +2^e; 6, 5, 3 = -2^e)
+        constexpr u32 ETAB = 0x690u, NTAB = 0x68u;
+        const int e_pv = (int)((ETAB >> (2 * pv)) & 3u), n_pv = (int)((NTAB >> pv) & 1u);
+        const int e_inv = (3 - e_pv) % 3, n_inv = n_pv;  // pv^-1 = (-1)^n 2^-e
+        const int e_v = (int)((ETAB >> (2 * v)) & 3u), n_v = (int)((NTAB >> v) & 1u);
+        int e = me ? e_inv : e_v + e_inv;
+        if (e >= 3) e -= 3;
+        const u32 negm = (me ? n_inv : (n_v ^ n_inv ^ 1)) ? ~0u : 0u;
+#pragma unroll
+        for (int w = 0; w < WF; w++) {
+            const u32 a0 = __builtin_amdgcn_readlane(x[0][w], pl), a1 = __builtin_amdgcn_readlane(x[1][w], pl),
+                      a2 = __builtin_amdgcn_readlane(x[2][w], pl);
+            // times 2^e: (a0, a1, a2) -> (a2, a0, a1) per factor 2
+            u32 r0 = e == 0 ? a0 : (e == 1 ? a2 : a1);
+            u32 r1 = e == 0 ? a1 : (e == 1 ? a0 : a2);
+            u32 r2 = e == 0 ? a2 : (e == 1 ? a1 : a0);
+            const u32 flip = (a0 | a1 | a2) & negm;
+            r0 = (r0 ^ flip) & live;
+            r1 = (r1 ^ flip) & live;
+            r2 = (r2 ^ flip) & live;
+            f7_add(x[0][w] & keep, x[1][w] & keep, x[2][w] & keep, r0, r1, r2, x[0][w], x[1][w], x[2][w]);
+        }
+    }
+}
 
 // One code on one wavefront (threads 0..63 of the workgroup).
 template <int P, int WF>
 __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32 *__restrict__ rows,
                                const RunArgs args, DecompLDS &lds) {
     constexpr int R = (P == 3) ? 2 : 3;
-    uint8_t *gl = lds.gl;
     u64 *binom = lds.binom;
     int32_t *sranks = lds.sranks;
     const int lane = threadIdx.x;
-    const int n = args.n, k = args.k, flags = args.flags;
+    // the arguments arrive in vector registers (a call, not inlined): pin them
+    // to scalars so that everything derived from them is wave-uniform
+    const int n = uni(args.n), k = uni(args.k), flags = uni(args.flags);
     CodeResult &res = cs->res;
     const bool tracing = (flags & FLAG_TRACE) != 0;
     const u64 t_start = tracing ? (u64)wall_clock64() : 0;
@@ -138,59 +191,72 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
         cs->max_codewords = args.max_codewords;
     }
 
-    // -- G into LDS with independent loads, then one ballot per row, plane and
-    //    64 columns transposes it into per-lane bit-plane rows
-    const int nbytes = k * n;
-    if ((reinterpret_cast<uintptr_t>(G) & 15) == 0) {
-        const int n16 = nbytes / 16;
-        const uint4 *G4 = reinterpret_cast<const uint4 *>(G);
-        uint4 *gl4 = reinterpret_cast<uint4 *>(gl);
-#pragma unroll 8
-        for (int i = lane; i < n16; i += 64) gl4[i] = G4[i];
-        for (int i = n16 * 16 + lane; i < nbytes; i += 64) gl[i] = G[i];
-    } else {
-        for (int i = lane; i < nbytes; i += 64) gl[i] = G[i];
+    // -- one round of independent loads: lane i < k reads row i of G (k x n
+    //    bytes, row-major) as the aligned 32-bit words that cover it (reads
+    //    stay inside the aligned words that hold bytes of G)
+    constexpr int NW = 8 * WF + 1;  // covers 32 WF bytes at any alignment
+    u32 raw[NW];
+    int sh;
+    {
+        const uintptr_t g0 = reinterpret_cast<uintptr_t>(G);
+        const uintptr_t addr = g0 + (uintptr_t)(lane < k ? lane : 0) * (uintptr_t)n;
+        const u32 *src = reinterpret_cast<const u32 *>(addr & ~(uintptr_t)3);
+        const u32 *last = reinterpret_cast<const u32 *>((g0 + (uintptr_t)k * (uintptr_t)n - 1) & ~(uintptr_t)3);
+        sh = (int)(addr & 3);
+#pragma unroll
+        for (int t = 0; t < NW; t++) raw[t] = *(src + t <= last ? src + t : last);
     }
-    // binomials for the schedule by Pascal's rule, lane i holding C(c, i)
-    // (exact: every C(c, i) with c <= 64 fits 64 bits)
+    // binomials for the schedule by Pascal's rule while the loads are in
+    // flight, lane i holding C(c, i) (exact: every C(c, i) with c <= 64 fits 64 bits)
+    // (the left neighbour by a wave-wide DPP shift; lane 0 receives 0)
     {
         u64 v = (lane == 0) ? 1u : 0u;
         for (int c = 0; c <= k; c++) {
             binom[c * 65 + lane] = v;
             if (lane == 0) binom[c * 65 + 64] = (c == 64) ? 1u : 0u;
-            const u64 left = __shfl_up(v, 1);
-            if (lane >= 1) v += left;
+            const u32 llo = __builtin_amdgcn_update_dpp(0u, (u32)v, 0x138, 0xf, 0xf, false);  // wave_shr:1
+            const u32 lhi = __builtin_amdgcn_update_dpp(0u, (u32)(v >> 32), 0x138, 0xf, 0xf, false);
+            v += ((u64)lhi << 32) | llo;
         }
     }
-    __syncthreads();
-    u32 x[3][4];
-#pragma unroll
-    for (int b = 0; b < 3; b++)
-#pragma unroll
-        for (int w = 0; w < 4; w++) x[b][w] = 0;
-    bool bad = false;
-    for (int i = 0; i < k; i++) {
-#pragma unroll
-        for (int cb = 0; cb < WF; cb += 2) {
-            const int c = cb * 32 + lane;
-            const int v = (c < n) ? (int)gl[i * n + c] : 0;
-            bad |= (v >= P);
-#pragma unroll
-            for (int b = 0; b < R; b++) {
-                const u64 msk = __ballot((v >> b) & 1);
-                if (lane == i) {
-                    x[b][cb] = (u32)msk;
-                    if (cb + 1 < WF) x[b][cb + 1] = (u32)(msk >> 32);
-                }
-            }
-        }
-    }
+    // the row's bytes, realigned, into bit planes: bit b of the symbol in
+    // column c goes to bit c % 32 of x[b][c / 32]; columns >= n are cleared
+    // below, symbols >= p flag the code as invalid
     u32 colmask[4];
 #pragma unroll
     for (int w = 0; w < 4; w++) {
         const int lo = w * 32;
         colmask[w] = (n >= lo + 32) ? 0xffffffffu : (n > lo ? ((1u << (n - lo)) - 1u) : 0u);
     }
+    u32 x[3][4];
+#pragma unroll
+    for (int b = 0; b < 3; b++)
+#pragma unroll
+        for (int w = 0; w < 4; w++) x[b][w] = 0;
+    bool bad = false;
+    {
+        constexpr u32 K = (0x80u - (u32)P) * 0x01010101u;  // byte + K has bit 7 set iff byte >= P (byte < 128)
+#pragma unroll
+        for (int t = 0; t < 8 * WF; t++) {
+            const u32 wd = __builtin_amdgcn_alignbyte(raw[t + 1], raw[t], (u32)sh);  // bytes 4t .. 4t+3
+            const int valid = n - 4 * t;  // bytes of this word inside the row (uniform)
+            const u32 vm = valid >= 4 ? 0x80808080u : valid > 0 ? (0x80808080u >> (8 * (4 - valid))) : 0u;
+            bad |= ((wd | (wd + K)) & vm) != 0;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int c = 4 * t + q;
+#pragma unroll
+                for (int b = 0; b < R; b++)
+                    x[b][c >> 5] |= ((wd >> (8 * q + b)) & 1u) << (c & 31);
+            }
+        }
+        if (lane >= k) bad = false;
+#pragma unroll
+        for (int b = 0; b < 3; b++)
+#pragma unroll
+            for (int w = 0; w < 4; w++) x[b][w] = (lane < k) ? (x[b][w] & colmask[w]) : 0u;
+    }
+    __syncthreads();
     const u64 t_loaded = tracing ? (u64)wall_clock64() : 0;
 
     int status = BZ_OK;
@@ -211,62 +277,33 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
         }
         if (!anyu) break;
         // Gauss-Jordan with the unused columns first, then the used ones, each
-        // ascending; piv_lane = pivot index of this lane's row
+        // ascending; the pivot of a column is the lowest row that is not yet a
+        // pivot row and has a nonzero entry there.  piv_lane = pivot index of
+        // this lane's row; free_rows (wave-uniform) = rows not yet pivots.
         int piv_lane = -1, npiv = 0, kj = 0;
+        u64 free_rows = (k >= 64) ? ~0ull : ((1ull << k) - 1ull);
         u32 pivmask[4] = {0, 0, 0, 0};
         for (int pass = 0; pass < 2 && npiv < k; pass++) {
 #pragma unroll
             for (int w = 0; w < WF; w++) {
-                u32 bits = pass == 0 ? unused[w] : (colmask[w] & used[w]);
+                u32 bits = uni(pass == 0 ? unused[w] : (colmask[w] & used[w]));
                 while (bits && npiv < k) {
                     const int t = __builtin_ctz(bits);
                     bits &= bits - 1;
                     int v = 0;
 #pragma unroll
                     for (int b = 0; b < R; b++) v |= (int)((x[b][w] >> t) & 1u) << b;
-                    const bool cand = lane < k && piv_lane < 0 && v != 0;
-                    const u64 cm = __ballot(cand);
+                    // (the wave-uniform loop state is pinned to scalar registers)
+                    const u64 cm = uni64(__ballot(v != 0) & free_rows);
                     if (cm == 0) continue;
-                    const int pl = __ffsll((unsigned long long)cm) - 1;
+                    const int pl = uni(__builtin_ctzll(cm));
+                    free_rows = uni64(free_rows & ~(1ull << pl));
                     const int pv = __builtin_amdgcn_readlane(v, pl);
-                    const int inv = inv_mod(P, pv);
-                    // normalised pivot row, wave-uniform
-                    u32 pr[3][4];
-#pragma unroll
-                    for (int ww = 0; ww < WF; ww++) {
-                        u32 raw[3] = {0, 0, 0}, sc[3] = {0, 0, 0};
-#pragma unroll
-                        for (int b = 0; b < R; b++) raw[b] = __builtin_amdgcn_readlane(x[b][ww], pl);
-                        scale<P>(inv, raw, sc);
-#pragma unroll
-                        for (int b = 0; b < 3; b++) pr[b][ww] = sc[b];
-                    }
-                    // every row: row -= v * pivot (row + (p - v) * pivot, nothing when v = 0);
-                    // the pivot's own row becomes the normalised pivot row.  Branch-free: the
-                    // multiple is picked per lane from the p - 1 scaled copies of the pivot row.
-                    const bool me = lane == pl;
-#pragma unroll
-                    for (int ww = 0; ww < WF; ww++) {
-                        u32 sc[3] = {0, 0, 0};
-#pragma unroll
-                        for (int h = 1; h < P; h++) {
-                            u32 src[3] = {pr[0][ww], pr[1][ww], pr[2][ww]}, t[3] = {0, 0, 0};
-                            scale<P>(h, src, t);
-                            const bool pick = (v != 0) && (P - v == h);
-#pragma unroll
-                            for (int b = 0; b < 3; b++) sc[b] = pick ? t[b] : sc[b];
-                        }
-                        u32 y0, y1, y2 = 0;
-                        if constexpr (P == 3) f3_add(x[0][ww], x[1][ww], sc[0], sc[1], y0, y1);
-                        else f7_add(x[0][ww], x[1][ww], x[2][ww], sc[0], sc[1], sc[2], y0, y1, y2);
-                        x[0][ww] = me ? pr[0][ww] : y0;
-                        x[1][ww] = me ? pr[1][ww] : y1;
-                        if constexpr (P == 7) x[2][ww] = me ? pr[2][ww] : y2;
-                    }
-                    if (me) piv_lane = npiv;
-                    npiv++;
-                    if (pass == 0) kj++;
-                    pivmask[w] |= 1u << t;
+                    eliminate<P, WF>(x, v, pl, pv);
+                    piv_lane = (lane == pl) ? npiv : piv_lane;
+                    npiv = uni(npiv + 1);
+                    if (pass == 0) kj = uni(kj + 1);
+                    pivmask[w] = uni(pivmask[w] | (1u << t));
                 }
             }
         }
@@ -275,7 +312,24 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
             break;
         }
         if (kj == 0) break;
-        // -- pack Gamma_m: row piv_lane of matrix m; slot 3 of each word = OR of planes
+        // -- pack Gamma_m: row piv_lane of matrix m; slot 3 of each word = OR of planes.
+        //    Identity skip: the n-k non-pivot columns of every row compressed, in
+        //    order, into columns 0 .. n-k-1 (one column map for all rows; only
+        //    weights are used, so any fixed map would do).  The compress plans
+        //    and bit positions depend on the pivot columns only (wave-uniform).
+        Compress32 plan[WF];
+        u32 npm[WF];
+        int at[WF];
+        if (skip) {
+            int pos = 0;
+#pragma unroll
+            for (int w = 0; w < WF; w++) {
+                npm[w] = uni(colmask[w] & ~pivmask[w]);
+                plan[w] = compress_plan(npm[w]);
+                at[w] = pos;
+                pos += __builtin_popcount(npm[w]);
+            }
+        }
         if (lane < k) {
             u32 *dst = rows + (size_t)(m * BZ_MAX_K + piv_lane) * ROW_WORDS;
             u32 out[3][4];
@@ -284,62 +338,23 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
 #pragma unroll
                 for (int w = 0; w < 4; w++) out[b][w] = 0;
             if (skip) {
-                // the n-k non-pivot columns moved into columns 0 .. n-k-1: every
-                // non-pivot column at or beyond n-k takes the place of a pivot column
-                // below n-k (pairs taken in ascending order); the columns of a row
-                // can be permuted freely since only weights are used
 #pragma unroll
-                for (int b = 0; b < 3; b++)
+                for (int b = 0; b < R; b++) {
+                    u64 lo = 0, hi = 0;
 #pragma unroll
-                    for (int w = 0; w < 4; w++) out[b][w] = (w < WF) ? x[b][w] : 0u;
-                const int nk = n - k;
-                // 128-bit column sets as two 64-bit halves (wave-uniform)
-                u64 lp[2] = {0, 0}, hn[2] = {0, 0};
-#pragma unroll
-                for (int w = 0; w < 4; w++) {
-                    const int lo = w * 32;
-                    const u32 below = (nk >= lo + 32) ? 0xffffffffu : (nk > lo ? ((1u << (nk - lo)) - 1u) : 0u);
-                    lp[w >> 1] |= (u64)(pivmask[w] & below) << (32 * (w & 1));
-                    hn[w >> 1] |= (u64)(colmask[w] & ~pivmask[w] & ~below) << (32 * (w & 1));
-                }
-                // each plane as two 64-bit halves held in scalars (no indexed arrays)
-                u64 h0l = (u64)out[0][0] | ((u64)out[0][1] << 32), h0h = (u64)out[0][2] | ((u64)out[0][3] << 32);
-                u64 h1l = (u64)out[1][0] | ((u64)out[1][1] << 32), h1h = (u64)out[1][2] | ((u64)out[1][3] << 32);
-                u64 h2l = (u64)out[2][0] | ((u64)out[2][1] << 32), h2h = (u64)out[2][2] | ((u64)out[2][3] << 32);
-                for (;;) {
-                    if ((lp[0] | lp[1]) == 0 || (hn[0] | hn[1]) == 0) break;
-                    const int pa = lp[0] ? __builtin_ctzll(lp[0]) : 64 + __builtin_ctzll(lp[1]);
-                    const int pb = hn[0] ? __builtin_ctzll(hn[0]) : 64 + __builtin_ctzll(hn[1]);
-                    if (lp[0]) lp[0] &= lp[0] - 1;
-                    else lp[1] &= lp[1] - 1;
-                    if (hn[0]) hn[0] &= hn[0] - 1;
-                    else hn[1] &= hn[1] - 1;
-                    // pb >= n-k > pa: move bit pb to bit pa in every plane
-                    const u64 ma = 1ull << (pa & 63);
-                    const int sb = pb & 63;
-                    const bool la = pa < 64, lb = pb < 64;
-                    u64 b0 = ((lb ? h0l : h0h) >> sb) & 1ull, b1 = ((lb ? h1l : h1h) >> sb) & 1ull,
-                        b2 = ((lb ? h2l : h2h) >> sb) & 1ull;
-                    if (la) {
-                        h0l = (h0l & ~ma) | (b0 << (pa & 63));
-                        h1l = (h1l & ~ma) | (b1 << (pa & 63));
-                        h2l = (h2l & ~ma) | (b2 << (pa & 63));
-                    } else {
-                        h0h = (h0h & ~ma) | (b0 << (pa & 63));
-                        h1h = (h1h & ~ma) | (b1 << (pa & 63));
-                        h2h = (h2h & ~ma) | (b2 << (pa & 63));
+                    for (int w = 0; w < WF; w++) {
+                        const u64 c = compress_apply(x[b][w], npm[w], plan[w]);
+                        if (at[w] < 64) {
+                            lo |= c << at[w];
+                            if (at[w] > 32) hi |= c >> (64 - at[w]);
+                        } else {
+                            hi |= c << (at[w] - 64);
+                        }
                     }
-                }
-                out[0][0] = (u32)h0l; out[0][1] = (u32)(h0l >> 32); out[0][2] = (u32)h0h; out[0][3] = (u32)(h0h >> 32);
-                out[1][0] = (u32)h1l; out[1][1] = (u32)(h1l >> 32); out[1][2] = (u32)h1h; out[1][3] = (u32)(h1h >> 32);
-                out[2][0] = (u32)h2l; out[2][1] = (u32)(h2l >> 32); out[2][2] = (u32)h2h; out[2][3] = (u32)(h2h >> 32);
-                // clear everything from column n-k on
-#pragma unroll
-                for (int w = 0; w < 4; w++) {
-                    const int lo = w * 32;
-                    const u32 below = (nk >= lo + 32) ? 0xffffffffu : (nk > lo ? ((1u << (nk - lo)) - 1u) : 0u);
-#pragma unroll
-                    for (int b = 0; b < 3; b++) out[b][w] &= below;
+                    out[b][0] = (u32)lo;
+                    out[b][1] = (u32)(lo >> 32);
+                    out[b][2] = (u32)hi;
+                    out[b][3] = (u32)(hi >> 32);
                 }
             } else {
 #pragma unroll
@@ -398,20 +413,46 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
             s_tasks[lane] = (g <= SUBSET_G) ? small_stage_tasks(k, g) : 0;
         }
         __syncthreads();
-        // task counts of the rounds g >= 3 that the table reaches, one wave-parallel pass each
+        // task counts of the rounds g > SUBSET_G that the table reaches, one
+        // round per lane: tasks(g) = sum over q of ceil(bases(q, g) / 64) nb(q),
+        // the blocks nb(q) of a q-group being the same in every round (the sum
+        // of fill_qtable)
         const int last_g = (ns + m - 1) / m;
-        for (int gg = SUBSET_G + 1; gg <= last_g; gg++) {
-            const u64 t = wave_qtable(k, gg, s_combos[gg - 1], sweep_cap_for(P, W, args.sweep_ops), binom, nullptr);
-            if (t >= (1ull << 62)) {
-                ns = min(ns, (gg - 1) * m);
-                complete = 0;
-                break;
+        const uint32_t cap = sweep_cap_for(P, W, args.sweep_ops);
+        if (lane <= k - 3) lds.s_nb[lane] = qgroup_blocks(k, cap, lane);
+        __syncthreads();
+        const bool counted = in && g > SUBSET_G && g <= last_g;
+        u64 tg = 0;
+        if (counted) {
+            for (int q = g - 3; q <= k - 3; q++) {
+                // (ceil64 <= 2^58 and nb <= 62: the second product cannot overflow)
+                const u64 bases = sat_mul32(binom[q * 65 + (g - 3)], (uint32_t)combos);
+                tg = sat_add(tg, ceil64(bases) * (u64)lds.s_nb[q]);
             }
-            if (lane == 0) s_tasks[gg - 1] = t;
+            s_tasks[lane] = tg;
+        }
+        // the first round with 2^62 tasks or more cuts the table before it
+        const u64 over = __ballot(counted && tg >= (1ull << 62));
+        if (over) {
+            ns = min(ns, __builtin_ctzll(over) * m);
+            complete = 0;
         }
         if (ns > BZ_MAX_STAGES) {
             ns = BZ_MAX_STAGES;
             complete = 0;
+        }
+        __syncthreads();
+        // tiles of the rounds before each round (exclusive saturating scan)
+        {
+            const u64 mine_t = in ? (s_tasks[lane] + WAVES_PER_GROUP - 1) / WAVES_PER_GROUP : 0;
+            u64 it = mine_t;
+            for (int off = 1; off < 64; off <<= 1) {
+                const u64 o = __shfl_up(it, off);
+                if (lane >= off) it = sat_add(it, o);
+            }
+            u64 tb = __shfl_up(it, 1);
+            if (lane == 0) tb = 0;
+            if (in) lds.s_tbefore[lane] = tb;
         }
         __syncthreads();
     }
@@ -432,7 +473,9 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
             d.coef_combos = s_combos[g - 1];
             d.parts = (uint32_t)(d.tiles < (u64)args.grid ? d.tiles : (u64)args.grid);
             d.sweep_cap = cap;
-            d.pad = 0;
+            const u64 off = deal_offset(m, lds.s_tbefore[g - 1], j, d.tiles);
+            d.nowait = off < (u64)args.grid;
+            d.rot = deal_rot(off, args.grid);
             cs->stages[s] = d;
             res.stage_min[s] = (int)BIG;
             res.stage_count[s] = 0;
@@ -462,6 +505,7 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
         res.n_table = ns;
         res.table_complete = complete;
     }
+    if (lane < WAKE_COPIES) cs->wake[lane][0] = wake_make(0, -1);
 }
 
 template <int P, int WF>
@@ -808,6 +852,9 @@ __device__ void run_checker(CodeState *cs, const StageDesc *sdesc, int ns) {
             ok = __hip_atomic_compare_exchange_strong(&cs->res.ctl, &st, nw, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT);
         ok = __shfl(ok, 0);
+        if (ok && lane < WAKE_COPIES)
+            __hip_atomic_fetch_max(&cs->wake[lane][0], wake_make(ctl_checked(nw), ctl_term(nw)), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
         // done: the run ended, or every done stage is checked; another checker
         // moved the state first: look again
         if (ok && (stops || nd < 64)) return;
@@ -833,7 +880,13 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
     const uint32_t grid = gridDim.x, b = blockIdx.x;
     const int k = ea.k, n = ea.n;
     const bool tracing = (ea.flags & FLAG_TRACE) != 0;
-    if (tracing && threadIdx.x == 0) atomicMin((unsigned long long *)&cs->trace[1][0], (unsigned long long)wall_clock64());
+    // workgroup times from every TRACE_EVERY-th workgroup only: the real-time
+    // counter is one unit for the whole device, and a thousand workgroups
+    // reading it at the same moment (all leave a wait together) queue for tens
+    // of microseconds, which would show up as a false spread of start times
+    constexpr uint32_t TRACE_EVERY = 7;
+    const bool tr_wg = tracing && blockIdx.x % TRACE_EVERY == 0;
+    if (tr_wg && threadIdx.x == 0) atomicMin((unsigned long long *)&cs->trace[1][0], (unsigned long long)wall_clock64());
     // one round of independent loads: the decomposition's status and table
     // size, one stage descriptor per thread (ns <= BZ_MAX_STAGES = blockDim.x)
     // and the binomials
@@ -847,23 +900,25 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
     if (uni(status0) != BZ_OK) return;
     const int ns = uni(ns0);
     const bool skip = (ea.flags & FLAG_SKIP) != 0;
+    u64 *wake = &cs->wake[b % WAKE_COPIES][0];
     u32 *lh = HIST ? &lhist[wid * (BZ_MAX_N + 1)] : nullptr;
     const u32 cap = (u32)n;
     for (int s = 0; s < ns; s++) {
         const StageDesc &sd = sdesc[s];
-        if (tile_of(0, b, grid, s) >= sd.tiles) continue;  // no tile of this stage here
+        if (tile_of(0, b, grid, sd.rot) >= sd.tiles) continue;  // no tile of this stage here
+        int term0 = 0;
         if (threadIdx.x == 0) {
-            // a large stage waits until every stage before s - lookahead is checked
-            // (small ones never wait), or the run ended
+            // a stage that is not nowait waits until every stage before
+            // s - lookahead is checked, or the run ended
             // the clock and the status word are read every 256 polls only: the
             // real-time counter is one shared unit, slow when a thousand waves read it
             u64 t0 = 0;
             int term;
             u64 st;
             for (uint32_t it = 0;; it++) {
-                st = ld_poll(&cs->res.ctl);
-                term = ctl_term(st);
-                if (term >= 0 || sd.codewords <= SMALL_STAGE || ctl_checked(st) >= s - lookahead) break;
+                st = ld_poll(wake);
+                term = wake_term(st);
+                if (term >= 0 || sd.nowait || wake_checked(st) >= s - lookahead) break;
                 if ((it & 255u) == 255u) {
                     if (ld_poll(&cs->res.status) != BZ_OK) {
                         term = -2;
@@ -882,14 +937,19 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
                 __builtin_amdgcn_s_sleep(8);
             }
             s_term = term;
-            if (tracing) {
+            term0 = term;
+            if (tr_wg) {
                 const unsigned long long now = (unsigned long long)wall_clock64();
                 atomicMin((unsigned long long *)&cs->trace[2 + s][0], now);
                 atomicMax((unsigned long long *)&cs->trace[2 + s][3], now);
             }
-            s_crit = ctl_checked(st) >= s;  // the earliest unchecked stage: no later stage can wait on it
+            s_crit = wake_checked(st) >= s;  // the earliest unchecked stage: no later stage can wait on it
         }
-        if (wid == 0 && sd.g > SUBSET_G) wave_qtable(k, sd.g, sd.coef_combos, sd.sweep_cap, gbin, qtab);
+        if (wid == 0 && sd.g > SUBSET_G) {
+            // the q-groups of the stage, unless the run ended (thread 0 is lane 0 of wave 0)
+            const int tw = __builtin_amdgcn_readfirstlane(term0);
+            if (!(tw == -2 || (tw >= 0 && s > tw))) wave_qtable(k, sd.g, sd.coef_combos, sd.sweep_cap, gbin, qtab);
+        }
         __syncthreads();
         const int term = s_term;
         const bool crit = s_crit != 0;
@@ -906,11 +966,11 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
         u32 lmin = BIG;
         u64 cnt = 0;
         for (u64 r = 0;; r++) {
-            const u64 tile = tile_of(r, b, grid, s);
+            const u64 tile = tile_of(r, b, grid, sd.rot);
             if (tile >= tiles) break;  // a missing tile only happens in the last round
             if (r > 0) {
                 // a later stage after termination is abandoned (its results are never read)
-                const int t2 = uni(lane == 0 ? ctl_term(ld_poll(&cs->res.ctl)) : 0);
+                const int t2 = uni(lane == 0 ? wake_term(ld_poll(wake)) : 0);
                 if (t2 >= 0 && s > t2) break;
             }
             const u64 task = tile * WAVES_PER_GROUP + (u64)wid;
@@ -950,7 +1010,8 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
                 atomicAdd((unsigned long long *)&cs->res.stage_count[s], (unsigned long long)bc);
                 drain_vmem();  // minimum and count performed before done counts this workgroup
                 done = __hip_atomic_fetch_add(&cs->stage_done[s], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-                if (tracing) atomicMax((unsigned long long *)&cs->trace[2 + s][1], (unsigned long long)wall_clock64());
+                if (tr_wg || (tracing && done == sd.parts))  // the last one always
+                    atomicMax((unsigned long long *)&cs->trace[2 + s][1], (unsigned long long)wall_clock64());
             }
             // the last workgroup of a stage checks it (and every done stage after it)
             if (uni(done) == sd.parts) {
@@ -961,7 +1022,7 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
         }
         __syncthreads();  // qtab and red_* are rewritten by the next stage
     }
-    if (tracing && threadIdx.x == 0) atomicMax((unsigned long long *)&cs->trace[1][1], (unsigned long long)wall_clock64());
+    if (tr_wg && threadIdx.x == 0) atomicMax((unsigned long long *)&cs->trace[1][1], (unsigned long long)wall_clock64());
 }
 
 // =====================================================================
@@ -1032,7 +1093,7 @@ __global__ void features_kernel(const CodeState *__restrict__ css, const int32_t
     feat[i * 4 + 3] = (float)(cs.k - km) / 8.0f;
 }
 
-// The tiles of one part of a stage: tile_of(r, part, parts, s) for r = 0, 1, ...
+// The tiles of one part of a stage: tile_of(r, part, parts, rot) for r = 0, 1, ...
 template <int P, int W>
 __device__ u64 run_part(const StageDesc &sd, int s, uint32_t part, int k, const u32 *__restrict__ rows,
                         const u64 *sbin, const u64 *__restrict__ gbin, const QEntry *qtab, u32 woff, u32 cap,
@@ -1043,7 +1104,7 @@ __device__ u64 run_part(const StageDesc &sd, int s, uint32_t part, int k, const 
     const uint32_t parts = uni(sd.parts);
     u64 cnt = 0;
     for (u64 r = 0;; r++) {
-        const u64 tile = tile_of(r, part, parts, s);
+        const u64 tile = tile_of(r, part, parts, sd.rot);
         if (tile >= tiles) break;
         const u64 task = tile * WAVES_PER_GROUP + (u64)wid;
         if (task >= tasks) continue;

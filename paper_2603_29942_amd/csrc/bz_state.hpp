@@ -36,21 +36,28 @@ constexpr uint64_t DEFAULT_LIMIT = 1ull << 44;
 //           wave-uniform.  Blocks are sized so that a lane's sweep is bounded
 //           (the heaviest bases, with the smallest q, are split over many tasks).
 // Tasks are dealt four at a time (one per wavefront of a workgroup), round by
-// round, to the workgroups of the grid.
+// round, to the workgroups of the grid.  The deal of stage s starts at
+// workgroup off_s mod grid, off_s being the tiles of all stages before s, so
+// that the stages whose deal starts within the first pass over the grid
+// (off_s < grid) begin on workgroups of their own, at once and side by side,
+// without waiting for the checks of earlier stages ("nowait"); every later
+// stage waits (see LOOKAHEAD).
 constexpr int WAVES_PER_GROUP = 4;
 
 struct StageDesc {
     int32_t g, j;
     int32_t L;          // L_{g,j}
-    int32_t check;      // 1: test L >= U after this stage
+    int16_t check;      // 1: test L >= U after this stage
+    int16_t nowait;     // 1: off_s < grid, starts without waiting for checks
     u64 tasks;          // wave tasks in the stage
     u64 tiles;          // ceil(tasks / WAVES_PER_GROUP)
     u64 codewords;      // C(k,g) (p-1)^(g-1)
     uint32_t coef_combos;  // (p-1)^(g-3) for g >= 3, else 1
     uint32_t parts;        // workgroups that own at least one tile: min(grid, tiles)
     uint32_t sweep_cap;    // g >= 3: target (s, L) steps per lane and task
-    uint32_t pad;
+    uint32_t rot;          // (grid - off_s mod grid) mod grid, see tile_of
 };
+
 
 // Bases with top row q (g >= 3): how many, and how their rows s are blocked.
 struct QEntry {
@@ -74,6 +81,14 @@ struct CodeResult {
     u64 stage_count[BZ_MAX_STAGES];
 };
 
+// Progress word of the wake copies: stages checked (bits 0-31), terminating
+// stage + 1 (bits 32-63).  It only grows (checked grows, the terminating stage
+// is set once), so the checkers publish it with atomic max in any order.
+constexpr int WAKE_COPIES = 16;
+BZ_HD u64 wake_make(int checked, int term) { return ((u64)(uint32_t)(term + 1) << 32) | (uint32_t)checked; }
+BZ_HD int wake_checked(u64 w) { return (int)(uint32_t)w; }
+BZ_HD int wake_term(u64 w) { return (int)(w >> 32) - 1; }
+
 struct CodeState {
     CodeResult res;
     // inputs of this run
@@ -91,6 +106,10 @@ struct CodeState {
     StageDesc stages[BZ_MAX_STAGES];
     // batched runs: the stage whose parts workgroups claim (see claim_make)
     u64 claim;
+    // copies of the checker's progress for the workgroups that wait on it,
+    // one per 128-byte line (workgroup b reads copy b mod WAKE_COPIES), so
+    // that a thousand pollers do not queue on one address; see wake_make
+    u64 wake[WAKE_COPIES][16];
 };
 
 // Claim word of a code in a batch: stage + 1 (bits 48-63, 0 = nothing to
@@ -129,14 +148,12 @@ BZ_HD int ctl_checked(u64 c) { return (int)(c & 0xffff); }
 BZ_HD int ctl_term(u64 c) { return (int)((c >> 16) & 0xffff) - 1; }
 BZ_HD int ctl_U(u64 c) { return (int)((c >> 32) & 0xffff); }
 
-// Stages with at most this many combinations never wait for earlier stages.
-constexpr uint64_t SMALL_STAGE = 1ull << 22;
 
-// Workgroups start a large stage only once every stage more than LOOKAHEAD
-// places before it has been checked.  0 (the default) runs large stages one at
-// a time: work on a stage beyond the current one competes with it for the
-// vector ALUs and is thrown away when the current stage ends the run, which
-// measured slower than draining each stage first.
+// Workgroups start a stage that is not "nowait" only once every stage more
+// than LOOKAHEAD places before it has been checked.  0 (the default) runs
+// those stages one at a time: work on a stage beyond the current one competes
+// with it for the vector ALUs and is thrown away when the current stage ends
+// the run, which measured slower than draining each stage first.
 #ifndef BZ_LOOKAHEAD
 #define BZ_LOOKAHEAD 0
 #endif
@@ -147,6 +164,18 @@ BZ_HD u64 sat_mul(u64 a, u64 b) {
     return __builtin_mul_overflow(a, b, &r) ? ~0ull : r;
 }
 BZ_HD u64 sat_add(u64 a, u64 b) { return a > ~0ull - b ? ~0ull : a + b; }
+// sat_mul(a, b) for b < 2^32, from two 32 x 32 -> 64 products
+BZ_HD u64 sat_mul32(u64 a, uint32_t b) {
+    const u64 lo = (u64)(uint32_t)a * b, hi = (a >> 32) * (u64)b + (lo >> 32);
+    return (hi >> 32) ? ~0ull : (hi << 32) | (uint32_t)lo;
+}
+
+// off_s of stage (g, j): m times the tiles of the rounds before g, plus j - 1
+// times the tiles of round g (saturating; tiles_before = the first sum).
+BZ_HD u64 deal_offset(int m, u64 tiles_before, int j, u64 tiles) {
+    return sat_add(sat_mul((u64)m, tiles_before), sat_mul((u64)(j - 1), tiles));
+}
+BZ_HD uint32_t deal_rot(u64 off, uint32_t grid) { return (uint32_t)((grid - off % grid) % grid); }
 
 BZ_HD u64 binom_sat(int n, int r) {
     if (r < 0 || r > n) return 0;
@@ -176,15 +205,23 @@ BZ_HD uint32_t sweep_cap_for(int p, int W, uint32_t ops = DEFAULT_SWEEP_OPS) {
 
 // The q-group of bases with top row q (g >= 3): its number of bases and the
 // blocking of its rows s.
+BZ_HD uint32_t qgroup_rows(int k, uint32_t cap, int q) {
+    const uint32_t len = (uint32_t)(k - 2 - q);  // rows s = q+1 .. k-2; the first has len rows L
+    const uint32_t b = cap / len;
+    return b < 1 ? 1 : b;
+}
+BZ_HD uint32_t qgroup_blocks(int k, uint32_t cap, int q) {
+    const uint32_t len = (uint32_t)(k - 2 - q), b = qgroup_rows(k, cap, q);
+    return (len + b - 1) / b;
+}
 BZ_HD void qgroup(int k, int g, u64 M, uint32_t cap, const u64 *binom, int q, u64 *bases, uint32_t *B,
                   uint32_t *nb) {
     *bases = sat_mul(binom[q * 65 + (g - 3)], M);
-    const uint32_t len = (uint32_t)(k - 2 - q);  // rows s = q+1 .. k-2; the first has len rows L
-    uint32_t b = cap / len;
-    if (b < 1) b = 1;
-    *B = b;
-    *nb = (len + b - 1) / b;
+    *B = qgroup_rows(k, cap, q);
+    *nb = qgroup_blocks(k, cap, q);
 }
+// chunks of 64 bases (no overflow at the saturated value)
+BZ_HD u64 ceil64(u64 bases) { return (bases >> 6) + ((bases & 63) != 0); }
 
 // Number of tasks of a stage with g >= 3 (saturating); with tab != NULL also
 // fills the q-groups (entries for q = g-3 .. k-3, index q-(g-3)).
@@ -201,7 +238,7 @@ BZ_HD u64 fill_qtable(int k, int g, u64 M, uint32_t cap, const u64 *binom, QEntr
             e.B = B;
             e.nb = nb;
         }
-        first = sat_add(first, sat_mul((bases + 63) / 64, (u64)nb));
+        first = sat_add(first, sat_mul(ceil64(bases), (u64)nb));
     }
     return first;
 }
@@ -281,16 +318,20 @@ BZ_HD void decode_base(int g, int q, u64 M, u64 bi, Bin bin, Visit visit) {
 // Round g of the schedule (its m stages (g, 1..m) share these): the
 // combinations of one stage, C(k, g) (p-1)^(g-1), and the coefficient
 // combinations (p-1)^(g-3) of one base of g-3 rows (1 for g < 3); saturating.
-BZ_HD u64 round_codewords(int p, int k, int g, const u64 *binom) {
-    u64 pw = 1;
-    for (int t = 1; t < g; t++) pw = sat_mul(pw, (u64)(p - 1));
-    return sat_mul(binom[k * 65 + g], pw);
+// (p-1)^e, saturating (p - 1 = 2: a shift; p - 1 = 6: at most 25 steps
+// before it saturates, each a constant multiply and compare)
+BZ_HD u64 pow_sat(int p, int e) {
+    if (e <= 0) return 1;
+    if (p == 3) return e >= 64 ? ~0ull : (1ull << e);
+    u64 r = 1;
+    for (int t = 0; t < e; t++) {
+        if (r > ~0ull / 6u) return ~0ull;
+        r *= 6u;
+    }
+    return r;
 }
-BZ_HD u64 round_combos(int p, int g) {
-    u64 c = 1;
-    for (int t = 3; t < g; t++) c = sat_mul(c, (u64)(p - 1));
-    return c;
-}
+BZ_HD u64 round_codewords(int p, int k, int g, const u64 *binom) { return sat_mul(binom[k * 65 + g], pow_sat(p, g - 1)); }
+BZ_HD u64 round_combos(int p, int g) { return pow_sat(p, g - 3); }
 // Stages of round g within the codeword limit, given cum = the (saturated)
 // codewords of all earlier rounds: the largest j <= m with
 // sat(cum + j cw) <= max_codewords, or 0 when the coefficient combinations do
@@ -299,6 +340,7 @@ BZ_HD int round_stages(int m, u64 cum, u64 cw, u64 combos, u64 max_codewords) {
     if (combos >= (1ull << 32)) return 0;
     if (max_codewords == ~0ull) return m;
     if (cum > max_codewords) return 0;
+    if (sat_mul(cw, (u64)m) <= max_codewords - cum) return m;  // the usual case, without a division
     const u64 j = (max_codewords - cum) / cw;
     return j < (u64)m ? (int)j : m;
 }
@@ -339,7 +381,7 @@ BZ_HD int build_schedule(int p, int k, int m, const int32_t *ranks, int flags, u
                          uint32_t grid, int W, const u64 *binom, StageDesc *st, int *complete,
                          bool count_tasks = true, uint32_t sweep_ops = DEFAULT_SWEEP_OPS) {
     int ns = 0;
-    u64 cum = 0;
+    u64 cum = 0, tiles_before = 0;
     *complete = 1;
     const uint32_t cap = sweep_cap_for(p, W, sweep_ops);
     for (int g = 1; g <= k; g++) {
@@ -370,20 +412,23 @@ BZ_HD int build_schedule(int p, int k, int m, const int32_t *ranks, int flags, u
             d.coef_combos = (uint32_t)combos;
             d.parts = (uint32_t)(d.tiles < (u64)grid ? d.tiles : (u64)grid);
             d.sweep_cap = cap;
-            d.pad = 0;
+            const u64 off = deal_offset(m, tiles_before, j, d.tiles);
+            d.nowait = off < (u64)grid;
+            d.rot = deal_rot(off, grid);
             cum = sat_add(cum, cw);
             ns++;
         }
+        tiles_before = sat_add(tiles_before, (tasks + WAVES_PER_GROUP - 1) / WAVES_PER_GROUP);
     }
     return ns;
 }
 
-// Tile owned by workgroup b in round r of stage s.  Rounds alternate direction
-// so that the heavy-first order of the items spreads evenly over the
-// workgroups, and the deal starts at a different workgroup in every stage so
-// that the heaviest tiles of successive stages land on different workgroups.
-BZ_HD u64 tile_of(u64 r, uint32_t b, uint32_t grid, int s) {
-    const uint32_t bb = (uint32_t)((b + (u64)s * 97u) % grid);
+// Tile owned by workgroup b in round r of a stage whose deal is rotated by
+// rot.  Rounds alternate direction so that the heavy-first order of the items
+// spreads evenly over the workgroups; in round 0 workgroup off_s mod grid
+// takes tile 0, the next one tile 1, and so on.
+BZ_HD u64 tile_of(u64 r, uint32_t b, uint32_t grid, uint32_t rot) {
+    const uint32_t bb = (uint32_t)(((u64)b + rot) % grid);
     return r * grid + ((r & 1) ? (grid - 1 - bb) : bb);
 }
 

@@ -135,7 +135,8 @@ static void check_schedule() {
             int complete = 0;
             const uint32_t grid = 1000;
             int ns = build_schedule(c.p, c.k, c.m, c.ranks.data(), flags, ~0ull, grid, 2, BINOM, st, &complete);
-            u64 cum = 0;
+            u64 cum = 0, off = 0;
+            std::vector<int> owner(grid, -1);  // nowait stages that fit the grid own disjoint workgroups
             for (int s = 0; s < ns; s++) {
                 const StageDesc &d = st[s];
                 CHECK(d.g == s / c.m + 1 && d.j == s % c.m + 1);
@@ -157,16 +158,34 @@ static void check_schedule() {
                     std::vector<int> seen(d.tiles, 0);
                     for (uint32_t b = 0; b < grid; b++)
                         for (u64 r = 0;; r++) {
-                            const u64 t = tile_of(r, b, grid, s);
+                            const u64 t = tile_of(r, b, grid, d.rot);
                             if (t >= d.tiles) break;
                             seen[t]++;
                         }
                     for (u64 t = 0; t < d.tiles; t++) CHECK(seen[t] == 1);
-                    // the workgroups that own a round-0 tile are exactly d.parts many
+                    // the workgroups that own a round-0 tile are exactly d.parts many,
+                    // the ones from off_s mod grid on
                     uint32_t owners = 0;
-                    for (uint32_t b = 0; b < grid; b++) owners += tile_of(0, b, grid, s) < d.tiles;
+                    for (uint32_t b = 0; b < grid; b++) {
+                        const bool own = tile_of(0, b, grid, d.rot) < d.tiles;
+                        owners += own;
+                        CHECK(own == ((b + grid - (uint32_t)(off % grid)) % grid < d.parts));
+                    }
                     CHECK(owners == d.parts);
                 }
+                // the deal starts where the previous stage's ended; the stages that
+                // start within the first pass over the grid do not wait
+                CHECK(d.rot == (grid - off % grid) % grid);
+                CHECK(d.nowait == (off < grid));
+                if (d.nowait && off + d.tiles <= grid) {
+                    for (uint32_t b = 0; b < grid; b++) {
+                        const bool own = tile_of(0, b, grid, d.rot) < d.tiles;
+                        CHECK(own == (b >= off && b < off + d.tiles));
+                        if (own) CHECK(owner[b] == -1);
+                        if (own) owner[b] = s;
+                    }
+                }
+                off = sat_add(off, d.tiles);
                 cum = sat_add(cum, d.codewords);
                 // L_{g,j} at j = m is Algorithm 6's (m-1)(g+1) + max(0, g+1-k+k_m) when only
                 // the last matrix may be partial
@@ -240,6 +259,15 @@ static int lane_parallel_schedule(int p, int k, int m, const int *ranks, int fla
         ns = BZ_MAX_STAGES;
         *complete = 0;
     }
+    // tiles of the rounds before each round: an inclusive saturating scan over
+    // the lanes in the kernel's order (offsets 1, 2, 4, ...), then shifted by one
+    u64 scan[64];
+    for (int l = 0; l < 64; l++) scan[l] = (l < k) ? (tasks[l] + WAVES_PER_GROUP - 1) / WAVES_PER_GROUP : 0;
+    for (int off = 1; off < 64; off <<= 1) {
+        u64 nxt[64];
+        for (int l = 0; l < 64; l++) nxt[l] = l >= off ? sat_add(scan[l], scan[l - off]) : scan[l];
+        std::memcpy(scan, nxt, sizeof scan);
+    }
     for (int s = 0; s < ns; s++) {
         const int g = s / m + 1, j = s % m + 1;
         int L = 0;
@@ -255,7 +283,9 @@ static int lane_parallel_schedule(int p, int k, int m, const int *ranks, int fla
         d.coef_combos = combos[g - 1];
         d.parts = (uint32_t)(d.tiles < (u64)grid ? d.tiles : (u64)grid);
         d.sweep_cap = cap;
-        d.pad = 0;
+        const u64 off = deal_offset(m, g >= 2 ? scan[g - 2] : 0, j, d.tiles);
+        d.nowait = off < (u64)grid;
+        d.rot = deal_rot(off, grid);
     }
     return ns;
 }
@@ -429,8 +459,41 @@ static void check_unrank() {
     if (fails == before) std::printf("OK unrank\n");
 }
 
+// Bit helpers of the decomposition against plain definitions: compress (the
+// masked bits of x in order, to the low end), the saturating products and
+// powers against step-by-step saturation.
+static void check_bits() {
+    const int before = fails;
+    std::mt19937_64 rng(777);
+    for (int it = 0; it < 200000; it++) {
+        u32 x = (u32)rng(), m = (u32)rng();
+        if (it % 4 == 1) m &= (u32)rng();
+        if (it % 4 == 2) m |= (u32)rng();
+        if (it % 97 == 0) m = 0;
+        if (it % 89 == 0) m = ~0u;
+        u32 want = 0;
+        int o = 0;
+        for (int i = 0; i < 32; i++)
+            if ((m >> i) & 1u) want |= ((x >> i) & 1u) << o++;
+        CHECK(compress_apply(x, m, compress_plan(m)) == want);
+    }
+    for (int it = 0; it < 200000; it++) {
+        const u64 a = rng() >> (rng() % 64);
+        const uint32_t b = (uint32_t)(rng() >> (rng() % 32 + 32));
+        CHECK(sat_mul32(a, b) == sat_mul(a, (u64)b));
+    }
+    for (int p : {3, 7})
+        for (int e = -2; e <= 70; e++) {
+            u64 r = 1;
+            for (int t = 0; t < e; t++) r = sat_mul(r, (u64)(p - 1));
+            CHECK(pow_sat(p, e) == r);
+        }
+    if (fails == before) std::printf("OK bits\n");
+}
+
 int main() {
     fill_binomials(BINOM);
+    check_bits();
     for (int a = 0; a <= 64; a++)
         for (int b = 0; b <= 64; b++) CHECK(binom_sat(a, b) == ~0ull || BINOM[a * 65 + b] == binom_sat(a, b));
     check_arith();
