@@ -112,6 +112,14 @@ typedef struct {
                                  are those of every seventh workgroup (the device's one
                                  real-time counter slows down when a thousand workgroups
                                  read it at once); "checked" is exact */
+    int32_t cooperative;      /* 1: launch the persistent enumeration kernel with
+                                 hipLaunchCooperativeKernel, which guarantees that all its
+                                 workgroups are resident at once (about 11 us more per call);
+                                 0 (default): an ordinary launch sized to the device's
+                                 occupancy.  The plain path deals its tiles to fixed
+                                 workgroups, so with an ordinary launch a workgroup kept off
+                                 the device by other kernels delays the run until it starts
+                                 (or until wait_timeout_s, BZ_ERR_DEVICE) */
 } bz_options;
 
 /* Fill *o with the defaults above. */
@@ -159,6 +167,10 @@ typedef struct {
     int32_t timing;          /* 1: fill the two fields below (HIP events on the stream) */
     float decompose_ms;      /* out: decomposition launch */
     float enum_ms;           /* out: enumeration launch */
+    int32_t cooperative;     /* 1: hipLaunchCooperativeKernel for the persistent launch; 0
+                                (default): an ordinary launch (the batched kernel hands out
+                                work dynamically, so it never waits for a workgroup that has
+                                not started) */
 } bz_batch_options;
 
 void bz_default_batch_options(bz_batch_options *o);
@@ -202,6 +214,7 @@ typedef struct {
     int32_t device;
     int32_t wait_timeout_s;   /* as in bz_batch_options */
     int32_t max_n;            /* largest n accepted, 0 = 128; sizes each slot */
+    int32_t cooperative;      /* as in bz_batch_options */
 } bz_server_options;
 
 void bz_default_server_options(bz_server_options *o);

@@ -49,7 +49,8 @@ class bz_options(ctypes.Structure):
                 ("hist_out", ctypes.POINTER(ctypes.c_uint64)), ("max_codewords", ctypes.c_uint64),
                 ("hip_stream", ctypes.c_void_p), ("device", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("wait_timeout_s", ctypes.c_int32), ("trace_out", ctypes.POINTER(ctypes.c_uint64))]
+                ("wait_timeout_s", ctypes.c_int32), ("trace_out", ctypes.POINTER(ctypes.c_uint64)),
+                ("cooperative", ctypes.c_int32)]
 
 
 class bz_code(ctypes.Structure):
@@ -62,14 +63,14 @@ class bz_batch_options(ctypes.Structure):
                 ("identity_skip", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("max_codewords", ctypes.c_uint64), ("hip_stream", ctypes.c_void_p),
                 ("device", ctypes.c_int32), ("wait_timeout_s", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("decompose_ms", ctypes.c_float), ("enum_ms", ctypes.c_float)]
+                ("decompose_ms", ctypes.c_float), ("enum_ms", ctypes.c_float), ("cooperative", ctypes.c_int32)]
 
 
 class bz_server_options(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_int32), ("policy", ctypes.c_int32), ("mlp_params", ctypes.c_void_p),
                 ("check", ctypes.c_int32), ("identity_skip", ctypes.c_int32), ("max_codewords", ctypes.c_uint64),
                 ("blocks_per_cu", ctypes.c_int32), ("device", ctypes.c_int32), ("wait_timeout_s", ctypes.c_int32),
-                ("max_n", ctypes.c_int32)]
+                ("max_n", ctypes.c_int32), ("cooperative", ctypes.c_int32)]
 
 
 SERVE_FIFO, SERVE_PREDICTED = 0, 1
@@ -181,10 +182,11 @@ def result_dict(st, r, hist=None):
 
 
 def min_distance(p, G, *, check="stage", no_termination=False, identity_skip=True, max_codewords=0,
-                 histograms=False, blocks_per_cu=0, trace=False):
+                 histograms=False, blocks_per_cu=0, trace=False, cooperative=False):
     """Convenience wrapper: same keys as the oracle's result dict (plus
     ``trace``, the device timeline in ns, when asked for)."""
     o = bz_default_options()
+    o.cooperative = int(bool(cooperative))
     tr = None
     if trace:
         tr = np.zeros((MAX_STAGES + 2, 4), dtype=np.uint64)
@@ -256,7 +258,8 @@ def bz_min_distance_batch(buf, descs, options=None):
 
 
 def min_distance_batch(codes, *, check="stage", no_termination=False, identity_skip=True, max_codewords=0,
-                       blocks_per_cu=0, sweep_ops=None, device=None, timing=False, wait_timeout_s=0):
+                       blocks_per_cu=0, sweep_ops=None, device=None, timing=False, wait_timeout_s=0,
+                       cooperative=False):
     """Convenience wrapper: one result dict per code (same keys as
     min_distance).  sweep_ops: None, an int for every code, or a function
     (p, W) -> int (e.g. the autotuner's table)."""
@@ -277,6 +280,7 @@ def min_distance_batch(codes, *, check="stage", no_termination=False, identity_s
     o.blocks_per_cu = int(blocks_per_cu)
     o.timing = int(bool(timing))
     o.wait_timeout_s = int(wait_timeout_s)
+    o.cooperative = int(bool(cooperative))
     st, res, o = bz_min_distance_batch(buf, descs, o)
     if st != OK:
         raise RuntimeError(f"bz_min_distance_batch: {bz_status_str(st)}")

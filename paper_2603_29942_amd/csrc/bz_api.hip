@@ -130,7 +130,11 @@ hipError_t launch_decompose(int WF, const uint8_t *G, CodeState *cs, u32 *rows, 
 // (see enum_grid) is clamped to the kernel's occupancy.
 template <int P, int W, bool H>
 hipError_t launch_enum_one(int grid, CodeState *cs, const u32 *rows, const u64 *binom, u64 *hist, EnumArgs ea,
-                           hipStream_t s) {
+                           bool coop, hipStream_t s) {
+    if (!coop) {
+        enum_kernel<P, W, H><<<grid, 256, 0, s>>>(cs, rows, binom, hist, ea);
+        return hipGetLastError();
+    }
     void *args[] = {&cs, &rows, &binom, &hist, &ea};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(enum_kernel<P, W, H>), dim3(grid), dim3(256),
                                       args, 0, s);
@@ -138,20 +142,20 @@ hipError_t launch_enum_one(int grid, CodeState *cs, const u32 *rows, const u64 *
 
 template <int P, bool H>
 hipError_t launch_enum_h(int W, int grid, CodeState *cs, const u32 *rows, const u64 *binom, u64 *hist, EnumArgs ea,
-                         hipStream_t s) {
+                         bool coop, hipStream_t s) {
     switch (W) {
-    case 1: return launch_enum_one<P, 1, H>(grid, cs, rows, binom, hist, ea, s);
-    case 2: return launch_enum_one<P, 2, H>(grid, cs, rows, binom, hist, ea, s);
-    case 3: return launch_enum_one<P, 3, H>(grid, cs, rows, binom, hist, ea, s);
-    default: return launch_enum_one<P, 4, H>(grid, cs, rows, binom, hist, ea, s);
+    case 1: return launch_enum_one<P, 1, H>(grid, cs, rows, binom, hist, ea, coop, s);
+    case 2: return launch_enum_one<P, 2, H>(grid, cs, rows, binom, hist, ea, coop, s);
+    case 3: return launch_enum_one<P, 3, H>(grid, cs, rows, binom, hist, ea, coop, s);
+    default: return launch_enum_one<P, 4, H>(grid, cs, rows, binom, hist, ea, coop, s);
     }
 }
 
 template <int P>
 hipError_t launch_enum(bool hist_mode, int W, int grid, CodeState *cs, const u32 *rows, const u64 *binom, u64 *hist,
-                       EnumArgs ea, hipStream_t s) {
-    return hist_mode ? launch_enum_h<P, true>(W, grid, cs, rows, binom, hist, ea, s)
-                     : launch_enum_h<P, false>(W, grid, cs, rows, binom, hist, ea, s);
+                       EnumArgs ea, bool coop, hipStream_t s) {
+    return hist_mode ? launch_enum_h<P, true>(W, grid, cs, rows, binom, hist, ea, coop, s)
+                     : launch_enum_h<P, false>(W, grid, cs, rows, binom, hist, ea, coop, s);
 }
 
 // Largest grid the enumeration kernel may get for (p, W, histograms): the
@@ -395,8 +399,9 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, c
     ea.flags = flags;
     ea.lookahead = LOOKAHEAD;
     ea.timeout_ticks = timeout;
-    HIP_OK(p == 3 ? launch_enum<3>(o.histograms != 0, W, grid, c->cs, c->rows, c->binom, c->hist, ea, s)
-                  : launch_enum<7>(o.histograms != 0, W, grid, c->cs, c->rows, c->binom, c->hist, ea, s));
+    const bool coop = o.cooperative != 0;
+    HIP_OK(p == 3 ? launch_enum<3>(o.histograms != 0, W, grid, c->cs, c->rows, c->binom, c->hist, ea, coop, s)
+                  : launch_enum<7>(o.histograms != 0, W, grid, c->cs, c->rows, c->binom, c->hist, ea, coop, s));
     if (o.timing) HIP_OK(hipEventRecord(c->ev[2], s));
     HIP_OK(hipMemcpyAsync(c->host_res, &c->cs->res, sizeof(CodeResult), hipMemcpyDeviceToHost, s));
     if (o.histograms)
@@ -520,10 +525,9 @@ int bz_min_distance_batch(int ncodes, const bz_code *codes, const uint8_t *G, ui
         const uint32_t *yield = nullptr;
         uint32_t *done = nullptr;
         void *args[] = {&css, &cds, &nc, &rows, &bin, &bs, &to, &order, &yield, &done};
-        if (wmax <= 2)
-            HIP_OK(hipLaunchCooperativeKernel((const void *)enum_batch_kernel<2>, dim3(grid), dim3(256), args, 0, s));
-        else
-            HIP_OK(hipLaunchCooperativeKernel((const void *)enum_batch_kernel<4>, dim3(grid), dim3(256), args, 0, s));
+        const void *fn = wmax <= 2 ? (const void *)enum_batch_kernel<2> : (const void *)enum_batch_kernel<4>;
+        if (o.cooperative) HIP_OK(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(256), args, 0, s));
+        else HIP_OK(hipLaunchKernel(fn, dim3(grid), dim3(256), args, 0, s));
     }
     if (o.timing) HIP_OK(hipEventRecord(c->ev[2], s));
     HIP_OK(hipMemcpy2DAsync(c->b_host_res, sizeof(CodeResult), &c->b_cs->res, sizeof(CodeState),
@@ -725,8 +729,10 @@ hipError_t server_launch(bz_server *s, int nactive) {
     const uint32_t *yield = s->yield_dev;
     uint32_t *done = s->done_dev;
     void *args[] = {&css, &cds, &nc, &rows, &bin, &bs, &to, &order, &yield, &done};
-    return hipLaunchCooperativeKernel((const void *)enum_batch_kernel<WMAX>, dim3(s->grid), dim3(256), args, 0,
-                                      s->run);
+    if (s->o.cooperative)
+        return hipLaunchCooperativeKernel((const void *)enum_batch_kernel<WMAX>, dim3(s->grid), dim3(256), args, 0,
+                                          s->run);
+    return hipLaunchKernel((const void *)enum_batch_kernel<WMAX>, dim3(s->grid), dim3(256), args, 0, s->run);
 }
 
 // Admit queued requests into free slots, decompose them, order the active

@@ -73,7 +73,7 @@ def test_batch_mixed_equals_plain_and_oracle(bz, oracle):
 
 
 @pytest.mark.parametrize("opts", [dict(check="round"), dict(identity_skip=False),
-                                  dict(no_termination=True, max_codewords=3_000_000)])
+                                  dict(no_termination=True, max_codewords=3_000_000), dict(cooperative=True)])
 def test_batch_options_equal_plain(bz, opts):
     import torch
     cs = mixed_codes()[:16] + synth.batch_codes(3, count=16)

@@ -250,6 +250,20 @@ def test_device_input_and_determinism(bz, oracle):
             same(bz.min_distance(p, G, blocks_per_cu=bpc), ref)
 
 
+def test_cooperative_launch_same_results(bz, oracle):
+    """The persistent kernel launched with co-residency guaranteed
+    (hipLaunchCooperativeKernel) and as an ordinary launch: identical runs."""
+    for cfg, seed in [(1, 3), (2, 1)]:
+        p, G = synth.config_code(cfg, seed)
+        say(f"case cooperative cfg{cfg} seed={seed}")
+        ref = oracle.min_distance(p, G) if cfg == 1 else None
+        a = bz.min_distance(p, G, cooperative=True)
+        b = bz.min_distance(p, G, cooperative=False)
+        assert a == b
+        if ref is not None:
+            same(a, ref)
+
+
 def test_config2_full_size(bz, oracle):
     """F_3 [72,36]: the whole run against the oracle."""
     for seed in (0, 2):
