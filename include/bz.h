@@ -149,7 +149,7 @@ const char *bz_status_str(int status);
 typedef struct {
     int32_t p, n, k;      /* as for bz_min_distance */
     int32_t sweep_ops;    /* VALU operations per lane and task (the size of a unit of
-                             work), 0 = default 3000; chosen per (p, words) by the
+                             work), 0 = default 4500; chosen per (p, words) by the
                              autotuner; results do not depend on it */
     uint64_t g_offset;    /* byte offset of this code's k x n row-major generator in G */
 } bz_code;

@@ -82,9 +82,9 @@ __device__ __forceinline__ u64 wave_qtable(int k, int g, u64 M, uint32_t cap, co
     const int q = g - 3 + lane;
     const bool in = q <= k - 3;
     u64 bases = 0, val = 0;
-    uint32_t B = 1, nb = 0;
+    uint32_t nb = 0;
     if (in) {
-        qgroup(k, g, M, cap, binom, q, &bases, &B, &nb);
+        qgroup(k, g, M, cap, binom, q, &bases, &nb);
         val = ceil64(bases) * (u64)nb;  // <= 2^58 * 62: no overflow
     }
     // inclusive scan of val over the lanes (saturating)
@@ -97,8 +97,8 @@ __device__ __forceinline__ u64 wave_qtable(int k, int g, u64 M, uint32_t cap, co
         QEntry &e = tab[lane];
         e.first = inc - val;
         e.bases = bases;
-        e.B = B;
         e.nb = nb;
+        e.pad = 0;
     }
     return uni64(__shfl(inc, 63));
 }
@@ -787,12 +787,12 @@ __device__ u64 run_base_task(const StageDesc &sd, int k, int j, const u32 *__res
     const int q = g - 3 + qi;
     // the q-group's entry as wave-uniform (scalar) values
     const u64 e_first = uni64(qtab[qi].first), e_bases = uni64(qtab[qi].bases);
-    const uint32_t e_B = uni(qtab[qi].B), e_nb = uni(qtab[qi].nb);
+    const uint32_t e_nb = uni(qtab[qi].nb);
     const u64 local = task - e_first;
     const u64 chunk = local / e_nb;
     const int block = (int)(local - chunk * e_nb);
-    const int s_lo = q + 1 + block * (int)e_B;
-    const int s_hi = min(s_lo + (int)e_B, k - 1);
+    const int s_lo = q + 1 + uni(qgroup_block_start(k, q, e_nb, (uint32_t)block));
+    const int s_hi = q + 1 + uni(qgroup_block_start(k, q, e_nb, (uint32_t)block + 1));
     const u64 bi = chunk * 64 + (u64)lane;
     const bool valid = bi < e_bases;
     u32 Q[3][W];

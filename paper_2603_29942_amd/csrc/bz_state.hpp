@@ -33,8 +33,10 @@ constexpr uint64_t DEFAULT_LIMIT = 1ull << 44;
 //           multiplier.  Bases are grouped by q.  A task is (q, a chunk of 64
 //           bases, a block of consecutive rows s): each lane holds one base, and
 //           all lanes share q and the rows s, so the sweeps over L are
-//           wave-uniform.  Blocks are sized so that a lane's sweep is bounded
-//           (the heaviest bases, with the smallest q, are split over many tasks).
+//           wave-uniform.  Row s sweeps k-1-s last rows, so the rows of a
+//           q-group weigh len, len-1, ..., 1 (len = k-2-q); the blocks split
+//           that total into nearly equal parts of at most about `cap` (s, L)
+//           steps, which keeps every task of a stage about equally long.
 // Tasks are dealt four at a time (one per wavefront of a workgroup), round by
 // round, to the workgroups of the grid.  The deal of stage s starts at
 // workgroup off_s mod grid, off_s being the tiles of all stages before s, so
@@ -63,8 +65,8 @@ struct StageDesc {
 struct QEntry {
     u64 first;     // first task of the group
     u64 bases;     // C(q, g-3) (p-1)^(g-3)
-    uint32_t B;    // rows s per block
-    uint32_t nb;   // blocks: ceil((k-2-q) / B)
+    uint32_t nb;   // blocks of rows s, see qgroup_blocks
+    uint32_t pad;
 };
 
 // Results the host reads back (kept contiguous and first in CodeState).
@@ -196,7 +198,10 @@ BZ_HD int bound_c(int g, int k, int kj) {
 // Target (s, L) steps per lane in one task: about `ops` VALU operations, from
 // the per-step cost of the completions (F_3: two prefixes, add and subtract;
 // F_7: six prefixes, three rotations, add and subtract).
-constexpr uint32_t DEFAULT_SWEEP_OPS = 3000;
+#ifndef BZ_SWEEP_OPS
+#define BZ_SWEEP_OPS 4500
+#endif
+constexpr uint32_t DEFAULT_SWEEP_OPS = BZ_SWEEP_OPS;
 BZ_HD uint32_t sweep_cap_for(int p, int W, uint32_t ops = DEFAULT_SWEEP_OPS) {
     const uint32_t per = (p == 3) ? 2u * (6u * (uint32_t)W + 1u) : 6u * (25u * (uint32_t)W + 3u);
     const uint32_t cap = (ops ? ops : DEFAULT_SWEEP_OPS) / per;
@@ -204,20 +209,32 @@ BZ_HD uint32_t sweep_cap_for(int p, int W, uint32_t ops = DEFAULT_SWEEP_OPS) {
 }
 
 // The q-group of bases with top row q (g >= 3): its number of bases and the
-// blocking of its rows s.
-BZ_HD uint32_t qgroup_rows(int k, uint32_t cap, int q) {
-    const uint32_t len = (uint32_t)(k - 2 - q);  // rows s = q+1 .. k-2; the first has len rows L
-    const uint32_t b = cap / len;
-    return b < 1 ? 1 : b;
-}
+// blocking of its rows s = q+1 .. k-2.  Row q+1+i sweeps len-i last rows
+// (len = k-2-q), so the first i rows hold P(i) = i len - i(i-1)/2 steps and
+// all of them T = len(len+1)/2.  nb = min(len, ceil(T / cap)) blocks; block
+// b starts at row offset max(b, the least i with nb P(i) >= b T): equal
+// shares of T, except that a row heavier than a share is a block of its own
+// (the rows get lighter as s grows, so those come first, and every block
+// holds at least one row).
 BZ_HD uint32_t qgroup_blocks(int k, uint32_t cap, int q) {
-    const uint32_t len = (uint32_t)(k - 2 - q), b = qgroup_rows(k, cap, q);
-    return (len + b - 1) / b;
+    const uint32_t len = (uint32_t)(k - 2 - q), T = len * (len + 1) / 2;
+    const uint32_t nb = (T + cap - 1) / cap;
+    return nb > len ? len : (nb < 1 ? 1 : nb);
 }
-BZ_HD void qgroup(int k, int g, u64 M, uint32_t cap, const u64 *binom, int q, u64 *bases, uint32_t *B,
-                  uint32_t *nb) {
+BZ_HD int qgroup_block_start(int k, int q, uint32_t nb, uint32_t b) {
+    const uint32_t len = (uint32_t)(k - 2 - q), T = len * (len + 1) / 2;
+    const uint32_t target = b * T;  // <= 62 * 1953: fits 32 bits
+    uint32_t lo = 0, hi = len;      // nb P(len) = nb T >= target
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        const uint32_t P = mid * len - mid * (mid - 1) / 2;
+        if (nb * P >= target) hi = mid;
+        else lo = mid + 1;
+    }
+    return (int)(lo > b ? lo : b);
+}
+BZ_HD void qgroup(int k, int g, u64 M, uint32_t cap, const u64 *binom, int q, u64 *bases, uint32_t *nb) {
     *bases = sat_mul(binom[q * 65 + (g - 3)], M);
-    *B = qgroup_rows(k, cap, q);
     *nb = qgroup_blocks(k, cap, q);
 }
 // chunks of 64 bases (no overflow at the saturated value)
@@ -229,14 +246,14 @@ BZ_HD u64 fill_qtable(int k, int g, u64 M, uint32_t cap, const u64 *binom, QEntr
     u64 first = 0;
     for (int q = g - 3; q <= k - 3; q++) {
         u64 bases;
-        uint32_t B, nb;
-        qgroup(k, g, M, cap, binom, q, &bases, &B, &nb);
+        uint32_t nb;
+        qgroup(k, g, M, cap, binom, q, &bases, &nb);
         if (tab) {
             QEntry &e = tab[q - (g - 3)];
             e.first = first;
             e.bases = bases;
-            e.B = B;
             e.nb = nb;
+            e.pad = 0;
         }
         first = sat_add(first, sat_mul(ceil64(bases), (u64)nb));
     }

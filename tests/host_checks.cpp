@@ -411,13 +411,18 @@ static void check_unrank() {
                             const u64 local = t - e.first;
                             const u64 chunk = local / e.nb;
                             const int block = (int)(local - chunk * e.nb);
-                            const int s_lo = q + 1 + block * (int)e.B;
-                            const int s_hi = std::min(s_lo + (int)e.B, k - 1);
-                            CHECK(s_lo < s_hi);
-                            // a lane's (s, L) steps in one task stay near the cap
+                            const int s_lo = q + 1 + qgroup_block_start(k, q, e.nb, (uint32_t)block);
+                            const int s_hi = q + 1 + qgroup_block_start(k, q, e.nb, (uint32_t)block + 1);
+                            CHECK(s_lo < s_hi && s_hi <= k - 1);
+                            if (block == 0) CHECK(s_lo == q + 1);
+                            if (block + 1 == (int)e.nb) CHECK(s_hi == k - 1);
+                            // a lane's (s, L) steps in one task: at most one share of the
+                            // group's total plus one row, or a single row
                             int steps = 0;
                             for (int s = s_lo; s < s_hi; s++) steps += k - 1 - s;
-                            CHECK(steps <= (int)std::max<uint32_t>(d.sweep_cap, (uint32_t)(k - 2 - q)));
+                            const int len = k - 2 - q, T = len * (len + 1) / 2;
+                            CHECK(steps <= std::max(len, (T + (int)e.nb - 1) / (int)e.nb + len));
+                            CHECK(s_hi - s_lo == 1 || steps <= 2 * (int)d.sweep_cap);
                             u64 nvalid = 0;
                             for (int l = 0; l < 64; l++) {
                                 const u64 bi = chunk * 64 + (u64)l;
@@ -491,9 +496,37 @@ static void check_bits() {
     if (fails == before) std::printf("OK bits\n");
 }
 
+// The blocks of rows s of every q-group: they partition the rows in order,
+// none is empty, and each holds at most one share of the group's steps plus
+// one row (or is a single row).
+static void check_blocks() {
+    const int before = fails;
+    for (int k = 3; k <= 64; k++)
+        for (int q = 0; q <= k - 3; q++)
+            for (uint32_t cap : {1u, 2u, 4u, 7u, 17u, 57u, 115u, 300u, 2000u, 100000u}) {
+                const uint32_t nb = qgroup_blocks(k, cap, q);
+                const int len = k - 2 - q, T = len * (len + 1) / 2;
+                CHECK(nb >= 1 && (int)nb <= len);
+                CHECK((int)nb == std::min(len, (T + (int)cap - 1) / (int)cap));
+                int prev = qgroup_block_start(k, q, nb, 0);
+                CHECK(prev == 0);
+                for (uint32_t b = 1; b <= nb; b++) {
+                    const int st = qgroup_block_start(k, q, nb, b);
+                    CHECK(st > prev);
+                    int steps = 0;
+                    for (int i = prev; i < st; i++) steps += len - i;
+                    CHECK(st - prev == 1 || steps <= (T + (int)nb - 1) / (int)nb + len);
+                    prev = st;
+                }
+                CHECK(prev == len);
+            }
+    if (fails == before) std::printf("OK blocks\n");
+}
+
 int main() {
     fill_binomials(BINOM);
     check_bits();
+    check_blocks();
     for (int a = 0; a <= 64; a++)
         for (int b = 0; b <= 64; b++) CHECK(binom_sat(a, b) == ~0ull || BINOM[a * 65 + b] == binom_sat(a, b));
     check_arith();
