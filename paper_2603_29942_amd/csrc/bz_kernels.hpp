@@ -802,10 +802,10 @@ __device__ u64 run_base_task(const StageDesc &sd, int k, int j, const u32 *__res
         for (int w = 0; w < W; w++) Q[b][w] = 0;
     if (valid) {
         decode_base<P>(g, q, M, bi, [&](int c, int i) { return binom_at(sbin, gbin, c, i); },
-                    [&](int row, int coef) {
-                        const Row<W> r = load_row<P, W>(rows, j, row);
-                        add_scaled<P, W>(Q, r.p, coef);
-                    });
+                       [&](int row, int coef) {
+                           const Row<W> r = load_row<P, W>(rows, j, row);
+                           add_scaled<P, W>(Q, r.p, coef);
+                       });
     }
     const u64 nact = (u64)__popcll(__ballot(valid));
     u64 cnt = 0;

@@ -284,57 +284,79 @@ BZ_HD int qtable_find(const QEntry *tab, int nq, u64 t) {
     return lo;
 }
 
+// The largest c in [i-1, hi] with C(c, i) <= rho, given rho < C(hi+1, i):
+// the next row of a colex unranking.  For i = 1 that is rho itself; larger i
+// search the table (measured faster than starting from the root of
+// C(c, i) = rho and stepping to the exact answer).
+template <typename Bin>
+BZ_HD int top_row(u64 rho, int i, int hi, Bin bin) {
+    if (i == 1) return (int)rho;
+    int lo = i - 1, h = hi;
+    while (lo < h) {
+        const int mid = (lo + h + 1) >> 1;
+        if (bin(mid, i) <= rho) lo = mid;
+        else h = mid - 1;
+    }
+    return lo;
+}
+
 // Decode base number bi (< bases) of the group with top row q: its lower rows
 // (the (g-3)-subset of {0..q-1} of colex rank bi / M, M = (p-1)^(g-3)) and the
 // coefficients from the base-(p-1) digits of bi % M, least significant first.
-// visit(row, coef) is called for every row of the base, the top row q first.
-// The lowest row of the base gets coefficient 1.  bin(c, i) returns C(c, i).
-// M < 2^32 (the schedule guarantees it), so the digits are 32-bit work with a
-// constant divisor; the rank takes a shift (p = 3) or one division by M.
-template <int P, typename Bin, typename Visit>
-BZ_HD void decode_base(int g, int q, u64 M, u64 bi, Bin bin, Visit visit) {
+// The lowest row of the base gets coefficient 1.  BaseCursor yields the rows
+// one at a time, the top row q first: first() then next() for i = g-3 .. 1.
+struct BaseCursor {
+    u64 rho;      // colex rank still to decode
+    uint32_t ci;  // coefficient digits still to use
+    int hi;       // the next row is below hi + 1
+};
+template <int P>
+BZ_HD BaseCursor base_first(int g, int q, u64 M, u64 bi, int *coef) {
     const int t = g - 3;  // lower rows
-    u64 rho;
-    uint32_t ci;
+    BaseCursor c;
     if (P == 3) {
-        rho = bi >> t;
-        ci = (uint32_t)bi & (uint32_t)(M - 1);
+        c.rho = bi >> t;
+        c.ci = (uint32_t)bi & (uint32_t)(M - 1);
     } else if ((bi >> 32) == 0) {
         const uint32_t b32 = (uint32_t)bi, r = b32 / (uint32_t)M;
-        rho = r;
-        ci = b32 - r * (uint32_t)M;
+        c.rho = r;
+        c.ci = b32 - r * (uint32_t)M;
     } else {
-        rho = bi / M;
-        ci = (uint32_t)(bi - rho * M);
+        c.rho = bi / M;
+        c.ci = (uint32_t)(bi - c.rho * M);
     }
-    int coef = 1;
+    *coef = 1;
     if (t > 0) {
-        coef = (int)(ci % (uint32_t)(P - 1)) + 1;
-        ci /= (uint32_t)(P - 1);
+        *coef = (int)(c.ci % (uint32_t)(P - 1)) + 1;
+        c.ci /= (uint32_t)(P - 1);
     }
+    c.hi = q - 1;
+    return c;
+}
+template <int P, typename Bin>
+BZ_HD int base_next(BaseCursor &c, int i, Bin bin, int *coef) {
+    const int lo = top_row(c.rho, i, c.hi, bin);
+    c.rho -= bin(lo, i);
+    c.hi = lo - 1;
+    *coef = 1;
+    if (i > 1) {
+        *coef = (int)(c.ci % (uint32_t)(P - 1)) + 1;
+        c.ci /= (uint32_t)(P - 1);
+    }
+    return lo;
+}
+// visit(row, coef) for every row of the base, the top row q first.
+template <int P, typename Bin, typename Visit>
+BZ_HD void decode_base(int g, int q, u64 M, u64 bi, Bin bin, Visit visit) {
+    int coef;
+    BaseCursor c = base_first<P>(g, q, M, bi, &coef);
     visit(q, coef);
-    int hi = q - 1;
-    for (int i = t; i >= 1; i--) {
-        int lo = i - 1, h = hi;
-        while (lo < h) {
-            const int mid = (lo + h + 1) >> 1;
-            if (bin(mid, i) <= rho) lo = mid;
-            else h = mid - 1;
-        }
-        rho -= bin(lo, i);
-        hi = lo - 1;
-        int cf = 1;
-        if (i > 1) {
-            cf = (int)(ci % (uint32_t)(P - 1)) + 1;
-            ci /= (uint32_t)(P - 1);
-        }
-        visit(lo, cf);
+    for (int i = g - 3; i >= 1; i--) {
+        const int row = base_next<P>(c, i, bin, &coef);
+        visit(row, coef);
     }
 }
 
-// Round g of the schedule (its m stages (g, 1..m) share these): the
-// combinations of one stage, C(k, g) (p-1)^(g-1), and the coefficient
-// combinations (p-1)^(g-3) of one base of g-3 rows (1 for g < 3); saturating.
 // (p-1)^e, saturating (p - 1 = 2: a shift; p - 1 = 6: at most 25 steps
 // before it saturates, each a constant multiply and compare)
 BZ_HD u64 pow_sat(int p, int e) {
@@ -347,6 +369,9 @@ BZ_HD u64 pow_sat(int p, int e) {
     }
     return r;
 }
+// Round g of the schedule (its m stages (g, 1..m) share these): the
+// combinations of one stage, C(k, g) (p-1)^(g-1), and the coefficient
+// combinations (p-1)^(g-3) of one base of g-3 rows (1 for g < 3); saturating.
 BZ_HD u64 round_codewords(int p, int k, int g, const u64 *binom) { return sat_mul(binom[k * 65 + g], pow_sat(p, g - 1)); }
 BZ_HD u64 round_combos(int p, int g) { return pow_sat(p, g - 3); }
 // Stages of round g within the codeword limit, given cum = the (saturated)
@@ -376,12 +401,7 @@ BZ_HD void decode_subset(u64 r, int k, Bin bin, int (&rows)[G]) {
     int hi = k - 1;
 #pragma unroll
     for (int t = G; t >= 1; t--) {
-        int lo = t - 1, h = hi;
-        while (lo < h) {
-            const int mid = (lo + h + 1) >> 1;
-            if (bin(mid, t) <= r) lo = mid;
-            else h = mid - 1;
-        }
+        const int lo = top_row(r, t, hi, bin);
         rows[t - 1] = lo;
         r -= bin(lo, t);
         hi = lo - 1;

@@ -523,8 +523,30 @@ static void check_blocks() {
     if (fails == before) std::printf("OK blocks\n");
 }
 
+// The next row of a colex unranking (direct for i = 1, a table search above)
+// against a plain scan for the largest c with C(c, i) <= rho.
+static void check_top_row() {
+    const int before = fails;
+    auto bin = [](int c, int i) { return BINOM[c * 65 + i]; };
+    std::mt19937_64 rng(99);
+    for (int i = 1; i <= 6; i++)
+        for (int hi = i - 1; hi <= 63; hi++) {
+            const u64 lim = BINOM[(hi + 1) * 65 + i];  // rho < C(hi + 1, i)
+            for (int it = 0; it < 300; it++) {
+                u64 rho = (it < 100 && (u64)it < lim) ? (u64)it : (lim > 1 ? rng() % lim : 0);
+                if (it == 299) rho = lim - 1;
+                int want = i - 1;
+                for (int c = i - 1; c <= hi; c++)
+                    if (BINOM[c * 65 + i] <= rho) want = c;
+                CHECK(top_row(rho, i, hi, bin) == want);
+            }
+        }
+    if (fails == before) std::printf("OK top row\n");
+}
+
 int main() {
     fill_binomials(BINOM);
+    check_top_row();
     check_bits();
     check_blocks();
     for (int a = 0; a <= 64; a++)
