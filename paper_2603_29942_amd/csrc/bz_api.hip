@@ -93,7 +93,9 @@ int init_ctx(int dev) {
     if (hipHostMalloc(&c.host_trace, sizeof(CodeState::trace), hipHostMallocDefault) != hipSuccess)
         return BZ_ERR_NOMEM;
     HIP_OK(hipMemcpy(c.binom, host_binom(), sizeof(u64) * 65 * 65, hipMemcpyHostToDevice));
-    for (auto &e : c.ev) HIP_OK(hipEventCreate(&e));
+    // timing only: no system-scope fence at the records (the results are read after a
+    // stream synchronisation anyway), which otherwise writes back and invalidates caches
+    for (auto &e : c.ev) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     c.ready = true;
     return BZ_OK;
 }
