@@ -424,7 +424,12 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
         const bool counted = in && g > SUBSET_G && g <= last_g;
         u64 tg = 0;
         if (counted) {
-            for (int q = g - 3; q <= k - 3; q++) {
+            // q runs over a wave-uniform range (rows q < g-3 add nothing) so
+            // that the unrolled LDS reads overlap
+            const int q0 = uni(SUBSET_G - 2);  // the smallest g - 3 of a counted round
+#pragma unroll 4
+            for (int q = q0; q <= k - 3; q++) {
+                if (q < g - 3) continue;
                 // (ceil64 <= 2^58 and nb <= 62: the second product cannot overflow)
                 const u64 bases = sat_mul32(binom[q * 65 + (g - 3)], (uint32_t)combos);
                 tg = sat_add(tg, ceil64(bases) * (u64)lds.s_nb[q]);
