@@ -131,7 +131,11 @@ int bz_min_distance(int p, int n, int k, const uint8_t *G, bz_result *out);
 /* As bz_min_distance, with options.  G_is_device = 1: G is a device pointer
  * (already resident in GPU memory on options->device, readable from the
  * stream); 0: a host pointer, copied to the device inside the call.  On
- * return the stream has been synchronised and *out is complete. */
+ * return *out is complete and G is no longer read.  Without histograms or a
+ * trace, the check that ends the run writes the result block to host memory
+ * and the call returns as soon as it has, while workgroups of the launch may
+ * still be retiring (work queued later on the stream runs after them); with
+ * histograms or a trace the stream has been synchronised. */
 int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device,
                        const bz_options *o, bz_result *out);
 

@@ -34,6 +34,11 @@ struct DevCtx {
     u64 *binom = nullptr;
     u64 *hist = nullptr;
     CodeResult *host_res = nullptr;
+    // mapped host memory the final check writes the result block to, and the
+    // flag it raises after it (the call's epoch); device addresses of both
+    CodeResult *res_map = nullptr, *res_map_dev = nullptr;
+    uint32_t *flag_map = nullptr, *flag_map_dev = nullptr;
+    uint32_t epoch = 0;
     u64 *host_hist = nullptr;
     u64 (*host_trace)[4] = nullptr;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
@@ -92,6 +97,12 @@ int init_ctx(int dev) {
         return BZ_ERR_NOMEM;
     if (hipHostMalloc(&c.host_trace, sizeof(CodeState::trace), hipHostMallocDefault) != hipSuccess)
         return BZ_ERR_NOMEM;
+    if (hipHostMalloc(&c.res_map, sizeof(CodeResult), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess ||
+        hipHostMalloc(&c.flag_map, sizeof(uint32_t), hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess)
+        return BZ_ERR_NOMEM;
+    *c.flag_map = 0;
+    HIP_OK(hipHostGetDevicePointer((void **)&c.res_map_dev, c.res_map, 0));
+    HIP_OK(hipHostGetDevicePointer((void **)&c.flag_map_dev, c.flag_map, 0));
     HIP_OK(hipMemcpy(c.binom, host_binom(), sizeof(u64) * 65 * 65, hipMemcpyHostToDevice));
     // timing only: no system-scope fence at the records (the results are read after a
     // stream synchronisation anyway), which otherwise writes back and invalidates caches
@@ -401,17 +412,57 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, c
     ea.flags = flags;
     ea.lookahead = LOOKAHEAD;
     ea.timeout_ticks = timeout;
+    // without histograms or a trace, the check that ends the run hands the
+    // result block to the host itself (mapped memory and a flag): no copy
+    // launch and no wait for the last workgroups to retire
+    const bool mapped = !o.histograms && !o.trace_out;
+    ea.res_out = nullptr;
+    ea.flag_out = nullptr;
+    ea.epoch = 0;
+    ea.pad = 0;
+    if (mapped) {
+        if (++c->epoch == 0) c->epoch = 1;
+        ea.res_out = c->res_map_dev;
+        ea.flag_out = c->flag_map_dev;
+        ea.epoch = c->epoch;
+    }
     const bool coop = o.cooperative != 0;
     HIP_OK(p == 3 ? launch_enum<3>(o.histograms != 0, W, grid, c->cs, c->rows, c->binom, c->hist, ea, coop, s)
                   : launch_enum<7>(o.histograms != 0, W, grid, c->cs, c->rows, c->binom, c->hist, ea, coop, s));
     if (o.timing) HIP_OK(hipEventRecord(c->ev[2], s));
-    HIP_OK(hipMemcpyAsync(c->host_res, &c->cs->res, sizeof(CodeResult), hipMemcpyDeviceToHost, s));
-    if (o.histograms)
-        HIP_OK(hipMemcpyAsync(c->host_hist, c->hist, sizeof(u64) * BZ_MAX_STAGES * (BZ_MAX_N + 1),
-                              hipMemcpyDeviceToHost, s));
-    if (o.trace_out)
-        HIP_OK(hipMemcpyAsync(c->host_trace, c->cs->trace, sizeof(c->cs->trace), hipMemcpyDeviceToHost, s));
-    HIP_OK(hipStreamSynchronize(s));
+    bool have = false;
+    if (mapped) {
+        // the flag, or the end of the launch without it (no stage, a failed
+        // decomposition, a device-side wait timeout: the block is then read
+        // the ordinary way below); the stream is asked now and then so that a
+        // device error cannot leave the caller spinning
+        for (u64 it = 1;; it++) {
+            if (__atomic_load_n(c->flag_map, __ATOMIC_ACQUIRE) == ea.epoch) {
+                have = true;
+                break;
+            }
+            if ((it & 1023u) == 0) {
+                const hipError_t q = hipStreamQuery(s);
+                if (q == hipErrorNotReady) continue;
+                if (q != hipSuccess) return BZ_ERR_DEVICE;
+                have = __atomic_load_n(c->flag_map, __ATOMIC_ACQUIRE) == ea.epoch;
+                break;
+            }
+        }
+        if (have) {
+            std::memcpy(c->host_res, c->res_map, sizeof(CodeResult));
+            if (o.timing) HIP_OK(hipEventSynchronize(c->ev[2]));
+        }
+    }
+    if (!have) {
+        HIP_OK(hipMemcpyAsync(c->host_res, &c->cs->res, sizeof(CodeResult), hipMemcpyDeviceToHost, s));
+        if (o.histograms)
+            HIP_OK(hipMemcpyAsync(c->host_hist, c->hist, sizeof(u64) * BZ_MAX_STAGES * (BZ_MAX_N + 1),
+                                  hipMemcpyDeviceToHost, s));
+        if (o.trace_out)
+            HIP_OK(hipMemcpyAsync(c->host_trace, c->cs->trace, sizeof(c->cs->trace), hipMemcpyDeviceToHost, s));
+        HIP_OK(hipStreamSynchronize(s));
+    }
     st = finish(p, n, k, flags, max_cw, *c->host_res, out);
     if (o.timing) {
         HIP_OK(hipEventElapsedTime(&out->decompose_ms, c->ev[0], c->ev[1]));

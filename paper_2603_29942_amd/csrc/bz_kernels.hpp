@@ -63,7 +63,28 @@ __device__ __forceinline__ u32 pick(const u32 (&a)[N], int q) {
 struct EnumArgs {
     int32_t k, n, flags, lookahead;
     u64 timeout_ticks;
+    // optional: when a check ends the run (or checks the last stage), the
+    // checking wavefront copies the result block to res_out (mapped host
+    // memory) and then stores epoch to *flag_out
+    CodeResult *res_out;
+    uint32_t *flag_out;
+    uint32_t epoch, pad;
 };
+
+// The result block to mapped host memory by one whole wavefront: agent-scope
+// atomic loads (the minima and counts are atomics performed at the coherence
+// point), plain stores, a system-scope release, then the flag.
+__device__ __forceinline__ void publish_result(const CodeState *cs, const EnumArgs &ea) {
+    const int lane = __lane_id();
+    constexpr int NWORDS = (int)(sizeof(CodeResult) / sizeof(u32));
+    static_assert(sizeof(CodeResult) % sizeof(u32) == 0, "the result block in 32-bit words");
+    const u32 *src = reinterpret_cast<const u32 *>(&cs->res);
+    u32 *dst = reinterpret_cast<u32 *>(ea.res_out);
+    for (int i = lane; i < NWORDS; i += 64)
+        dst[i] = __hip_atomic_load(const_cast<u32 *>(src + i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __atomic_thread_fence(__ATOMIC_RELEASE);  // system scope: the stores before the flag
+    if (lane == 0) __hip_atomic_store(ea.flag_out, ea.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 
 struct RunArgs {
     int32_t n, k, flags, U0;
@@ -828,7 +849,7 @@ __device__ u64 run_base_task(const StageDesc &sd, int k, int j, const u32 *__res
 // workgroups are all done are checked in order (U takes their minima, a
 // prefix minimum over the lanes) and the first with L_{g,j} >= U ends the
 // run; one compare-and-swap publishes the new state.
-__device__ void run_checker(CodeState *cs, const StageDesc *sdesc, int ns) {
+__device__ void run_checker(CodeState *cs, const StageDesc *sdesc, int ns, const EnumArgs &ea) {
     const int lane = __lane_id();
     for (int guard = 0; guard <= 2 * BZ_MAX_STAGES; guard++) {
         u64 st = 0;
@@ -860,6 +881,8 @@ __device__ void run_checker(CodeState *cs, const StageDesc *sdesc, int ns) {
         if (ok && lane < WAKE_COPIES)
             __hip_atomic_fetch_max(&cs->wake[lane][0], wake_make(ctl_checked(nw), ctl_term(nw)), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
+        // the run's result is final: the terminating stage is found, or every stage is checked
+        if (ok && ea.res_out && (stops || c + nd >= ns)) publish_result(cs, ea);
         // done: the run ended, or every done stage is checked; another checker
         // moved the state first: look again
         if (ok && (stops || nd < 64)) return;
@@ -1020,7 +1043,7 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
             }
             // the last workgroup of a stage checks it (and every done stage after it)
             if (uni(done) == sd.parts) {
-                run_checker(cs, sdesc, ns);
+                run_checker(cs, sdesc, ns, ea);
                 if (tracing && lane == 0)
                     atomicMax((unsigned long long *)&cs->trace[2 + s][2], (unsigned long long)wall_clock64());
             }
