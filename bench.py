@@ -224,12 +224,17 @@ def main():
         __import__("numpy").stack([synth.config_code(cfg, 10000 + s)[1] for s in range(max(Wm, 1))])).to(dev)
     torch.cuda.synchronize()
 
+    # one options block for the whole run (as a caller issuing many codes
+    # would keep it): the library's stream is torch's current one
+    o = bz.bz_default_options()
+    o.timing = 1
+    o.blocks_per_cu = args.blocks_per_cu
+    o.max_codewords = 1 << 40
+    o.hip_stream = bz._stream_of(Gt)
+    out = bz.bz_result()
+
     def run(G):
-        o = bz.bz_default_options()
-        o.timing = 1
-        o.blocks_per_cu = args.blocks_per_cu
-        o.max_codewords = 1 << 40
-        st, r = bz.bz_min_distance_ex(p, G, o)
+        st, r = bz.bz_min_distance_ex(p, G, o, out)
         if st != bz.OK:
             raise RuntimeError(f"bz_min_distance_ex: {bz.bz_status_str(st)}")
         return r
