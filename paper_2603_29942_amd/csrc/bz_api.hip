@@ -138,9 +138,11 @@ hipError_t launch_decompose(int WF, const uint8_t *G, CodeState *cs, u32 *rows, 
     return hipGetLastError();
 }
 
-// The enumeration kernel is launched cooperatively: every workgroup of the grid
-// is resident at once, which its waits for earlier stages rely on.  The grid
-// (see enum_grid) is clamped to the kernel's occupancy.
+// The enumeration kernel's grid (see enum_grid) is clamped to its occupancy,
+// so on an otherwise idle device every workgroup is resident at once, which
+// its waits for earlier stages rely on.  An ordinary launch by default; coop
+// asks for hipLaunchCooperativeKernel, which guarantees co-residency but
+// starts the kernel about 11 us later.
 template <int P, int W, bool H>
 hipError_t launch_enum_one(int grid, CodeState *cs, const u32 *rows, const u64 *binom, u64 *hist, EnumArgs ea,
                            bool coop, hipStream_t s) {

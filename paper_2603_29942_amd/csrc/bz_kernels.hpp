@@ -1168,7 +1168,7 @@ __device__ void batch_check(CodeState *cs, int s, const StageDesc &sd, BatchStat
     }
 }
 
-// Persistent, cooperative: every workgroup repeatedly claims one part of the
+// Persistent: every workgroup repeatedly claims one part of the
 // current stage of some code (wave 0 scans 64 codes per step for an open claim
 // word, starting after the code it took last), runs it, reports minimum and
 // count, and the workgroup that finishes a stage's last part checks it.  Exits
