@@ -298,7 +298,7 @@ class Server:
     the server and returns [(tag, result dict)] of the codes that finished."""
 
     def __init__(self, policy="fifo", mlp_params=None, slots=1024, max_n=0, check="stage", identity_skip=True,
-                 max_codewords=0, blocks_per_cu=0, wait_timeout_s=0, max_out=1024):
+                 max_codewords=0, blocks_per_cu=0, wait_timeout_s=0, max_out=1024, cooperative=False):
         o = bz_server_options()
         lib().bz_default_server_options(ctypes.byref(o))
         o.slots = int(slots)
@@ -313,6 +313,7 @@ class Server:
         o.blocks_per_cu = int(blocks_per_cu)
         o.wait_timeout_s = int(wait_timeout_s)
         o.max_n = int(max_n)
+        o.cooperative = int(bool(cooperative))
         h = ctypes.c_void_p()
         _check(lib().bz_server_start(ctypes.byref(o), ctypes.byref(h)), "bz_server_start")
         self._h = h

@@ -565,7 +565,7 @@ int bz_min_distance_batch(int ncodes, const bz_code *codes, const uint8_t *G, ui
     HIP_OK(hipGetLastError());
     if (o.timing) HIP_OK(hipEventRecord(c->ev[0], s));
     decompose_batch_kernel<<<ncodes, 64, 0, s>>>(Gd, c->b_codes, c->b_cs, c->b_rows, (uint32_t)grid, c->b_state,
-                                                nullptr, nullptr);
+                                                nullptr, nullptr, nullptr);
     HIP_OK(hipGetLastError());
     if (o.timing) HIP_OK(hipEventRecord(c->ev[1], s));
     {
@@ -579,7 +579,8 @@ int bz_min_distance_batch(int ncodes, const bz_code *codes, const uint8_t *G, ui
         const int32_t *order = nullptr;
         const uint32_t *yield = nullptr;
         uint32_t *done = nullptr;
-        void *args[] = {&css, &cds, &nc, &rows, &bin, &bs, &to, &order, &yield, &done};
+        CodeResult *resm = nullptr;
+        void *args[] = {&css, &cds, &nc, &rows, &bin, &bs, &to, &order, &yield, &done, &resm};
         const void *fn = wmax <= 2 ? (const void *)enum_batch_kernel<2> : (const void *)enum_batch_kernel<4>;
         if (o.cooperative) HIP_OK(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(256), args, 0, s));
         else HIP_OK(hipLaunchKernel(fn, dim3(grid), dim3(256), args, 0, s));
@@ -689,7 +690,7 @@ int bz_sliced_op(int p, int op, int nvec, int nsym, const uint32_t *a, const uin
 struct bz_server {
     int dev = 0;
     DevCtx *c = nullptr;
-    hipStream_t run = nullptr, copy = nullptr;  // the launches; result copies beside them
+    hipStream_t run = nullptr;  // the launches
     hipEvent_t round_done = nullptr;
     bz_server_options o{};
     int slots = 0, grid = 0, decomp_grid = 0, flags = 0;
@@ -707,7 +708,8 @@ struct bz_server {
     uint8_t *g_h = nullptr;
     uint32_t *yield_h = nullptr, *done_h = nullptr;  // mapped host memory
     uint32_t *yield_dev = nullptr, *done_dev = nullptr;  // the same, as device addresses
-    CodeResult *res_h = nullptr;
+    CodeResult *res_h = nullptr;    // mapped: a code's result block, written before its done flag
+    CodeResult *res_dev = nullptr;
     int32_t *order_h = nullptr, *new_h = nullptr;
     float *pred_h = nullptr;
     // bookkeeping
@@ -736,7 +738,6 @@ namespace {
 
 void server_free(bz_server *s) {
     if (s->run) hipStreamSynchronize(s->run);
-    if (s->copy) hipStreamSynchronize(s->copy);
     for (void *p : {(void *)s->cs, (void *)s->codes, (void *)s->rows, (void *)s->g, (void *)s->bs,
                     (void *)s->order_d, (void *)s->new_d, (void *)s->feat_d, (void *)s->pred_d, (void *)s->mlp_d})
         if (p) hipFree(p);
@@ -745,19 +746,18 @@ void server_free(bz_server *s) {
         if (p) hipHostFree(p);
     if (s->round_done) hipEventDestroy(s->round_done);
     if (s->run) hipStreamDestroy(s->run);
-    if (s->copy) hipStreamDestroy(s->copy);
     delete s;
 }
 
-// Harvest codes that ended: copy their result blocks back and rebuild their traces.
+// Harvest codes that ended and rebuild their traces.  The kernel that ended a
+// code wrote its result block to mapped host memory before raising its done
+// flag, so nothing is copied here: a copy would need a free compute unit, and
+// a running round holds all of them.
 int server_harvest(bz_server *s, int max_out, uint64_t *tags, bz_result *results, int32_t *statuses, int *n_out) {
     std::vector<int> done;
     for (int i = 0; i < s->slots && (int)done.size() < max_out - *n_out; i++)
         if (s->slot[(size_t)i].state == 1 && __atomic_load_n(&s->done_h[i], __ATOMIC_ACQUIRE) != 0) done.push_back(i);
     if (done.empty()) return BZ_OK;
-    for (int i : done)
-        HIP_OK(hipMemcpyAsync(&s->res_h[i], &s->cs[i].res, sizeof(CodeResult), hipMemcpyDeviceToHost, s->copy));
-    HIP_OK(hipStreamSynchronize(s->copy));
     for (int i : done) {
         bz_server::Slot &sl = s->slot[(size_t)i];
         const int k = *n_out;
@@ -783,7 +783,8 @@ hipError_t server_launch(bz_server *s, int nactive) {
     const int32_t *order = s->order_d;
     const uint32_t *yield = s->yield_dev;
     uint32_t *done = s->done_dev;
-    void *args[] = {&css, &cds, &nc, &rows, &bin, &bs, &to, &order, &yield, &done};
+    CodeResult *resm = s->res_dev;
+    void *args[] = {&css, &cds, &nc, &rows, &bin, &bs, &to, &order, &yield, &done, &resm};
     if (s->o.cooperative)
         return hipLaunchCooperativeKernel((const void *)enum_batch_kernel<WMAX>, dim3(s->grid), dim3(256), args, 0,
                                           s->run);
@@ -831,7 +832,7 @@ int server_round(bz_server *s) {
                               s->run));
         HIP_OK(hipMemcpyAsync(s->new_d, s->new_h, sizeof(int32_t) * (size_t)nf, hipMemcpyHostToDevice, s->run));
         decompose_batch_kernel<<<nf, 64, 0, s->run>>>(s->g, s->codes, s->cs, s->rows, (uint32_t)s->decomp_grid, s->bs,
-                                                      s->new_d, s->done_dev);
+                                                      s->new_d, s->done_dev, s->res_dev);
         HIP_OK(hipGetLastError());
         if (s->o.policy == BZ_SERVE_PREDICTED) {
             features_kernel<<<(nf + 63) / 64, 64, 0, s->run>>>(s->cs, s->new_d, nf, s->feat_d);
@@ -913,7 +914,6 @@ int bz_server_start(const bz_server_options *opt, bz_server **out) {
     s->slot.resize((size_t)s->slots);
     const size_t ns = (size_t)s->slots;
     bool ok = s->grid > 0 && hipStreamCreateWithFlags(&s->run, hipStreamNonBlocking) == hipSuccess &&
-              hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) == hipSuccess &&
               hipEventCreateWithFlags(&s->round_done, hipEventDisableTiming) == hipSuccess &&
               hipMalloc(&s->cs, sizeof(CodeState) * ns) == hipSuccess &&
               hipMalloc(&s->codes, sizeof(BatchCode) * ns) == hipSuccess &&
@@ -929,7 +929,8 @@ int bz_server_start(const bz_server_options *opt, bz_server **out) {
               hipHostMalloc(&s->yield_h, sizeof(uint32_t), hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess &&
               hipHostMalloc(&s->done_h, sizeof(uint32_t) * ns, hipHostMallocMapped | hipHostMallocCoherent) ==
                   hipSuccess &&
-              hipHostMalloc(&s->res_h, sizeof(CodeResult) * ns, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&s->res_h, sizeof(CodeResult) * ns, hipHostMallocMapped | hipHostMallocCoherent) ==
+                  hipSuccess &&
               hipHostMalloc(&s->order_h, sizeof(int32_t) * ns, hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc(&s->new_h, sizeof(int32_t) * ns, hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc(&s->pred_h, sizeof(float) * ns, hipHostMallocDefault) == hipSuccess;
@@ -938,7 +939,8 @@ int bz_server_start(const bz_server_options *opt, bz_server **out) {
         return BZ_ERR_NOMEM;
     }
     if (hipHostGetDevicePointer((void **)&s->yield_dev, s->yield_h, 0) != hipSuccess ||
-        hipHostGetDevicePointer((void **)&s->done_dev, s->done_h, 0) != hipSuccess) {
+        hipHostGetDevicePointer((void **)&s->done_dev, s->done_h, 0) != hipSuccess ||
+        hipHostGetDevicePointer((void **)&s->res_dev, s->res_h, 0) != hipSuccess) {
         server_free(s);
         return BZ_ERR_DEVICE;
     }

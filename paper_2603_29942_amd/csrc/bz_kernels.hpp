@@ -71,19 +71,23 @@ struct EnumArgs {
     uint32_t epoch, pad;
 };
 
-// The result block to mapped host memory by one whole wavefront: agent-scope
-// atomic loads (the minima and counts are atomics performed at the coherence
-// point), plain stores, a system-scope release, then the flag.
-__device__ __forceinline__ void publish_result(const CodeState *cs, const EnumArgs &ea) {
+// A code's result block to mapped host memory by one whole wavefront:
+// agent-scope atomic loads (the minima and counts are atomics performed at the
+// coherence point), plain stores, a system-scope release, then lane 0 stores
+// `value` to the flag the host waits on.  res_out may be NULL (flag only).
+__device__ __forceinline__ void hand_out_result(const CodeState *cs, CodeResult *res_out, uint32_t *flag,
+                                                uint32_t value) {
     const int lane = __lane_id();
-    constexpr int NWORDS = (int)(sizeof(CodeResult) / sizeof(u32));
-    static_assert(sizeof(CodeResult) % sizeof(u32) == 0, "the result block in 32-bit words");
-    const u32 *src = reinterpret_cast<const u32 *>(&cs->res);
-    u32 *dst = reinterpret_cast<u32 *>(ea.res_out);
-    for (int i = lane; i < NWORDS; i += 64)
-        dst[i] = __hip_atomic_load(const_cast<u32 *>(src + i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __atomic_thread_fence(__ATOMIC_RELEASE);  // system scope: the stores before the flag
-    if (lane == 0) __hip_atomic_store(ea.flag_out, ea.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (res_out) {
+        constexpr int NWORDS = (int)(sizeof(CodeResult) / sizeof(u32));
+        static_assert(sizeof(CodeResult) % sizeof(u32) == 0, "the result block in 32-bit words");
+        const u32 *src = reinterpret_cast<const u32 *>(&cs->res);
+        u32 *dst = reinterpret_cast<u32 *>(res_out);
+        for (int i = lane; i < NWORDS; i += 64)
+            dst[i] = __hip_atomic_load(const_cast<u32 *>(src + i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __atomic_thread_fence(__ATOMIC_RELEASE);  // system scope: the stores before the flag
+    }
+    if (lane == 0) __hip_atomic_store(flag, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 struct RunArgs {
@@ -882,7 +886,7 @@ __device__ void run_checker(CodeState *cs, const StageDesc *sdesc, int ns, const
             __hip_atomic_fetch_max(&cs->wake[lane][0], wake_make(ctl_checked(nw), ctl_term(nw)), __ATOMIC_RELAXED,
                                    __HIP_MEMORY_SCOPE_AGENT);
         // the run's result is final: the terminating stage is found, or every stage is checked
-        if (ok && ea.res_out && (stops || c + nd >= ns)) publish_result(cs, ea);
+        if (ok && ea.res_out && (stops || c + nd >= ns)) hand_out_result(cs, ea.res_out, ea.flag_out, ea.epoch);
         // done: the run ended, or every done stage is checked; another checker
         // moved the state first: look again
         if (ok && (stops || nd < 64)) return;
@@ -1064,7 +1068,8 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
 __global__ __launch_bounds__(64) void decompose_batch_kernel(const uint8_t *__restrict__ G,
                                                              const BatchCode *__restrict__ codes, CodeState *css,
                                                              u32 *__restrict__ rows, uint32_t grid, BatchState *bs,
-                                                             const int32_t *__restrict__ slots, uint32_t *done_flags) {
+                                                             const int32_t *__restrict__ slots, uint32_t *done_flags,
+                                                             CodeResult *res_map) {
     __shared__ DecompLDS lds;
     const int c = slots ? slots[blockIdx.x] : (int)blockIdx.x;  // a list of slots, or every code
     const BatchCode bc = codes[c];
@@ -1095,13 +1100,19 @@ __global__ __launch_bounds__(64) void decompose_batch_kernel(const uint8_t *__re
         default: decompose_code<7, 4>(g, cs, r, a, lds); break;
         }
     }
+    int work = 0;
     if (threadIdx.x == 0) {
         // lane 0 wrote the status, the table size and stage 0 itself
-        const bool work = cs->res.status == BZ_OK && cs->res.n_table > 0;
+        work = cs->res.status == BZ_OK && cs->res.n_table > 0;
         cs->claim = work ? claim_make(0, cs->stages[0].parts) : 0ull;
         if (work) atomicAdd(&bs->remaining, 1u);
-        // serving: a code with nothing to enumerate is done at once
-        else if (done_flags) __hip_atomic_store(done_flags + c, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    // serving: a code with nothing to enumerate is done at once; its result
+    // block (written by this wavefront with plain stores) goes to the device's
+    // memory first so that the hand-out's coherent loads see it
+    if (!uni(work) && done_flags) {
+        __threadfence();
+        hand_out_result(cs, res_map ? res_map + c : nullptr, done_flags + c, 1u);
     }
 }
 
@@ -1146,26 +1157,26 @@ __device__ u64 run_part(const StageDesc &sd, int s, uint32_t part, int k, const 
 
 // After the last part of stage s of a code: U takes the stage minimum, the
 // L >= U test (Alg. 6) ends the code or publishes the next stage's claim word.
-// Run by one whole wavefront; only lane 0 touches memory.  done_flag (or
-// NULL) is raised when the code ends.
-__device__ void batch_check(CodeState *cs, int s, const StageDesc &sd, BatchState *bs, uint32_t *done_flag) {
-    if (__lane_id() != 0) return;
-    const u64 st = rd_atomic(&cs->res.ctl);
-    const int U = min((int)ctl_U(st), rd_atomic(&cs->res.stage_min[s]));
-    const int ns = cs->res.n_table;
-    const bool stop = sd.check && sd.L >= U;
-    const bool last = stop || s + 1 >= ns;
-    __hip_atomic_exchange(&cs->res.ctl, stop ? ctl_make(s, s, U) : ctl_make(s + 1, -1, U), __ATOMIC_RELAXED,
-                          __HIP_MEMORY_SCOPE_AGENT);
-    drain_vmem();  // U is in place before the next stage can be claimed and checked
-    __hip_atomic_exchange(&cs->claim, last ? 0ull : claim_make(s + 1, cs->stages[s + 1].parts), __ATOMIC_RELAXED,
-                          __HIP_MEMORY_SCOPE_AGENT);
-    if (last) {
-        __hip_atomic_fetch_sub(&bs->remaining, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // serving: tell the host (mapped host memory); the release makes the
-        // code's result block visible to a copy the host then issues
-        if (done_flag) __hip_atomic_store(done_flag, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+// Run by one whole wavefront; lane 0 applies the check.  done_flag (serving)
+// is raised when the code ends, after its result block went to res_out.
+__device__ void batch_check(CodeState *cs, int s, const StageDesc &sd, BatchState *bs, uint32_t *done_flag,
+                            CodeResult *res_out) {
+    int last = 0;
+    if (__lane_id() == 0) {
+        const u64 st = rd_atomic(&cs->res.ctl);
+        const int U = min((int)ctl_U(st), rd_atomic(&cs->res.stage_min[s]));
+        const int ns = cs->res.n_table;
+        const bool stop = sd.check && sd.L >= U;
+        last = stop || s + 1 >= ns;
+        __hip_atomic_exchange(&cs->res.ctl, stop ? ctl_make(s, s, U) : ctl_make(s + 1, -1, U), __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_AGENT);
+        drain_vmem();  // U is in place before the next stage can be claimed and checked
+        __hip_atomic_exchange(&cs->claim, last ? 0ull : claim_make(s + 1, cs->stages[s + 1].parts),
+                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (last) __hip_atomic_fetch_sub(&bs->remaining, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    // serving: hand the result block and the done flag to the host (mapped memory)
+    if (uni(last) && done_flag) hand_out_result(cs, res_out, done_flag, 1u);
 }
 
 // Persistent: every workgroup repeatedly claims one part of the
@@ -1183,7 +1194,8 @@ __global__ __launch_bounds__(256) void enum_batch_kernel(CodeState *css, const B
                                                          int ncodes, const u32 *__restrict__ rows,
                                                          const u64 *__restrict__ gbin, BatchState *bs,
                                                          u64 timeout_ticks, const int32_t *__restrict__ order,
-                                                         const uint32_t *yield, uint32_t *done_flags) {
+                                                         const uint32_t *yield, uint32_t *done_flags,
+                                                         CodeResult *res_map) {
     __shared__ u64 sbin[BZ_MAX_K * BIN_I];
     __shared__ QEntry qtab[BZ_MAX_K];
     __shared__ u32 red_min[WAVES_PER_GROUP];
@@ -1310,7 +1322,8 @@ __global__ __launch_bounds__(256) void enum_batch_kernel(CodeState *css, const B
                 drain_vmem();  // minimum and count performed before done counts this part
                 done = __hip_atomic_fetch_add(&cs->stage_done[s], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
             }
-            if (uni(done) == sd.parts) batch_check(cs, s, sd, bs, done_flags ? done_flags + code : nullptr);
+            if (uni(done) == sd.parts)
+                batch_check(cs, s, sd, bs, done_flags ? done_flags + code : nullptr, res_map ? res_map + code : nullptr);
         }
         __syncthreads();  // qtab, red_* and s_* are rewritten by the next claim
     }
