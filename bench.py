@@ -277,7 +277,7 @@ def main():
         "config": {"workload": f"one random {CONFIG_NAMES[cfg]} code per step (seeds 0..{K - 1}), "
                                "plain path, generator resident on the GPU",
                    "p": p, "n": n, "k": k, "identity_skip": True,
-                   "blocks_per_cu": args.blocks_per_cu or 4},
+                   "blocks_per_cu": args.blocks_per_cu or "occupancy"},
         "time_to_d_ms": {"p50": pct(per_step, 50) * 1e3, "p99": pct(per_step, 99) * 1e3,
                          "mean": elapsed / K * 1e3},
         "codewords_per_step": {"mean": total_cw / K, "min": min(cws), "max": max(cws)},

@@ -98,7 +98,8 @@ typedef struct {
     uint64_t max_codewords;   /* work limit; 0 = default (2^44) */
     void *hip_stream;         /* hipStream_t to run on; NULL = the library's stream */
     int32_t device;           /* HIP device ordinal */
-    int32_t blocks_per_cu;    /* enumeration grid: workgroups per compute unit; 0 = default */
+    int32_t blocks_per_cu;    /* enumeration grid: workgroups per compute unit; 0 = as many
+                                 as the kernel's registers and LDS allow */
     int32_t timing;           /* 1: fill bz_result.decompose_ms / enum_ms */
     int32_t wait_timeout_s;   /* workgroups that wait for earlier stages give up (BZ_ERR_DEVICE)
                                  after this many seconds; 0 = default (120) */

@@ -381,7 +381,8 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, c
     const int WF = (n + 31) / 32;
     int W = o.identity_skip ? (n - k + 31) / 32 : WF;
     if (W < 1) W = 1;
-    const int bpc = o.blocks_per_cu ? o.blocks_per_cu : 4;
+    // default: as many workgroups as fit (finer deals of the large stages)
+    const int bpc = o.blocks_per_cu ? o.blocks_per_cu : 64;
     const int grid = enum_grid(p, o.histograms != 0, W, c->cu, bpc);
     if (grid < 1) return BZ_ERR_DEVICE;
     const u64 timeout = c->ticks_per_s * (u64)(o.wait_timeout_s > 0 ? o.wait_timeout_s : 120);
