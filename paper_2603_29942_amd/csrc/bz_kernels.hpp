@@ -101,16 +101,16 @@ struct RunArgs {
 // q-groups of a stage with g >= 3 computed by the 64 lanes of a wavefront
 // (lane = q - (g-3)); the same values as fill_qtable.  Returns the number of
 // tasks (wave-uniform); with tab != nullptr the lanes also store their entry.
-__device__ __forceinline__ u64 wave_qtable(int k, int g, u64 M, uint32_t cap, const u64 *__restrict__ binom,
-                                           QEntry *tab) {
+__device__ __forceinline__ u64 wave_qtable(int p, int k, int g, u64 M, uint32_t cap, uint32_t vcap,
+                                           const u64 *__restrict__ binom, QEntry *tab) {
     const int lane = __lane_id();
     const int q = g - 3 + lane;
     const bool in = q <= k - 3;
     u64 bases = 0, val = 0;
-    uint32_t nb = 0;
+    uint32_t nb = 0, vd = 0;
     if (in) {
-        qgroup(k, g, M, cap, binom, q, &bases, &nb);
-        val = ceil64(bases) * (u64)nb;  // <= 2^58 * 62: no overflow
+        qgroup(k, g, M, cap, vcap, binom, q, &bases, &nb, &vd, p);
+        val = qgroup_tasks(bases, nb, vd);  // <= 2^58 * 62: no overflow
     }
     // inclusive scan of val over the lanes (saturating)
     u64 inc = val;
@@ -123,7 +123,7 @@ __device__ __forceinline__ u64 wave_qtable(int k, int g, u64 M, uint32_t cap, co
         e.first = inc - val;
         e.bases = bases;
         e.nb = nb;
-        e.pad = 0;
+        e.vd = vd;
     }
     return uni64(__shfl(inc, 63));
 }
@@ -138,8 +138,10 @@ struct DecompLDS {
     int32_t sranks[BZ_MAX_M];
     u64 s_cw[BZ_MAX_K], s_tasks[BZ_MAX_K];
     u64 s_tbefore[BZ_MAX_K];  // tiles of the rounds before round g, at [g - 1]
+    uint32_t s_vcap[BZ_MAX_K];  // run budget of round g (0: no runs), at [g - 1]
     uint32_t s_combos[BZ_MAX_K];
     uint32_t s_nb[BZ_MAX_K];  // blocks of rows s of the q-group with top row q, at [q]
+    uint32_t s_dt[BZ_MAX_K];  // F_3: digits_by_steps of the q-group with top row q, at [q]
 };
 
 // One Gauss-Jordan step on the rows held one per lane: row pl (pivot value
@@ -436,6 +438,7 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
             s_cw[lane] = cw;
             s_combos[lane] = (uint32_t)combos;
             s_tasks[lane] = (g <= SUBSET_G) ? small_stage_tasks(k, g) : 0;
+            lds.s_vcap[lane] = 0;
         }
         __syncthreads();
         // task counts of the rounds g > SUBSET_G that the table reaches, one
@@ -444,10 +447,14 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
         // of fill_qtable)
         const int last_g = (ns + m - 1) / m;
         const uint32_t cap = sweep_cap_for(P, W, args.sweep_ops);
-        if (lane <= k - 3) lds.s_nb[lane] = qgroup_blocks(k, cap, lane);
+        const uint32_t budget = run_budget(P, cap);
+        if (lane <= k - 3) {
+            lds.s_nb[lane] = qgroup_blocks(k, cap, lane);
+            if (P == 3) lds.s_dt[lane] = digits_by_steps(k, lane, budget);
+        }
         __syncthreads();
         const bool counted = in && g > SUBSET_G && g <= last_g;
-        u64 tg = 0;
+        u64 tg = 0, tgv = 0;  // without and with runs of bases
         if (counted) {
             // q runs over a wave-uniform range (rows q < g-3 add nothing) so
             // that the unrolled LDS reads overlap
@@ -455,11 +462,17 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
 #pragma unroll 4
             for (int q = q0; q <= k - 3; q++) {
                 if (q < g - 3) continue;
-                // (ceil64 <= 2^58 and nb <= 62: the second product cannot overflow)
+                // (ceil64 <= 2^58 and nb <= 62: the product cannot overflow)
                 const u64 bases = sat_mul32(binom[q * 65 + (g - 3)], (uint32_t)combos);
-                tg = sat_add(tg, ceil64(bases) * (u64)lds.s_nb[q]);
+                const uint32_t nb = lds.s_nb[q];
+                tg = sat_add(tg, qgroup_tasks(bases, nb, 0));
+                if constexpr (P == 3) tgv = sat_add(tgv, qgroup_tasks(bases, nb, digits_of(g, lds.s_dt[q], bases)));
             }
-            s_tasks[lane] = tg;
+            // the round takes runs of bases where they pay (qgroup_digits with
+            // the run budget, as a table of digits_by_steps)
+            const bool runs = P == 3 && runs_pay(tgv, args.grid);
+            s_tasks[lane] = runs ? tgv : tg;
+            lds.s_vcap[lane] = runs ? budget : 0u;
         }
         // the first round with 2^62 tasks or more cuts the table before it
         const u64 over = __ballot(counted && tg >= (1ull << 62));
@@ -503,6 +516,8 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
             d.coef_combos = s_combos[g - 1];
             d.parts = (uint32_t)(d.tiles < (u64)args.grid ? d.tiles : (u64)args.grid);
             d.sweep_cap = cap;
+            d.vcap = lds.s_vcap[g - 1];
+            d.pad = 0;
             const u64 off = deal_offset(m, lds.s_tbefore[g - 1], j, d.tiles);
             d.nowait = off < (u64)args.grid;
             d.rot = deal_rot(off, args.grid);
@@ -805,7 +820,12 @@ __device__ u64 run_small_task(int g, int k, int j, const u32 *__restrict__ rows,
     return (u64)((P - 1) * (P - 1) * (P - 1)) * (u64)__popcll(__ballot(valid));
 }
 
-// g > SUBSET_G: one task = (q, chunk of 64 bases, block of rows s); see StageDesc.
+// g > SUBSET_G: one task = (q, chunk of 64 lanes, block of rows s); see
+// StageDesc.  A lane takes the 2^vd consecutive bases (2^vd bi, ...,
+// 2^vd bi + 2^vd - 1), vd > 0 only for F_3: they differ in the coefficients
+// (1 or 2) of the first vd rows in decoding order, the top row q first.  The
+// lane decodes the first of them and walks the others in Gray-code order, one
+// row added (coefficient 1 -> 2) or subtracted (2 -> 1) per step.
 template <int P, int W, bool HIST>
 __device__ u64 run_base_task(const StageDesc &sd, int k, int j, const u32 *__restrict__ rows, const u64 *sbin,
                              const u64 *__restrict__ gbin, const QEntry *qtab, int nq, u64 task, u32 &lmin,
@@ -818,32 +838,76 @@ __device__ u64 run_base_task(const StageDesc &sd, int k, int j, const u32 *__res
     // the q-group's entry as wave-uniform (scalar) values
     const u64 e_first = uni64(qtab[qi].first), e_bases = uni64(qtab[qi].bases);
     const uint32_t e_nb = uni(qtab[qi].nb);
+    const int vd = (P == 3) ? uni(qtab[qi].vd) : 0;
     const u64 local = task - e_first;
     const u64 chunk = local / e_nb;
     const int block = (int)(local - chunk * e_nb);
     const int s_lo = q + 1 + uni(qgroup_block_start(k, q, e_nb, (uint32_t)block));
     const int s_hi = q + 1 + uni(qgroup_block_start(k, q, e_nb, (uint32_t)block + 1));
-    const u64 bi = chunk * 64 + (u64)lane;
-    const bool valid = bi < e_bases;
+    const u64 bi = (chunk * 64 + (u64)lane) << vd;
+    const bool valid = bi < e_bases;  // the 2^vd bases of a lane are valid together (2^vd divides bases)
     u32 Q[3][W];
 #pragma unroll
     for (int b = 0; b < 3; b++)
 #pragma unroll
         for (int w = 0; w < W; w++) Q[b][w] = 0;
-    if (valid) {
-        decode_base<P>(g, q, M, bi, [&](int c, int i) { return binom_at(sbin, gbin, c, i); },
-                       [&](int row, int coef) {
-                           const Row<W> r = load_row<P, W>(rows, j, row);
-                           add_scaled<P, W>(Q, r.p, coef);
-                       });
-    }
-    const u64 nact = (u64)__popcll(__ballot(valid));
     u64 cnt = 0;
-    for (int s = s_lo; s < s_hi; s++) {
-        // p-1 coefficients of row s, k-1-s last rows, p-1 multipliers, on nact lanes
-        cnt += nact * (u64)((P - 1) * (P - 1) * (k - 1 - s));
-        const Row<W> Rs = load_row<P, W>(rows, j, uni(s));
-        if (valid) extend_and_sweep<P, W, P - 1, HIST>(rows, j, s, k, Q, Rs, lmin, lh, woff, cap);
+    if (vd == 0) {
+        // one base per lane
+        if (valid) {
+            decode_base<P>(g, q, M, bi, [&](int c, int i) { return binom_at(sbin, gbin, c, i); },
+                           [&](int row, int coef) {
+                               const Row<W> r = load_row<P, W>(rows, j, row);
+                               add_scaled<P, W>(Q, r.p, coef);
+                           });
+        }
+        const u64 nact = (u64)__popcll(__ballot(valid));
+        for (int s = s_lo; s < s_hi; s++) {
+            // p-1 coefficients of row s, k-1-s last rows, p-1 multipliers, on nact lanes
+            cnt += nact * (u64)((P - 1) * (P - 1) * (k - 1 - s));
+            const Row<W> Rs = load_row<P, W>(rows, j, uni(s));
+            if (valid) extend_and_sweep<P, W, P - 1, HIST>(rows, j, s, k, Q, Rs, lmin, lh, woff, cap);
+        }
+        return cnt;
+    }
+    if constexpr (P == 3) {
+        // a run of 2^vd bases per lane; the rows of digits 1 and 2 are held
+        // (lane-specific), row q (digit 0) is loaded again (wave-uniform)
+        Row<W> Rd1, Rd2;
+        if (valid) {
+            int vi = 0;
+            decode_base<P>(g, q, M, bi, [&](int c, int i) { return binom_at(sbin, gbin, c, i); },
+                           [&](int row, int coef) {
+                               const Row<W> r = load_row<P, W>(rows, j, row);
+                               add_scaled<P, W>(Q, r.p, coef);
+                               if (vi == 1) Rd1 = r;
+                               if (vi == 2) Rd2 = r;
+                               vi++;
+                           });
+        }
+        const u64 nact = (u64)__popcll(__ballot(valid)) << vd;
+        for (int s = s_lo; s < s_hi; s++) cnt += nact * (u64)((P - 1) * (P - 1) * (k - 1 - s));
+        const int nv = 1 << vd;
+        uint32_t cur = 0;  // bit t: digit t's row has coefficient 2 (wave-uniform)
+        for (int v = 0; v < nv; v++) {
+            if (v > 0) {
+                const int t = __builtin_ctz((uint32_t)v);
+                const int h = ((cur >> t) & 1u) ? 2 : 1;  // 1 -> 2: + row; 2 -> 1: - row = + 2 row
+                cur ^= 1u << t;
+                if (t == 0) {
+                    const Row<W> Rq = load_row<P, W>(rows, j, q);
+                    if (valid) add_scaled<P, W>(Q, Rq.p, h);
+                } else if (t == 1) {
+                    if (valid) add_scaled<P, W>(Q, Rd1.p, h);
+                } else {
+                    if (valid) add_scaled<P, W>(Q, Rd2.p, h);
+                }
+            }
+            for (int s = s_lo; s < s_hi; s++) {
+                const Row<W> Rs = load_row<P, W>(rows, j, uni(s));
+                if (valid) extend_and_sweep<P, W, P - 1, HIST>(rows, j, s, k, Q, Rs, lmin, lh, woff, cap);
+            }
+        }
     }
     return cnt;
 }
@@ -980,7 +1044,7 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
         if (wid == 0 && sd.g > SUBSET_G) {
             // the q-groups of the stage, unless the run ended (thread 0 is lane 0 of wave 0)
             const int tw = __builtin_amdgcn_readfirstlane(term0);
-            if (!(tw == -2 || (tw >= 0 && s > tw))) wave_qtable(k, sd.g, sd.coef_combos, sd.sweep_cap, gbin, qtab);
+            if (!(tw == -2 || (tw >= 0 && s > tw))) wave_qtable(P, k, sd.g, sd.coef_combos, sd.sweep_cap, sd.vcap, gbin, qtab);
         }
         __syncthreads();
         const int term = s_term;
@@ -1284,7 +1348,7 @@ __global__ __launch_bounds__(256) void enum_batch_kernel(CodeState *css, const B
         const int n = uni(codes[code].n);
         const u64 row_off = uni64(codes[code].row_offset);
         const StageDesc sd = cs->stages[s];
-        if (wid == 0 && sd.g > SUBSET_G) wave_qtable(k, sd.g, sd.coef_combos, sd.sweep_cap, gbin, qtab);
+        if (wid == 0 && sd.g > SUBSET_G) wave_qtable(p, k, sd.g, sd.coef_combos, sd.sweep_cap, sd.vcap, gbin, qtab);
         __syncthreads();
         const u32 woff = (uni(codes[code].flags) & FLAG_SKIP) ? (u32)sd.g : 0u;
         const u32 cap = (u32)n;

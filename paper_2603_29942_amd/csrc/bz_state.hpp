@@ -58,6 +58,9 @@ struct StageDesc {
     uint32_t parts;        // workgroups that own at least one tile: min(grid, tiles)
     uint32_t sweep_cap;    // g >= 3: target (s, L) steps per lane and task
     uint32_t rot;          // (grid - off_s mod grid) mod grid, see tile_of
+    uint32_t vcap;         // F_3: step budget of a lane's run of bases (qgroup_digits);
+                           // 0: one base per lane
+    uint32_t pad;
 };
 
 
@@ -66,7 +69,7 @@ struct QEntry {
     u64 first;     // first task of the group
     u64 bases;     // C(q, g-3) (p-1)^(g-3)
     uint32_t nb;   // blocks of rows s, see qgroup_blocks
-    uint32_t pad;
+    uint32_t vd;   // a lane takes 2^vd consecutive bases, see qgroup_digits
 };
 
 // Results the host reads back (kept contiguous and first in CodeState).
@@ -233,29 +236,67 @@ BZ_HD int qgroup_block_start(int k, int q, uint32_t nb, uint32_t b) {
     }
     return (int)(lo > b ? lo : b);
 }
-BZ_HD void qgroup(int k, int g, u64 M, uint32_t cap, const u64 *binom, int q, u64 *bases, uint32_t *nb) {
+// Low coefficient digits a lane runs through itself (F_3 only): 2^vd
+// consecutive bases differ only in the coefficients (1 or 2) of their first vd
+// rows in decoding order (the top row q first), so one decoding and one row
+// addition per further base serve them all (a Gray-code walk).  vd is the
+// largest d <= min(g-3, 3) with T 2^d <= vcap (the lane's (s, L) steps stay
+// within the run budget; with vcap <= cap the group is then one block) and
+// bases >= 64 2^d (the group still fills a wavefront); T = len (len + 1) / 2
+// as in qgroup_blocks.  vcap = 0: no runs.
+constexpr int BZ_MAX_VD = 3;
+// the largest d with T 2^d <= vcap, 0 if none (vcap >= 1)
+BZ_HD uint32_t digits_by_steps(int k, int q, uint32_t vcap) {
+    const uint32_t len = (uint32_t)(k - 2 - q), T = len * (len + 1) / 2;
+    return vcap >= T ? 31u - (uint32_t)__builtin_clz(vcap / T) : 0u;
+}
+// the largest d with bases >= 64 2^d, 0 if none
+BZ_HD uint32_t digits_by_bases(u64 bases) { return bases >= 128 ? 57u - (uint32_t)__builtin_clzll(bases) : 0u; }
+BZ_HD uint32_t digits_of(int g, uint32_t by_steps, u64 bases) {
+    uint32_t d = (uint32_t)(g - 3 < BZ_MAX_VD ? g - 3 : BZ_MAX_VD);
+    d = by_steps < d ? by_steps : d;
+    const uint32_t b = digits_by_bases(bases);
+    return b < d ? b : d;
+}
+BZ_HD uint32_t qgroup_digits(int p, int k, int g, uint32_t vcap, int q, u64 bases) {
+    if (p != 3 || vcap == 0) return 0;
+    return digits_of(g, digits_by_steps(k, q, vcap), bases);
+}
+// Run budget of a round: runs shorten the work of a stage but lengthen its
+// tasks and cut their number, so a round takes them only when its stages
+// still have a tile for every workgroup with them (measured: the stages that
+// leave workgroups idle run slower with runs).
+BZ_HD uint32_t run_budget(int p, uint32_t cap) { return p == 3 ? cap : 0u; }
+BZ_HD bool runs_pay(u64 tasks_with_runs, uint32_t grid) {
+    return (tasks_with_runs + WAVES_PER_GROUP - 1) / WAVES_PER_GROUP >= (u64)grid;
+}
+BZ_HD void qgroup(int k, int g, u64 M, uint32_t cap, uint32_t vcap, const u64 *binom, int q, u64 *bases,
+                  uint32_t *nb, uint32_t *vd, int p) {
     *bases = sat_mul(binom[q * 65 + (g - 3)], M);
     *nb = qgroup_blocks(k, cap, q);
+    *vd = qgroup_digits(p, k, g, vcap, q, *bases);
 }
 // chunks of 64 bases (no overflow at the saturated value)
 BZ_HD u64 ceil64(u64 bases) { return (bases >> 6) + ((bases & 63) != 0); }
+// tasks of a q-group: chunks of 64 lanes of 2^vd bases each, times the blocks
+BZ_HD u64 qgroup_tasks(u64 bases, uint32_t nb, uint32_t vd) { return ceil64(bases >> vd) * (u64)nb; }
 
 // Number of tasks of a stage with g >= 3 (saturating); with tab != NULL also
 // fills the q-groups (entries for q = g-3 .. k-3, index q-(g-3)).
-BZ_HD u64 fill_qtable(int k, int g, u64 M, uint32_t cap, const u64 *binom, QEntry *tab) {
+BZ_HD u64 fill_qtable(int p, int k, int g, u64 M, uint32_t cap, uint32_t vcap, const u64 *binom, QEntry *tab) {
     u64 first = 0;
     for (int q = g - 3; q <= k - 3; q++) {
         u64 bases;
-        uint32_t nb;
-        qgroup(k, g, M, cap, binom, q, &bases, &nb);
+        uint32_t nb, vd;
+        qgroup(k, g, M, cap, vcap, binom, q, &bases, &nb, &vd, p);
         if (tab) {
             QEntry &e = tab[q - (g - 3)];
             e.first = first;
             e.bases = bases;
             e.nb = nb;
-            e.pad = 0;
+            e.vd = vd;
         }
-        first = sat_add(first, sat_mul(ceil64(bases), (u64)nb));
+        first = sat_add(first, qgroup_tasks(bases, nb, vd));
     }
     return first;
 }
@@ -411,28 +452,43 @@ BZ_HD void decode_subset(u64 r, int k, Bin bin, int (&rows)[G]) {
 // Build the schedule: stages (g, j) for g = 1..k, j = 1..m in order, while the
 // cumulative combination count stays within max_codewords, at most
 // BZ_MAX_STAGES stages, and every index fits the kernel ((p-1)^(g-3) < 2^32,
-// tasks < 2^62; the last condition only when count_tasks).  grid: workgroups of the enumeration launch; W: words per
-// plane of the packed rows.  Returns the number of stages; *complete = 1 if
-// the schedule reaches (k, m).  binom[c*65+i] = C(c, i) for c, i <= 64.
+// tasks < 2^62 counted without runs of bases; the last condition only when
+// count_tasks).  The deal of a stage starts at off_s = the tiles of all earlier
+// stages; stages with off_s < grid start at once (nowait), the others wait for
+// the checks.  F_3 rounds take runs of bases where runs_pay.  grid: workgroups
+// of the enumeration launch; W: words per plane of the packed rows.  Returns the
+// number of stages; *complete = 1 if the schedule reaches (k, m).
+// binom[c*65+i] = C(c, i) for c, i <= 64.
 BZ_HD int build_schedule(int p, int k, int m, const int32_t *ranks, int flags, u64 max_codewords,
                          uint32_t grid, int W, const u64 *binom, StageDesc *st, int *complete,
                          bool count_tasks = true, uint32_t sweep_ops = DEFAULT_SWEEP_OPS) {
     int ns = 0;
-    u64 cum = 0, tiles_before = 0;
+    u64 cum = 0, off = 0;
     *complete = 1;
     const uint32_t cap = sweep_cap_for(p, W, sweep_ops);
     for (int g = 1; g <= k; g++) {
         const u64 cw = round_codewords(p, k, g, binom);
-        u64 tasks;
+        u64 tasks0, tasks;  // without runs of bases; the round's own
+        uint32_t vcap = 0;
         const u64 combos = round_combos(p, g);
-        if (g <= SUBSET_G) tasks = small_stage_tasks(k, g);
-        else {
-            // without count_tasks the caller fills tasks, tiles and parts of these stages
-            tasks = (combos >= (1ull << 32)) ? ~0ull : count_tasks ? fill_qtable(k, g, combos, cap, binom, nullptr) : 0;
+        if (g <= SUBSET_G) tasks0 = tasks = small_stage_tasks(k, g);
+        else if (combos >= (1ull << 32)) tasks0 = tasks = ~0ull;
+        else if (count_tasks) {
+            tasks0 = tasks = fill_qtable(p, k, g, combos, cap, 0, binom, nullptr);
+            const uint32_t budget = run_budget(p, cap);
+            if (budget) {
+                const u64 tv = fill_qtable(p, k, g, combos, cap, budget, binom, nullptr);
+                if (runs_pay(tv, grid)) {
+                    tasks = tv;
+                    vcap = budget;
+                }
+            }
+        } else {
+            tasks0 = tasks = 0;  // the caller fills tasks, tiles and parts of these stages
         }
         for (int j = 1; j <= m; j++) {
             if (ns >= BZ_MAX_STAGES || sat_add(cum, cw) > max_codewords || combos >= (1ull << 32) ||
-                tasks >= (1ull << 62)) {
+                tasks0 >= (1ull << 62)) {
                 *complete = 0;
                 return ns;
             }
@@ -443,19 +499,20 @@ BZ_HD int build_schedule(int p, int k, int m, const int32_t *ranks, int flags, u
             for (int i = 1; i <= m; i++) L += bound_c(i <= j ? g : g - 1, k, ranks[i - 1]);
             d.L = L;
             d.check = (flags & FLAG_NO_TERM) ? 0 : ((flags & FLAG_ROUND) ? (j == m) : 1);
+            d.nowait = off < (u64)grid;
+            d.vcap = vcap;
+            d.pad = 0;
             d.tasks = tasks;
-            d.tiles = (tasks + WAVES_PER_GROUP - 1) / WAVES_PER_GROUP;
+            d.tiles = (d.tasks + WAVES_PER_GROUP - 1) / WAVES_PER_GROUP;
             d.codewords = cw;
             d.coef_combos = (uint32_t)combos;
             d.parts = (uint32_t)(d.tiles < (u64)grid ? d.tiles : (u64)grid);
             d.sweep_cap = cap;
-            const u64 off = deal_offset(m, tiles_before, j, d.tiles);
-            d.nowait = off < (u64)grid;
             d.rot = deal_rot(off, grid);
+            off = sat_add(off, d.tiles);
             cum = sat_add(cum, cw);
             ns++;
         }
-        tiles_before = sat_add(tiles_before, (tasks + WAVES_PER_GROUP - 1) / WAVES_PER_GROUP);
     }
     return ns;
 }

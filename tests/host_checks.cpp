@@ -222,7 +222,7 @@ static void check_schedule() {
 static int lane_parallel_schedule(int p, int k, int m, const int *ranks, int flags, u64 max_cw, uint32_t grid,
                                   int W, StageDesc *st, int *complete, uint32_t sweep_ops) {
     u64 cw[64], inc[64], tasks[64];
-    uint32_t combos[64];
+    uint32_t combos[64], vcaps[64];
     int js[64];
     for (int l = 0; l < 64; l++) {
         const int g = l + 1;
@@ -235,6 +235,7 @@ static int lane_parallel_schedule(int p, int k, int m, const int *ranks, int fla
         const u64 before = l ? inc[l - 1] : 0;
         js[l] = in ? round_stages(m, before, cw[l], cb, max_cw) : m;
         tasks[l] = (g <= SUBSET_G) ? small_stage_tasks(k, g) : 0;
+        vcaps[l] = 0;
     }
     int ns = k * m;
     *complete = 1;
@@ -247,13 +248,24 @@ static int lane_parallel_schedule(int p, int k, int m, const int *ranks, int fla
     const uint32_t cap = sweep_cap_for(p, W, sweep_ops);
     const int last_g = (ns + m - 1) / m;
     for (int g = SUBSET_G + 1; g <= last_g; g++) {
-        const u64 t = fill_qtable(k, g, combos[g - 1], cap, BINOM, nullptr);
+        // the kernel's per-q loop, with and without runs of bases (the digit
+        // count from its table of digits_by_steps)
+        const uint32_t budget = run_budget(p, cap);
+        u64 t = 0, tv = 0;
+        for (int q = g - 3; q <= k - 3; q++) {
+            const u64 bases = sat_mul32(BINOM[q * 65 + (g - 3)], combos[g - 1]);
+            const uint32_t nb = qgroup_blocks(k, cap, q);
+            t = sat_add(t, qgroup_tasks(bases, nb, 0));
+            if (p == 3) tv = sat_add(tv, qgroup_tasks(bases, nb, digits_of(g, digits_by_steps(k, q, budget), bases)));
+        }
         if (t >= (1ull << 62)) {
             ns = std::min(ns, (g - 1) * m);
             *complete = 0;
             break;
         }
-        tasks[g - 1] = t;
+        const bool runs = p == 3 && runs_pay(tv, grid);
+        tasks[g - 1] = runs ? tv : t;
+        vcaps[g - 1] = runs ? budget : 0u;
     }
     if (ns > BZ_MAX_STAGES) {
         ns = BZ_MAX_STAGES;
@@ -283,6 +295,8 @@ static int lane_parallel_schedule(int p, int k, int m, const int *ranks, int fla
         d.coef_combos = combos[g - 1];
         d.parts = (uint32_t)(d.tiles < (u64)grid ? d.tiles : (u64)grid);
         d.sweep_cap = cap;
+        d.vcap = vcaps[g - 1];
+        d.pad = 0;
         const u64 off = deal_offset(m, g >= 2 ? scan[g - 2] : 0, j, d.tiles);
         d.nowait = off < (u64)grid;
         d.rot = deal_rot(off, grid);
@@ -332,16 +346,22 @@ static void check_parallel_schedule() {
 // per-task counts the kernel adds up equal the combinations visited.
 static void check_unrank() {
     const int before = fails;
+    int vd_seen[BZ_MAX_VD + 1] = {0, 0, 0, 0};
     for (int P : {3, 7}) {
         for (int W : {1, 2, 4}) {
-            for (int k = 3; k <= 10; k++) {
-                for (int g = 1; g <= k && g <= 6; g++) {
+            for (int k = 3; k <= (P == 3 && W == 4 ? 13 : 10); k++) {
+                for (int g = 1; g <= k && g <= (P == 3 && W == 4 ? 7 : 6); g++) {
+                  // grid 1: every stage after the first waits (F_3: runs of bases);
+                  // a huge grid: every stage starts at once (one base per lane)
+                  for (uint32_t grid : {1u, 1u << 30}) {
+                    if (P == 7 && grid == 1) continue;
                     StageDesc st[BZ_MAX_STAGES];
                     int complete;
                     int32_t ranks[1] = {k};
-                    int ns = build_schedule(P, k, 1, ranks, FLAG_NO_TERM, ~0ull, 64, W, BINOM, st, &complete);
+                    int ns = build_schedule(P, k, 1, ranks, FLAG_NO_TERM, ~0ull, grid, W, BINOM, st, &complete);
                     CHECK(ns == k);
                     const StageDesc &d = st[g - 1];
+                    CHECK(d.vcap == ((P == 3 && g > SUBSET_G && grid == 1) ? d.sweep_cap : 0u));
                     std::map<std::vector<int>, int> seen;
                     u64 counted = 0;
                     auto add = [&](std::vector<int> rows, std::vector<int> coefs) {
@@ -400,7 +420,7 @@ static void check_unrank() {
                             }
                     } else {
                         std::vector<QEntry> tab(BZ_MAX_K);
-                        const u64 tasks = fill_qtable(k, g, d.coef_combos, d.sweep_cap, BINOM, tab.data());
+                        const u64 tasks = fill_qtable(P, k, g, d.coef_combos, d.sweep_cap, d.vcap, BINOM, tab.data());
                         CHECK(tasks == d.tasks);
                         const int nq = k - 2 - (g - 3);
                         for (u64 t = 0; t < d.tasks; t++) {
@@ -423,28 +443,61 @@ static void check_unrank() {
                             const int len = k - 2 - q, T = len * (len + 1) / 2;
                             CHECK(steps <= std::max(len, (T + (int)e.nb - 1) / (int)e.nb + len));
                             CHECK(s_hi - s_lo == 1 || steps <= 2 * (int)d.sweep_cap);
+                            // a lane's run of 2^vd bases: F_3 only, a whole group in one
+                            // block, within the step budget, every lane's run inside the group
+                            const int nv = 1 << e.vd;
+                            CHECK(e.vd <= (uint32_t)BZ_MAX_VD && (int)e.vd <= g - 3);
+                            if (e.vd > 0) {
+                                vd_seen[e.vd]++;
+                                CHECK(P == 3 && e.nb == 1 && (u64)nv * (u64)T <= d.sweep_cap);
+                                CHECK(e.bases % (u64)nv == 0 && e.bases >= 64 * (u64)nv);
+                            }
                             u64 nvalid = 0;
-                            for (int l = 0; l < 64; l++) {
-                                const u64 bi = chunk * 64 + (u64)l;
-                                if (bi >= e.bases) continue;
-                                nvalid++;
-                                std::vector<int> rows, coefs;
-                                auto bin = [&](int c, int i) { return BINOM[c * 65 + i]; };
+                            auto bin = [&](int c, int i) { return BINOM[c * 65 + i]; };
+                            auto decode = [&](u64 bi, std::vector<int> &rows, std::vector<int> &coefs) {
+                                rows.clear();
+                                coefs.clear();
                                 auto visit = [&](int row, int coef) { rows.push_back(row); coefs.push_back(coef); };
                                 if (P == 3) decode_base<3>(g, q, d.coef_combos, bi, bin, visit);
                                 else decode_base<7>(g, q, d.coef_combos, bi, bin, visit);
-                                CHECK((int)rows.size() == g - 2);
-                                CHECK(rows[0] == q);
-                                for (size_t i = 1; i < rows.size(); i++) CHECK(rows[i] < rows[i - 1]);
-                                for (int s = s_lo; s < s_hi; s++)
-                                    for (int a = 1; a < P; a++)
-                                        for (int L = s + 1; L < k; L++)
-                                            for (int h = 1; h < P; h++) {
-                                                std::vector<int> r2(rows), c2(coefs);
-                                                r2.push_back(s); c2.push_back(a);
-                                                r2.push_back(L); c2.push_back(h);
-                                                add(r2, c2);
-                                            }
+                            };
+                            for (int l = 0; l < 64; l++) {
+                                const u64 bi0 = (chunk * 64 + (u64)l) << e.vd;
+                                if (bi0 >= e.bases) continue;
+                                // the kernel's walk: decode the first base, then per step v
+                                // flip digit t = ctz(v) (coefficient 1 -> 2 or 2 -> 1 of the
+                                // t-th decoded row); the walk must meet the decodings of
+                                // bi0 .. bi0 + 2^vd - 1, each once
+                                std::vector<int> rows, coefs, r1, c1;
+                                decode(bi0, rows, coefs);
+                                std::set<std::vector<int>> walked, direct;
+                                uint32_t cur = 0;
+                                for (int v = 0; v < nv; v++) {
+                                    if (v > 0) {
+                                        const int t = __builtin_ctz((uint32_t)v);
+                                        const int h = ((cur >> t) & 1u) ? 2 : 1;
+                                        cur ^= 1u << t;
+                                        coefs[t] = (coefs[t] + h) % 3;
+                                    }
+                                    nvalid++;
+                                    decode(bi0 + (u64)v, r1, c1);
+                                    CHECK(r1 == rows);
+                                    walked.insert(coefs);
+                                    direct.insert(c1);
+                                    CHECK((int)rows.size() == g - 2);
+                                    CHECK(rows[0] == q);
+                                    for (size_t i = 1; i < rows.size(); i++) CHECK(rows[i] < rows[i - 1]);
+                                    for (int s = s_lo; s < s_hi; s++)
+                                        for (int a = 1; a < P; a++)
+                                            for (int L = s + 1; L < k; L++)
+                                                for (int h = 1; h < P; h++) {
+                                                    std::vector<int> r2(rows), c2(coefs);
+                                                    r2.push_back(s); c2.push_back(a);
+                                                    r2.push_back(L); c2.push_back(h);
+                                                    add(r2, c2);
+                                                }
+                                }
+                                CHECK(walked == direct && (int)walked.size() == nv);
                             }
                             for (int s = s_lo; s < s_hi; s++) counted += nvalid * (u64)((P - 1) * (P - 1) * (k - 1 - s));
                         }
@@ -457,16 +510,38 @@ static void check_unrank() {
                         CHECK(kv.second == 1);
                         CHECK(kv.first[1] == 1);  // coefficient of the lowest row
                     }
+                  }
                 }
             }
         }
     }
+    // every run length occurred (F_3 at W = 4 has the smallest step budget)
+    for (int v = 1; v <= BZ_MAX_VD; v++) CHECK(vd_seen[v] > 0);
     if (fails == before) std::printf("OK unrank\n");
 }
 
 // Bit helpers of the decomposition against plain definitions: compress (the
 // masked bits of x in order, to the low end), the saturating products and
 // powers against step-by-step saturation.
+// The digit count of a run of bases (closed form) against its definition: the
+// largest d <= min(g-3, 3) with T 2^d <= vcap and bases >= 64 2^d.
+static void check_digits() {
+    const int before = fails;
+    std::mt19937_64 rng(99);
+    for (int it = 0; it < 200000; it++) {
+        const int k = 4 + (int)(rng() % 61), g = 3 + (int)(rng() % 12), q = (int)(rng() % (k - 2));
+        const uint32_t vcap = (it % 7 == 0) ? 0u : 1u + (uint32_t)(rng() % 5000);
+        const u64 bases = (it % 3 == 0) ? rng() >> (rng() % 64) : rng() % 4096;
+        const uint32_t len = (uint32_t)(k - 2 - q), T = len * (len + 1) / 2;
+        uint32_t d = 0;
+        if (vcap)
+            while ((int)d < std::min(g - 3, BZ_MAX_VD) && (u64)T << (d + 1) <= vcap && (bases >> (d + 1)) >= 64) d++;
+        CHECK(qgroup_digits(3, k, g, vcap, q, bases) == d);
+        CHECK(qgroup_digits(7, k, g, vcap, q, bases) == 0);
+    }
+    if (fails == before) std::printf("OK digits\n");
+}
+
 static void check_bits() {
     const int before = fails;
     std::mt19937_64 rng(777);
@@ -549,6 +624,7 @@ int main() {
     check_top_row();
     check_bits();
     check_blocks();
+    check_digits();
     for (int a = 0; a <= 64; a++)
         for (int b = 0; b <= 64; b++) CHECK(binom_sat(a, b) == ~0ull || BINOM[a * 65 + b] == binom_sat(a, b));
     check_arith();
