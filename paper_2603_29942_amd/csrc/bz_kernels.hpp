@@ -147,8 +147,9 @@ struct DecompLDS {
 // One Gauss-Jordan step on the rows held one per lane: row pl (pivot value
 // pv in the pivot column) becomes pv^-1 times itself, every other row i
 // becomes row_i - v_i pv^-1 row_pl (v_i = its entry in the pivot column).
-// Branch-free per lane: the multiplier h of the raw pivot row is
-// h = pv^-1 on the pivot lane and -v pv^-1 elsewhere, and h * row is a
+// Branch-free per lane: a row takes h times the raw pivot row, h = -v pv^-1
+// off the pivot lane; the pivot lane's row is replaced by pv^-1 times the
+// pivot row (F_7) or adds pv^-1 - 1 times itself (F_3).  h * row is a
 // rotation and a negation of its planes (F_3: 2 = -1 swaps the planes; F_7:
 // every nonzero h is +-2^e, times 2 rotates the three planes, negation is the
 // complement on the nonzero positions, Sec. 4.2).
@@ -156,19 +157,22 @@ template <int P, int WF>
 __device__ __forceinline__ void eliminate(u32 (&x)[3][4], int v, int pl, int pv) {
     const int lane = __lane_id();
     const bool me = lane == pl;
-    const u32 keep = me ? 0u : ~0u;                     // pivot lane: replaced, others: added to
-    const u32 live = (me || v != 0) ? ~0u : 0u;         // rows with v = 0 are unchanged
     if constexpr (P == 3) {
-        // h = pv on the pivot lane, -v pv elsewhere: h = 2 (a swap) iff pv = 2,
-        // resp. iff v = pv
-        const bool sw = me ? (pv == 2) : (v == pv);
+        // every row adds h times the pivot row: h = pv^-1 - 1 = pv - 1 on the
+        // pivot lane (its own row, which so becomes pv^-1 times itself) and
+        // -v pv^-1 = -v pv elsewhere, i.e. 0 for v = 0, 2 for v = pv, else 1.
+        // h = 0: unchanged; h = 2: the planes swapped.
+        const bool sw = !me && v == pv;
+        const u32 live = (me ? pv == 2 : v != 0) ? ~0u : 0u;
 #pragma unroll
         for (int w = 0; w < WF; w++) {
             const u32 a0 = __builtin_amdgcn_readlane(x[0][w], pl), a1 = __builtin_amdgcn_readlane(x[1][w], pl);
             const u32 s0 = (sw ? a1 : a0) & live, s1 = (sw ? a0 : a1) & live;
-            f3_add(x[0][w] & keep, x[1][w] & keep, s0, s1, x[0][w], x[1][w]);
+            f3_add(x[0][w], x[1][w], s0, s1, x[0][w], x[1][w]);
         }
     } else {
+        const u32 keep = me ? 0u : ~0u;              // pivot lane: replaced, others: added to
+        const u32 live = (me || v != 0) ? ~0u : 0u;  // rows with v = 0 are unchanged
         // h = (-1)^neg 2^e; tables over v = 0..6 packed in constants:
         // e(v) two bits at 2v, neg(v) one bit at v (1, 2, 4 = +2^e; 6, 5, 3 = -2^e)
         constexpr u32 ETAB = 0x690u, NTAB = 0x68u;

@@ -199,6 +199,26 @@ def test_no_termination_histograms(bz, oracle, p, n, k):
                      identity_skip=skip)
 
 
+def test_runs_of_bases(bz, oracle):
+    """F_3 rounds whose stages give every workgroup a tile take runs of bases
+    (one decoding per lane, a Gray-code walk over the low coefficient digits).
+    With one workgroup per CU (256 workgroups), k = 17 takes runs from round 10
+    and k = 18 from round 9; with six per CU, k = 18 only from round 12.  The
+    full weight distribution of every stage equals the oracle's (k = 17) or
+    the other grid's (k = 18, where rounds 9-11 run with and without runs)."""
+    from math import comb
+    G = synth.random_generator(3, 34, 17, 0, stream=800)
+    r = run_both(bz, oracle, 3, G, "runs of bases k=17", hist=True, no_termination=True, blocks_per_cu=1)
+    assert all(st[2] == comb(17, st[0]) * 2 ** (st[0] - 1) for st in r["stages"])
+    G = synth.random_generator(3, 54, 18, 1, stream=800)
+    say("case runs of bases k=18 p=3 shape=(18, 54): grids of 1 and 6 workgroups per CU")
+    a = bz.min_distance(3, G, no_termination=True, histograms=True, blocks_per_cu=1)
+    b = bz.min_distance(3, G, no_termination=True, histograms=True, blocks_per_cu=6)
+    same(a, b, hist=True)
+    assert all(st[2] == comb(18, st[0]) * 2 ** (st[0] - 1) for st in a["stages"])
+    assert a["d"] == oracle.min_distance(3, G)["d"]
+
+
 def test_edge_cases(bz, oracle):
     for p in (3, 7):
         for n in (1, 2, 31, 32, 33, 64, 65, 128):
