@@ -189,7 +189,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
-              "the multi-GPU sharding is described in DESIGN.md but not built.", file=sys.stderr)
+              "sharding the stages over several GPUs is designed but not built.", file=sys.stderr)
         sys.exit(2)
 
     import torch
