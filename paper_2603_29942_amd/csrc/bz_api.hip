@@ -293,12 +293,14 @@ u64 batch_row_words(int n, int k) {
 
 int grow_batch(DevCtx &c, size_t ncodes, size_t row_words, size_t g_bytes) {
     if (ncodes > c.b_codes_cap) {
-        if (c.b_cs) {
-            hipFree(c.b_cs);
-            hipFree(c.b_codes);
-            hipHostFree(c.b_host_res);
-        }
+        // (errors of the frees are not actionable here; every pointer is reset so
+        // that a failed allocation below leaves nothing to free twice)
+        if (c.b_cs) (void)hipFree(c.b_cs);
+        if (c.b_codes) (void)hipFree(c.b_codes);
+        if (c.b_host_res) (void)hipHostFree(c.b_host_res);
         c.b_cs = nullptr;
+        c.b_codes = nullptr;
+        c.b_host_res = nullptr;
         c.b_codes_cap = 0;
         if (hipMalloc(&c.b_cs, sizeof(CodeState) * ncodes) != hipSuccess) return BZ_ERR_NOMEM;
         if (hipMalloc(&c.b_codes, sizeof(BatchCode) * ncodes) != hipSuccess) return BZ_ERR_NOMEM;
@@ -307,14 +309,14 @@ int grow_batch(DevCtx &c, size_t ncodes, size_t row_words, size_t g_bytes) {
         c.b_codes_cap = ncodes;
     }
     if (row_words > c.b_rows_cap) {
-        if (c.b_rows) hipFree(c.b_rows);
+        if (c.b_rows) (void)hipFree(c.b_rows);
         c.b_rows = nullptr;
         c.b_rows_cap = 0;
         if (hipMalloc(&c.b_rows, sizeof(u32) * row_words) != hipSuccess) return BZ_ERR_NOMEM;
         c.b_rows_cap = row_words;
     }
     if (g_bytes > c.b_g_cap) {
-        if (c.b_g) hipFree(c.b_g);
+        if (c.b_g) (void)hipFree(c.b_g);
         c.b_g = nullptr;
         c.b_g_cap = 0;
         if (hipMalloc(&c.b_g, g_bytes) != hipSuccess) return BZ_ERR_NOMEM;
@@ -738,15 +740,16 @@ struct bz_server {
 namespace {
 
 void server_free(bz_server *s) {
-    if (s->run) hipStreamSynchronize(s->run);
+    // teardown: errors are not actionable here
+    if (s->run) (void)hipStreamSynchronize(s->run);
     for (void *p : {(void *)s->cs, (void *)s->codes, (void *)s->rows, (void *)s->g, (void *)s->bs,
                     (void *)s->order_d, (void *)s->new_d, (void *)s->feat_d, (void *)s->pred_d, (void *)s->mlp_d})
-        if (p) hipFree(p);
+        if (p) (void)hipFree(p);
     for (void *p : {(void *)s->codes_h, (void *)s->g_h, (void *)s->yield_h, (void *)s->done_h, (void *)s->res_h,
                     (void *)s->order_h, (void *)s->new_h, (void *)s->pred_h})
-        if (p) hipHostFree(p);
-    if (s->round_done) hipEventDestroy(s->round_done);
-    if (s->run) hipStreamDestroy(s->run);
+        if (p) (void)hipHostFree(p);
+    if (s->round_done) (void)hipEventDestroy(s->round_done);
+    if (s->run) (void)hipStreamDestroy(s->run);
     delete s;
 }
 
