@@ -1012,13 +1012,15 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
             // s - lookahead is checked, or the run ended
             // the clock and the status word are read every 256 polls only: the
             // real-time counter is one shared unit, slow when a thousand waves read it
+            // (a nowait stage reads nothing: it starts at once, and work it
+            // does after the run has ended is never read)
             u64 t0 = 0;
-            int term;
-            u64 st;
-            for (uint32_t it = 0;; it++) {
+            int term = -1;
+            u64 st = wake_make(-1, -1);
+            for (uint32_t it = 0; !sd.nowait; it++) {
                 st = ld_poll(wake);
                 term = wake_term(st);
-                if (term >= 0 || sd.nowait || wake_checked(st) >= s - lookahead) break;
+                if (term >= 0 || wake_checked(st) >= s - lookahead) break;
                 if ((it & 255u) == 255u) {
                     if (ld_poll(&cs->res.status) != BZ_OK) {
                         term = -2;
