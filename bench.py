@@ -17,6 +17,7 @@ the oracle timed on the host cores on a bounded sample of the same workload.
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -80,10 +81,28 @@ def cpu_baseline(cfg, gpu_d, budget_s):
         match &= (r["d"] == gpu_d[seed])
         if spent >= budget_s:
             break
+    # one thread: the oracle's enumeration of one stage of the first code, the
+    # largest round with at most 1e7 combinations (a couple of seconds)
+    p, G = synth.config_code(cfg, 0)
+    k = G.shape[0]
+    _, gam, _, _ = bzref.decompose(p, G)
+    g1 = max(g for g in range(1, k + 1) if math.comb(k, g) * (p - 1) ** (g - 1) <= 10 ** 7)
+    t = time.perf_counter()
+    _, c1, _ = bzref.stage_enum(p, gam[0], g1, nthreads=1)
+    t1 = time.perf_counter() - t
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return {"value": cw / spent, "unit": "codewords/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(seeds)} whole {CONFIG_NAMES[cfg]} codes (seeds {seeds[0]}..{seeds[-1]}), "
                       f"{cw} combinations in {spent:.1f} s; oracle d equals GPU d: {match}",
-            "d_match": match}
+            "d_match": match, "cpu_model": model,
+            "single_thread": {"value": c1 / t1, "unit": "codewords/s", "cores": 1,
+                              "sample": f"stage g = {g1} of the first information set of seed 0: "
+                                        f"{c1} combinations in {t1:.2f} s"}}
 
 
 # The paper's arithmetic benchmark (Sec. 5, Tables 1-2): pairwise addition of
