@@ -101,15 +101,21 @@ struct RunArgs {
 // q-groups of a stage with g >= 3 computed by the 64 lanes of a wavefront
 // (lane = q - (g-3)); the same values as fill_qtable.  Returns the number of
 // tasks (wave-uniform); with tab != nullptr the lanes also store their entry.
+// The binomials C(q, g-3) come from the workgroup's LDS copy when g-3 < BIN_I
+// (C(c, i) at sbin[c * BIN_I + i]), else from the global table.
 __device__ __forceinline__ u64 wave_qtable(int p, int k, int g, u64 M, uint32_t cap, uint32_t vcap,
-                                           const u64 *__restrict__ binom, QEntry *tab) {
+                                           const u64 *sbin, const u64 *__restrict__ gbin, QEntry *tab) {
     const int lane = __lane_id();
     const int q = g - 3 + lane;
     const bool in = q <= k - 3;
     u64 bases = 0, val = 0;
     uint32_t nb = 0, vd = 0;
     if (in) {
-        qgroup(k, g, M, cap, vcap, binom, q, &bases, &nb, &vd, p);
+        // the values of qgroup
+        const u64 c = (g - 3 < BIN_I) ? sbin[q * BIN_I + (g - 3)] : gbin[q * 65 + (g - 3)];
+        bases = sat_mul(c, M);
+        nb = qgroup_blocks(k, cap, q);
+        vd = qgroup_digits(p, k, g, vcap, q, bases);
         val = qgroup_tasks(bases, nb, vd);  // <= 2^58 * 62: no overflow
     }
     // inclusive scan of val over the lanes (saturating)
@@ -696,11 +702,12 @@ __device__ __forceinline__ void extend_and_sweep(const u32 *__restrict__ rows, i
     }
 }
 
-// C(c, i) for i < BIN_I into LDS: every load of a thread is issued before
-// its first store (a loop that stores each value before the next load waits
-// for one memory round trip per element).  blockDim.x = 256.
-__device__ __forceinline__ void stage_binomials(u64 *sbin, const u64 *__restrict__ gbin) {
-    constexpr int N = BZ_MAX_K * BIN_I, PER = (N + 255) / 256;
+// C(c, i) for c < crows and i < BIN_I into LDS: every load of a thread is
+// issued before its first store (a loop that stores each value before the next
+// load waits for one memory round trip per element).  blockDim.x = 256.
+__device__ __forceinline__ void stage_binomials(u64 *sbin, const u64 *__restrict__ gbin, int crows) {
+    constexpr int NMAX = BZ_MAX_K * BIN_I, PER = (NMAX + 255) / 256;
+    const int N = min(crows, BZ_MAX_K) * BIN_I;
     u64 v[PER];
 #pragma unroll
     for (int r = 0; r < PER; r++) {
@@ -994,7 +1001,7 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
     const int status0 = cs->res.status, ns0 = cs->res.n_table;
     constexpr int EARLY = 32;  // descriptors loaded before the table size is known
     if (threadIdx.x < EARLY) sdesc[threadIdx.x] = cs->stages[threadIdx.x];
-    stage_binomials(sbin, gbin);
+    stage_binomials(sbin, gbin, k);  // the rows c < k: every binomial the stages read
     if (threadIdx.x >= EARLY && (int)threadIdx.x < ns0) sdesc[threadIdx.x] = cs->stages[threadIdx.x];
     __syncthreads();
     if (uni(status0) != BZ_OK) return;
@@ -1050,7 +1057,7 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
         if (wid == 0 && sd.g > SUBSET_G) {
             // the q-groups of the stage, unless the run ended (thread 0 is lane 0 of wave 0)
             const int tw = __builtin_amdgcn_readfirstlane(term0);
-            if (!(tw == -2 || (tw >= 0 && s > tw))) wave_qtable(P, k, sd.g, sd.coef_combos, sd.sweep_cap, sd.vcap, gbin, qtab);
+            if (!(tw == -2 || (tw >= 0 && s > tw))) wave_qtable(P, k, sd.g, sd.coef_combos, sd.sweep_cap, sd.vcap, sbin, gbin, qtab);
         }
         __syncthreads();
         const int term = s_term;
@@ -1274,7 +1281,7 @@ __global__ __launch_bounds__(256) void enum_batch_kernel(CodeState *css, const B
     __shared__ uint32_t s_part;
     const int lane = __lane_id();
     const int wid = threadIdx.x >> 6;
-    stage_binomials(sbin, gbin);
+    stage_binomials(sbin, gbin, BZ_MAX_K);
     uint32_t scan = (uint32_t)((u64)blockIdx.x * (u64)ncodes / gridDim.x);
     __syncthreads();
     for (;;) {
@@ -1354,7 +1361,7 @@ __global__ __launch_bounds__(256) void enum_batch_kernel(CodeState *css, const B
         const int n = uni(codes[code].n);
         const u64 row_off = uni64(codes[code].row_offset);
         const StageDesc sd = cs->stages[s];
-        if (wid == 0 && sd.g > SUBSET_G) wave_qtable(p, k, sd.g, sd.coef_combos, sd.sweep_cap, sd.vcap, gbin, qtab);
+        if (wid == 0 && sd.g > SUBSET_G) wave_qtable(p, k, sd.g, sd.coef_combos, sd.sweep_cap, sd.vcap, sbin, gbin, qtab);
         __syncthreads();
         const u32 woff = (uni(codes[code].flags) & FLAG_SKIP) ? (u32)sd.g : 0u;
         const u32 cap = (u32)n;
