@@ -11,6 +11,7 @@
 #include <algorithm>
 #include <cstring>
 #include <deque>
+#include <map>
 #include <mutex>
 #include <vector>
 
@@ -51,6 +52,9 @@ struct DevCtx {
     BatchState *b_state = nullptr;
     CodeResult *b_host_res = nullptr;
     BatchState *b_host_state = nullptr;
+    // the rounds' task counts per shape (p, k, W, grid, task size), on the
+    // device, built once on first use (fill_round_table)
+    std::map<std::vector<u64>, RoundTable *> rounds;
     std::mutex mu;
 };
 
@@ -407,6 +411,22 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, c
     a.grid = (uint32_t)grid;
     a.sweep_ops = DEFAULT_SWEEP_OPS;
     a.timeout_ticks = timeout;
+    {
+        const std::vector<u64> key = {(u64)p, (u64)k, (u64)W, (u64)grid, (u64)a.sweep_ops};
+        auto it = c->rounds.find(key);
+        if (it == c->rounds.end()) {
+            RoundTable t;
+            fill_round_table(p, k, W, (uint32_t)grid, a.sweep_ops, host_binom(), &t);
+            RoundTable *d = nullptr;
+            HIP_OK(hipMalloc(&d, sizeof(RoundTable)));
+            if (hipMemcpy(d, &t, sizeof(RoundTable), hipMemcpyHostToDevice) != hipSuccess) {
+                (void)hipFree(d);
+                return BZ_ERR_DEVICE;
+            }
+            it = c->rounds.emplace(key, d).first;
+        }
+        a.rounds = it->second;
+    }
     if (o.timing) HIP_OK(hipEventRecord(c->ev[0], s));
     HIP_OK(p == 3 ? launch_decompose<3>(WF, Gd, c->cs, c->rows, a, s)
                   : launch_decompose<7>(WF, Gd, c->cs, c->rows, a, s));

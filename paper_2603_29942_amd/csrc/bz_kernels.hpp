@@ -96,6 +96,7 @@ struct RunArgs {
     uint32_t grid;       // workgroups of the enumeration launch
     uint32_t sweep_ops;  // VALU operations per lane and task (sizes the blocks of rows s)
     u64 timeout_ticks;   // wall_clock64() ticks a workgroup may wait for earlier stages
+    const RoundTable *rounds;  // the rounds' task counts for this shape, or NULL: counted here
 };
 
 // q-groups of a stage with g >= 3 computed by the 64 lanes of a wavefront
@@ -458,14 +459,22 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
         const int last_g = (ns + m - 1) / m;
         const uint32_t cap = sweep_cap_for(P, W, args.sweep_ops);
         const uint32_t budget = run_budget(P, cap);
-        if (lane <= k - 3) {
+        const RoundTable *rt = args.rounds;
+        if (rt == nullptr && lane <= k - 3) {
             lds.s_nb[lane] = qgroup_blocks(k, cap, lane);
             if (P == 3) lds.s_dt[lane] = digits_by_steps(k, lane, budget);
         }
         __syncthreads();
         const bool counted = in && g > SUBSET_G && g <= last_g;
         u64 tg = 0, tgv = 0;  // without and with runs of bases
-        if (counted) {
+        if (rt != nullptr) {
+            // the table of this shape (fill_round_table)
+            if (counted) {
+                s_tasks[lane] = rt->tasks[lane];
+                lds.s_vcap[lane] = rt->vcap[lane];
+            }
+            tg = (counted && g >= rt->cut_g) ? (1ull << 62) : 0;  // the cut below, from cut_g
+        } else if (counted) {
             // q runs over a wave-uniform range (rows q < g-3 add nothing) so
             // that the unrolled LDS reads overlap
             const int q0 = uni(SUBSET_G - 2);  // the smallest g - 3 of a counted round
@@ -1160,6 +1169,7 @@ __global__ __launch_bounds__(64) void decompose_batch_kernel(const uint8_t *__re
     a.grid = grid;
     a.sweep_ops = bc.sweep_ops;
     a.timeout_ticks = 0;
+    a.rounds = nullptr;  // codes of every shape: the rounds are counted here
     const uint8_t *g = G + bc.g_offset;
     u32 *r = rows + bc.row_offset;
     if (bc.p == 3) {

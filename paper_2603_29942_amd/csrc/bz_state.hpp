@@ -517,6 +517,41 @@ BZ_HD int build_schedule(int p, int k, int m, const int32_t *ranks, int flags, u
     return ns;
 }
 
+// The task counts of the rounds g > SUBSET_G and their run budgets depend on
+// (p, k, W, grid, task size) only, not on the generator: the plain path
+// computes them once per shape on the host and the decomposition reads them
+// (the same values as build_schedule's and as the kernel's own loop).
+// cut_g: the first round whose count without runs reaches 2^62 (k + 1: none).
+struct RoundTable {
+    u64 tasks[BZ_MAX_K];     // round g at [g - 1]
+    uint32_t vcap[BZ_MAX_K];
+    int32_t cut_g;
+    uint32_t pad;
+};
+BZ_HD void fill_round_table(int p, int k, int W, uint32_t grid, uint32_t sweep_ops, const u64 *binom,
+                            RoundTable *t) {
+    const uint32_t cap = sweep_cap_for(p, W, sweep_ops), budget = run_budget(p, cap);
+    t->cut_g = k + 1;
+    t->pad = 0;
+    for (int g = 1; g <= BZ_MAX_K; g++) {
+        t->tasks[g - 1] = 0;
+        t->vcap[g - 1] = 0;
+        if (g <= SUBSET_G || g > k) continue;
+        const u64 combos = round_combos(p, g);
+        if (combos >= (1ull << 32)) continue;  // such rounds are never in a schedule
+        const u64 t0 = fill_qtable(p, k, g, combos, cap, 0, binom, nullptr);
+        if (t0 >= (1ull << 62) && t->cut_g > k) t->cut_g = g;
+        t->tasks[g - 1] = t0;
+        if (budget) {
+            const u64 tv = fill_qtable(p, k, g, combos, cap, budget, binom, nullptr);
+            if (runs_pay(tv, grid)) {
+                t->tasks[g - 1] = tv;
+                t->vcap[g - 1] = budget;
+            }
+        }
+    }
+}
+
 // Tile owned by workgroup b in round r of a stage whose deal is rotated by
 // rot.  Rounds alternate direction so that the heavy-first order of the items
 // spreads evenly over the workgroups; in round 0 workgroup off_s mod grid

@@ -217,10 +217,11 @@ static void check_schedule() {
 }
 
 // The decomposition kernel builds the schedule with one round g per lane (a
-// saturating scan of the codewords of the rounds, then one stage per lane);
-// replayed here, it gives the same table as build_schedule.
+// saturating scan of the codewords of the rounds, then one stage per lane),
+// the rounds' task counts from its own loop or from the per-shape table of the
+// plain path; replayed here both ways, it gives the same table as build_schedule.
 static int lane_parallel_schedule(int p, int k, int m, const int *ranks, int flags, u64 max_cw, uint32_t grid,
-                                  int W, StageDesc *st, int *complete, uint32_t sweep_ops) {
+                                  int W, StageDesc *st, int *complete, uint32_t sweep_ops, bool table) {
     u64 cw[64], inc[64], tasks[64];
     uint32_t combos[64], vcaps[64];
     int js[64];
@@ -247,7 +248,21 @@ static int lane_parallel_schedule(int p, int k, int m, const int *ranks, int fla
         }
     const uint32_t cap = sweep_cap_for(p, W, sweep_ops);
     const int last_g = (ns + m - 1) / m;
-    for (int g = SUBSET_G + 1; g <= last_g; g++) {
+    if (table) {
+        // the plain path: the rounds' counts from the per-shape table
+        static RoundTable rt;
+        fill_round_table(p, k, W, grid, sweep_ops, BINOM, &rt);
+        for (int g = SUBSET_G + 1; g <= last_g; g++) {
+            if (g >= rt.cut_g) {
+                ns = std::min(ns, (g - 1) * m);
+                *complete = 0;
+                break;
+            }
+            tasks[g - 1] = rt.tasks[g - 1];
+            vcaps[g - 1] = rt.vcap[g - 1];
+        }
+    }
+    for (int g = SUBSET_G + 1; g <= last_g && !table; g++) {
         // the kernel's per-q loop, with and without runs of bases (the digit
         // count from its table of digits_by_steps)
         const uint32_t budget = run_budget(p, cap);
@@ -329,13 +344,16 @@ static void check_parallel_schedule() {
         int ca = -1, cb = -1;
         const uint32_t ops = (it % 3 == 0) ? DEFAULT_SWEEP_OPS : 500u + (uint32_t)(rng() % 20000);
         const int na = build_schedule(p, k, m, ranks.data(), flags, max_cw, grid, W, BINOM, a, &ca, true, ops);
-        const int nb = lane_parallel_schedule(p, k, m, ranks.data(), flags, max_cw, grid, W, b, &cb, ops);
-        CHECK(na == nb && ca == cb);
-        if (na != nb) {
-            std::printf("  p=%d k=%d m=%d max=%llu: %d vs %d\n", p, k, m, (unsigned long long)max_cw, na, nb);
-            continue;
+        for (bool table : {false, true}) {
+            const int nb = lane_parallel_schedule(p, k, m, ranks.data(), flags, max_cw, grid, W, b, &cb, ops, table);
+            CHECK(na == nb && ca == cb);
+            if (na != nb) {
+                std::printf("  p=%d k=%d m=%d max=%llu table=%d: %d vs %d\n", p, k, m, (unsigned long long)max_cw,
+                            (int)table, na, nb);
+                continue;
+            }
+            for (int s = 0; s < na; s++) CHECK(std::memcmp(&a[s], &b[s], sizeof(StageDesc)) == 0);
         }
-        for (int s = 0; s < na; s++) CHECK(std::memcmp(&a[s], &b[s], sizeof(StageDesc)) == 0);
         cases++;
     }
     if (fails == before) std::printf("OK parallel schedule (%d cases)\n", cases);
