@@ -224,9 +224,14 @@ int finish(int p, int n, int k, int flags, u64 max_cw, const CodeResult &r, bz_r
     int complete = 1;
     int ns = 0;
     const int U0 = n - k + 1;
-    if ((flags & FLAG_NO_TERM) || U0 > 1)
-        ns = build_schedule(p, k, r.m, r.ranks, flags, max_cw ? max_cw : DEFAULT_LIMIT, 1, r.W, host_binom(), st,
-                            &complete, true, sweep_ops);
+    if ((flags & FLAG_NO_TERM) || U0 > 1) {
+        // the stage list without the task counts first (they only matter where a
+        // round would reach 2^62 tasks); with them when the stage counts differ
+        const u64 lim = max_cw ? max_cw : DEFAULT_LIMIT;
+        ns = build_schedule(p, k, r.m, r.ranks, flags, lim, 1, r.W, host_binom(), st, &complete, false, sweep_ops);
+        if (ns != r.n_table)
+            ns = build_schedule(p, k, r.m, r.ranks, flags, lim, 1, r.W, host_binom(), st, &complete, true, sweep_ops);
+    }
     if (ns != r.n_table) return BZ_ERR_DEVICE;
     int U = U0, term = -1;
     out->terminated_by = 2;
