@@ -54,7 +54,7 @@ struct DevCtx {
     BatchState *b_host_state = nullptr;
     // the rounds' task counts per shape (p, k, W, grid, task size), on the
     // device, built once on first use (fill_round_table)
-    std::map<std::vector<u64>, RoundTable *> rounds;
+    std::map<u64, RoundTable *> rounds;  // key: (p, k, W, grid, task size) in 64 bits
     std::mutex mu;
 };
 
@@ -417,7 +417,9 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, c
     a.sweep_ops = DEFAULT_SWEEP_OPS;
     a.timeout_ticks = timeout;
     {
-        const std::vector<u64> key = {(u64)p, (u64)k, (u64)W, (u64)grid, (u64)a.sweep_ops};
+        // (p, k, W, grid, task size) packed: 3 + 7 + 3 + 19 + 32 bits
+        const u64 key = ((u64)p << 61) | ((u64)k << 54) | ((u64)W << 51) | ((u64)(grid & 0x7ffff) << 32) |
+                        (u64)a.sweep_ops;
         auto it = c->rounds.find(key);
         if (it == c->rounds.end()) {
             RoundTable t;
