@@ -261,27 +261,30 @@ def main():
     ptr_t = [ctypes.c_void_p(Gt[i].data_ptr()) for i in range(K)]
     ptr_w = [ctypes.c_void_p(Gw[i].data_ptr()) for i in range(Gw.shape[0])]
 
-    def run(ptr):
-        st = fn(p, n, k, ptr, 1, o_ref, out_ref)
+    # one result block per step, read after the timed loop
+    outs = [bz.bz_result() for _ in range(K)]
+    out_refs = [ctypes.byref(r) for r in outs]
+
+    def run(ptr, ref):
+        st = fn(p, n, k, ptr, 1, o_ref, ref)
         if st != bz.OK:
             raise RuntimeError(f"bz_min_distance_ex: {bz.bz_status_str(st)}")
-        return out
 
     for i in range(Wm):
-        run(ptr_w[i])
+        run(ptr_w[i], out_ref)
     torch.cuda.synchronize()
-    per_step, cws, enum_ms, dec_ms, ds, words = [], [], [], [], [], []
+    per_step = [0.0] * K
     t0 = time.perf_counter()
     for i in range(K):
         ts = time.perf_counter()
-        r = run(ptr_t[i])
-        per_step.append(time.perf_counter() - ts)
-        cws.append(r.codewords_total)
-        enum_ms.append(r.enum_ms)
-        dec_ms.append(r.decompose_ms)
-        ds.append(r.d)
+        run(ptr_t[i], out_refs[i])
+        per_step[i] = time.perf_counter() - ts
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    cws = [r.codewords_total for r in outs]
+    enum_ms = [r.enum_ms for r in outs]
+    dec_ms = [r.decompose_ms for r in outs]
+    ds = [r.d for r in outs]
 
     W = (n - k + 31) // 32  # words per plane over the non-pivot columns
     opc = ops_per_codeword(p, W)
