@@ -55,6 +55,10 @@ struct DevCtx {
     // the rounds' task counts per shape (p, k, W, grid, task size), on the
     // device, built once on first use (fill_round_table)
     std::map<u64, RoundTable *> rounds;  // key: (p, k, W, grid, task size) in 64 bits
+    // the second information set computed ahead by a second workgroup of the
+    // decomposition launch, and the value its flag takes in this call
+    SpecBuf *spec = nullptr;
+    uint32_t spec_epoch = 0;
     std::mutex mu;
 };
 
@@ -95,6 +99,8 @@ int init_ctx(int dev) {
     if (hipMalloc(&c.rows, sizeof(u32) * BZ_MAX_M * BZ_MAX_K * ROW_WORDS) != hipSuccess) return BZ_ERR_NOMEM;
     if (hipMalloc(&c.binom, sizeof(u64) * 65 * 65) != hipSuccess) return BZ_ERR_NOMEM;
     if (hipMalloc(&c.hist, sizeof(u64) * BZ_MAX_STAGES * (BZ_MAX_N + 1)) != hipSuccess) return BZ_ERR_NOMEM;
+    if (hipMalloc(&c.spec, sizeof(SpecBuf)) != hipSuccess) return BZ_ERR_NOMEM;
+    HIP_OK(hipMemset(c.spec, 0, sizeof(SpecBuf)));
     if (hipHostMalloc(&c.host_res, sizeof(CodeResult), hipHostMallocDefault) != hipSuccess) return BZ_ERR_NOMEM;
     if (hipHostMalloc(&c.host_hist, sizeof(u64) * BZ_MAX_STAGES * (BZ_MAX_N + 1), hipHostMallocDefault) !=
         hipSuccess)
@@ -133,11 +139,12 @@ __global__ void zero_u64(u64 *p, size_t n) {
 template <int P>
 hipError_t launch_decompose(int WF, const uint8_t *G, CodeState *cs, u32 *rows, RunArgs a,
                             hipStream_t s) {
+    const int nb = a.spec ? 2 : 1;  // workgroup 1 computes the second information set ahead
     switch (WF) {
-    case 1: decompose_kernel<P, 1><<<1, 64, 0, s>>>(G, cs, rows, a); break;
-    case 2: decompose_kernel<P, 2><<<1, 64, 0, s>>>(G, cs, rows, a); break;
-    case 3: decompose_kernel<P, 3><<<1, 64, 0, s>>>(G, cs, rows, a); break;
-    default: decompose_kernel<P, 4><<<1, 64, 0, s>>>(G, cs, rows, a); break;
+    case 1: decompose_kernel<P, 1><<<nb, 64, 0, s>>>(G, cs, rows, a); break;
+    case 2: decompose_kernel<P, 2><<<nb, 64, 0, s>>>(G, cs, rows, a); break;
+    case 3: decompose_kernel<P, 3><<<nb, 64, 0, s>>>(G, cs, rows, a); break;
+    default: decompose_kernel<P, 4><<<nb, 64, 0, s>>>(G, cs, rows, a); break;
     }
     return hipGetLastError();
 }
@@ -434,6 +441,10 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, c
         }
         a.rounds = it->second;
     }
+    if (++c->spec_epoch == 0) c->spec_epoch = 1;
+    a.spec = c->spec;
+    a.epoch = c->spec_epoch;
+    a.pad = 0;
     if (o.timing) HIP_OK(hipEventRecord(c->ev[0], s));
     HIP_OK(p == 3 ? launch_decompose<3>(WF, Gd, c->cs, c->rows, a, s)
                   : launch_decompose<7>(WF, Gd, c->cs, c->rows, a, s));

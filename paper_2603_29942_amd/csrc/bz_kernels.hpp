@@ -97,6 +97,8 @@ struct RunArgs {
     uint32_t sweep_ops;  // VALU operations per lane and task (sizes the blocks of rows s)
     u64 timeout_ticks;   // wall_clock64() ticks a workgroup may wait for earlier stages
     const RoundTable *rounds;  // the rounds' task counts for this shape, or NULL: counted here
+    SpecBuf *spec;             // the second information set computed ahead, or NULL
+    uint32_t epoch, pad;       // this call's value of spec->flag
 };
 
 // q-groups of a stage with g >= 3 computed by the 64 lanes of a wavefront
@@ -207,9 +209,12 @@ __device__ __forceinline__ void eliminate(u32 (&x)[3][4], int v, int pl, int pv)
 }
 
 // One code on one wavefront (threads 0..63 of the workgroup).
+// ahead = true: the second workgroup of the plain path (see SpecBuf): the
+// elimination of one set with the columns 0 .. k-1 taken as used, packed into
+// args.spec, and nothing else.
 template <int P, int WF>
 __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32 *__restrict__ rows,
-                               const RunArgs args, DecompLDS &lds) {
+                               const RunArgs args, DecompLDS &lds, bool ahead = false) {
     constexpr int R = (P == 3) ? 2 : 3;
     u64 *binom = lds.binom;
     int32_t *sranks = lds.sranks;
@@ -218,9 +223,10 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
     // to scalars so that everything derived from them is wave-uniform
     const int n = uni(args.n), k = uni(args.k), flags = uni(args.flags);
     CodeResult &res = cs->res;
-    const bool tracing = (flags & FLAG_TRACE) != 0;
+    const bool tracing = !ahead && (flags & FLAG_TRACE) != 0;
     const u64 t_start = tracing ? (u64)wall_clock64() : 0;
-    if (lane == 0) {
+    SpecBuf *spec = args.spec;
+    if (lane == 0 && !ahead) {
         cs->p = P;
         cs->n = n;
         cs->k = k;
@@ -304,6 +310,18 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
     u32 used[4] = {0, 0, 0, 0};
     const bool skip = (flags & FLAG_SKIP) != 0;
     const int W = skip ? (n - k + 31) / 32 : WF;
+    // the columns 0 .. k-1
+    u32 firstk[4];
+#pragma unroll
+    for (int w = 0; w < 4; w++) {
+        const int lo = w * 32;
+        firstk[w] = (k >= lo + 32) ? 0xffffffffu : (k > lo ? ((1u << (k - lo)) - 1u) : 0u);
+    }
+    if (ahead) {
+#pragma unroll
+        for (int w = 0; w < 4; w++) used[w] = firstk[w];
+    }
+    bool first_is_firstk = false;  // the first set's pivots are the columns 0 .. k-1
 
     while (status == BZ_OK) {
         u32 unused[4];
@@ -314,6 +332,36 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
             anyu |= unused[w] != 0;
         }
         if (!anyu) break;
+        if (!ahead && spec != nullptr && m == 1 && first_is_firstk) {
+            // the second set from the workgroup that computed it ahead, when it
+            // has finished (a bounded wait; else it is computed here)
+            u32 f = 0;
+            for (int it = 0; it < 1024; it++) {
+                f = uni(__hip_atomic_load(&spec->flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT));
+                if (f == args.epoch) break;
+                __builtin_amdgcn_s_sleep(1);
+            }
+            if (f == args.epoch && uni(__hip_atomic_load(&spec->ok, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
+                const int kj2 = uni(__hip_atomic_load(&spec->kj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                if (lane < k) {
+                    const u32 *srow = spec->rows + (size_t)lane * ROW_WORDS;
+                    u32 *drow = rows + (size_t)(BZ_MAX_K + lane) * ROW_WORDS;
+#pragma unroll
+                    for (int w = 0; w < 16; w++)
+                        drow[w] = __hip_atomic_load(const_cast<u32 *>(srow + w), __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+                }
+#pragma unroll
+                for (int w = 0; w < 4; w++) {
+                    const u32 pm = uni(__hip_atomic_load(&spec->pivmask[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                    used[w] |= pm & unused[w];
+                }
+                if (lane == 0) sranks[1] = kj2;
+                m = 2;
+                if (kj2 < k || m == BZ_MAX_M) break;
+                continue;
+            }
+        }
         // Gauss-Jordan with the unused columns first, then the used ones, each
         // ascending; the pivot of a column is the lowest row that is not yet a
         // pivot row and has a nonzero entry there.  piv_lane = pivot index of
@@ -350,6 +398,8 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
             break;
         }
         if (kj == 0) break;
+        if (m == 0) first_is_firstk = kj == k && pivmask[0] == firstk[0] && pivmask[1] == firstk[1] &&
+                                      pivmask[2] == firstk[2] && pivmask[3] == firstk[3];
         // -- pack Gamma_m: row piv_lane of matrix m; slot 3 of each word = OR of planes.
         //    Identity skip: the n-k non-pivot columns of every row compressed, in
         //    order, into columns 0 .. n-k-1 (one column map for all rows; only
@@ -369,7 +419,8 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
             }
         }
         if (lane < k) {
-            u32 *dst = rows + (size_t)(m * BZ_MAX_K + piv_lane) * ROW_WORDS;
+            u32 *dst = ahead ? spec->rows + (size_t)piv_lane * ROW_WORDS
+                             : rows + (size_t)(m * BZ_MAX_K + piv_lane) * ROW_WORDS;
             u32 out[3][4];
 #pragma unroll
             for (int b = 0; b < 3; b++)
@@ -408,11 +459,30 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
                 dst[w * 4 + 3] = out[0][w] | out[1][w] | out[2][w];
             }
         }
+        if (ahead) {
+            // publish: the rows and the set's description, then the flag
+            if (lane == 0) {
+#pragma unroll
+                for (int w = 0; w < 4; w++) spec->pivmask[w] = pivmask[w] & unused[w];
+                spec->kj = kj;
+                spec->ok = 1;
+            }
+            __threadfence();
+            if (lane == 0) __hip_atomic_store(&spec->flag, args.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
         if (lane == 0) sranks[m] = kj;
         m++;
 #pragma unroll
         for (int w = 0; w < 4; w++) used[w] |= pivmask[w] & unused[w];
         if (kj < k || m == BZ_MAX_M) break;
+    }
+    if (ahead) {
+        // no second set to hand over (an invalid symbol, rank < k, no unused column)
+        if (lane == 0) spec->ok = 0;
+        __threadfence();
+        if (lane == 0) __hip_atomic_store(&spec->flag, args.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        return;
     }
     __syncthreads();
 
@@ -576,7 +646,8 @@ template <int P, int WF>
 __global__ __launch_bounds__(64) void decompose_kernel(const uint8_t *__restrict__ G, CodeState *cs,
                                                        u32 *__restrict__ rows, RunArgs args) {
     __shared__ DecompLDS lds;
-    decompose_code<P, WF>(G, cs, rows, args, lds);
+    // workgroup 1 (only with args.spec): the second information set ahead
+    decompose_code<P, WF>(G, cs, rows, args, lds, blockIdx.x == 1);
 }
 
 // =====================================================================
@@ -1170,6 +1241,9 @@ __global__ __launch_bounds__(64) void decompose_batch_kernel(const uint8_t *__re
     a.sweep_ops = bc.sweep_ops;
     a.timeout_ticks = 0;
     a.rounds = nullptr;  // codes of every shape: the rounds are counted here
+    a.spec = nullptr;
+    a.epoch = 0;
+    a.pad = 0;
     const uint8_t *g = G + bc.g_offset;
     u32 *r = rows + bc.row_offset;
     if (bc.p == 3) {

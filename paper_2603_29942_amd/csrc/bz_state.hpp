@@ -517,6 +517,18 @@ BZ_HD int build_schedule(int p, int k, int m, const int32_t *ranks, int flags, u
     return ns;
 }
 
+// The second information set computed ahead (plain path): a second
+// workgroup eliminates G with the column order {k, ..., n-1}, {0, ..., k-1},
+// which is the second set's order whenever the first set's pivots are columns
+// 0 .. k-1, and leaves the packed rows and the set's pivot columns and size
+// here; flag = the call's epoch once they are complete (and ok = 1).
+struct SpecBuf {
+    u32 rows[BZ_MAX_K * 16];
+    u32 pivmask[4];
+    int32_t kj, ok;
+    u32 flag, pad;
+};
+
 // The task counts of the rounds g > SUBSET_G and their run budgets depend on
 // (p, k, W, grid, task size) only, not on the generator: the plain path
 // computes them once per shape on the host and the decomposition reads them
