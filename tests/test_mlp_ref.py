@@ -37,3 +37,30 @@ def test_first_adam_step_closed_form():
     th, m, v = mlp_ref.adam(np.zeros(4), g, np.zeros(4), np.zeros(4), 1, 0.01)
     assert np.allclose(th, -0.01 * g / (np.abs(g) + 1e-8))
     assert np.allclose(m, 0.1 * g) and np.allclose(v, 0.001 * g * g)
+
+
+def test_adam_constant_gradient_closed_form():
+    # a constant gradient g from zero moments: m_t = (1 - b1^t) g and
+    # v_t = (1 - b2^t) g^2, so the bias-corrected moments are g and g^2 at every
+    # step and each step moves by lr * g / (|g| + eps)
+    g = np.array([0.5, -2.0, 1e-3, 3.0])
+    th, m, v = np.ones(4), np.zeros(4), np.zeros(4)
+    for t in range(1, 11):
+        th, m, v = mlp_ref.adam(th, g, m, v, t, 0.01)
+        assert np.allclose(th, 1.0 - t * 0.01 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-12)
+        assert np.allclose(m, (1 - 0.9 ** t) * g) and np.allclose(v, (1 - 0.999 ** t) * g * g)
+
+
+def test_two_adam_steps_closed_form():
+    # two steps with gradients g1, g2 from zero moments: the bias-corrected
+    # moments after step 2 are (b1 g1 + g2) / (1 + b1) and (b2 g1^2 + g2^2) / (1 + b2)
+    rng = np.random.default_rng(5)
+    g1, g2 = rng.normal(0, 1, 16), rng.normal(0, 1, 16)
+    b1, b2, lr, eps = 0.9, 0.999, 0.003, 1e-8
+    th0 = rng.normal(0, 1, 16)
+    th1, m1, v1 = mlp_ref.adam(th0, g1, np.zeros(16), np.zeros(16), 1, lr, b1, b2, eps)
+    th2, _, _ = mlp_ref.adam(th1, g2, m1, v1, 2, lr, b1, b2, eps)
+    mh = (b1 * g1 + g2) / (1 + b1)
+    vh = (b2 * g1 * g1 + g2 * g2) / (1 + b2)
+    want = th0 - lr * g1 / (np.abs(g1) + eps) - lr * mh / (np.sqrt(vh) + eps)
+    assert np.allclose(th2, want, rtol=0, atol=1e-12)

@@ -19,6 +19,8 @@ MUTANTS = {
     "bound_drops_plus_one": ("int v = g + 1 - (k - kj);", "int v = g - (k - kj);"),
     "bound_uses_rank_wrong": ("int v = g + 1 - (k - kj);", "int v = g + 1 - kj;"),
     "strict_termination": ("(!round_mode || j == m) && Lgj >= U", "(!round_mode || j == m) && Lgj > U"),
+    "round_check_first_matrix": ("(!round_mode || j == m) && Lgj >= U", "(!round_mode || j == 1) && Lgj >= U"),
+    "round_check_every_matrix": ("(!round_mode || j == m) && Lgj >= U", "(!round_mode || j >= 1) && Lgj >= U"),
     "singleton_off_by_one": ("int U = n - k + 1, L = 1;", "int U = n - k, L = 1;"),
     "elimination_sign": ("(A[i * n + t] + (p - f) * A[rank * n + t]) % p", "(A[i * n + t] + f * A[rank * n + t]) % p"),
     "coefficient_dropped": ("        for (int a = 1; a < p; a++) {\n            for (int t = 0; t < n; t++) next[t]",
@@ -50,6 +52,12 @@ def pin_suite(L):
           and r["terminated_by"] == 0)
     tetra = np.array(spec["tetracode_4_2_3"]["generator"], dtype=np.uint8)
     check("tetracode_trace", bzref.min_distance(3, tetra, _L=L)["stages"] == [(1, 1, 2, 3, 3, 3)])
+    # round mode (derived traces: only the last matrix of a round ends a run)
+    check("tetracode_round_trace", bzref.min_distance(3, tetra, check="round", _L=L)["stages"] ==
+          [(1, 1, 2, 3, 3, 3), (1, 2, 2, 3, 3, 4)])
+    r = bzref.min_distance(3, codes.extended_golay(), check="round", _L=L)
+    check("ext_golay_round_trace", r["stages"] == [(1, 1, 6, 6, 6, 3), (1, 2, 6, 6, 6, 4),
+                                                   (2, 1, 30, 6, 6, 5), (2, 2, 30, 6, 6, 6)])
     for n, k in [(7, 3), (6, 4), (7, 5)]:
         check("mds_d", bzref.min_distance(7, codes.reed_solomon(7, n, k), _L=L)["d"] == n - k + 1)
     # histogram identity on small random codes, and d against brute force

@@ -117,6 +117,51 @@ def test_tetracode(oracle):
     assert r["stages"] == [(1, 1, 2, 3, 3, 3)] and r["d"] == 3 and r["terminated_by"] == 0
 
 
+def test_round_mode_traces(oracle):
+    """Round mode (Algorithm 6 as listed) tests L >= U only after the last
+    matrix of a round.  Tetracode: every nonzero word has weight 3 and both
+    information sets have rank 2, so stage (1, 1) gives U = 3 with
+    L_{1,1} = c_1(1) + c_2(0) = 2 + 1 = 3, which ends a stage-mode run but not a
+    round-mode one; stage (1, 2) (two rows, weight 3 each) gives
+    L_{1,2} = 2 + 2 = 4 >= 3.  Extended Golay: L stays below U = 6 until
+    (2, 2), the last matrix of round 2, so both modes give the same trace."""
+    tetra = np.array(codes.golden("classical_codes.json")["tetracode_4_2_3"]["generator"], dtype=np.uint8)
+    r = oracle.min_distance(3, tetra, check="round")
+    assert r["stages"] == [(1, 1, 2, 3, 3, 3), (1, 2, 2, 3, 3, 4)]
+    assert r["terminated_by"] == 0 and r["d"] == 3 and r["codewords_total"] == 4
+    r = oracle.min_distance(3, codes.extended_golay(), check="round")
+    assert r["stages"] == [(1, 1, 6, 6, 6, 3), (1, 2, 6, 6, 6, 4), (2, 1, 30, 6, 6, 5),
+                           (2, 2, 30, 6, 6, 6)]
+    assert r["terminated_by"] == 0
+
+
+@pytest.mark.parametrize("p,n,k", [(3, 24, 8), (7, 16, 6), (3, 40, 10), (7, 20, 5), (3, 30, 6)])
+def test_round_mode_is_stage_mode_run_to_the_end_of_its_round(oracle, p, n, k):
+    """Both modes compute the same stages in the same order and differ only in
+    where they may stop: a round-mode run repeats the stage-mode trace, then
+    goes on to the first stage at or after it with j = m and L_{g,m} >= U, and
+    no earlier stage with j = m meets its bound."""
+    checked = 0
+    for seed in range(12):
+        G = _random_small(p, n, k, 300 + seed)
+        if oracle.rank(p, G) < k:
+            continue
+        st = oracle.min_distance(p, G)
+        rd = oracle.min_distance(p, G, check="round")
+        assert rd["d"] == st["d"] and rd["m"] == st["m"]
+        ns = len(st["stages"])
+        assert rd["stages"][:ns] == st["stages"]
+        m = rd["m"]
+        if rd["terminated_by"] == 0:
+            g, j, _, _, U, L = rd["stages"][-1]
+            assert j == m and L >= U
+        for g, j, _, _, U, L in rd["stages"][:-1]:
+            if j == m:
+                assert L < U
+        checked += 1
+    assert checked >= 6
+
+
 @pytest.mark.parametrize("n", [6, 7])
 @pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6])
 def test_mds_reed_solomon_f7(oracle, n, k):
