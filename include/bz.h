@@ -84,7 +84,12 @@ typedef struct {
        with HIP events on the call's stream (milliseconds); else 0 */
     float decompose_ms;
     float enum_ms;
+    int32_t info;                 /* BZ_INFO_* bits: how the run was carried out (never its result) */
 } bz_result;
+
+/* bz_result.info: the second information set was computed ahead by a second
+ * workgroup of the decomposition launch and handed over (see bz_options.no_ahead) */
+#define BZ_INFO_AHEAD 1
 
 typedef struct {
     int32_t check;            /* BZ_CHECK_STAGE (default) or BZ_CHECK_ROUND */
@@ -121,24 +126,46 @@ typedef struct {
                                  workgroups, so with an ordinary launch a workgroup kept off
                                  the device by other kernels delays the run until it starts
                                  (or until wait_timeout_s, BZ_ERR_DEVICE) */
+    int32_t no_ahead;         /* 1: the decomposition computes every information set itself;
+                                 0 (default): when the first set's pivots are the columns
+                                 0 .. k-1, the second set (columns k .. n-1 first) is taken
+                                 from a second workgroup that computed it in parallel, if it
+                                 has finished (BZ_INFO_AHEAD).  Results never depend on it */
 } bz_options;
 
 /* Fill *o with the defaults above. */
 void bz_default_options(bz_options *o);
 
-/* Minimum distance of the code generated by the host matrix G (k x n), default options. */
+/* Minimum distance d = min{wt(c) : c in C \ {0}} of the code generated by the
+ * host matrix G (k x n), default options: the problem statement of Sec. 3,
+ * computed with the rounds of Algorithm 6 (Sec. 3.1) over the information sets
+ * Gamma_j, the arithmetic of Sec. 2 (Algorithms 3, 4), the isometric last
+ * addition (Sec. 4.3) and the stage-by-stage termination test of Sec. 4.4.
+ * Returns BZ_OK and fills *out (d, m, the ranks k_j and the stage trace), or
+ * BZ_ERR_ARG / VALUE / RANK / LIMIT / DEVICE / NOMEM. */
 int bz_min_distance(int p, int n, int k, const uint8_t *G, bz_result *out);
 
-/* As bz_min_distance, with options.  G_is_device = 1: G is a device pointer
- * (already resident in GPU memory on options->device, readable from the
- * stream); 0: a host pointer, copied to the device inside the call.  On
- * return *out is complete and G is no longer read.  Without histograms or a
- * trace, the check that ends the run writes the result block to host memory
- * and the call returns as soon as it has, while workgroups of the launch may
- * still be retiring (work queued later on the stream runs after them); with
- * histograms or a trace the stream has been synchronised. */
+/* As bz_min_distance (Sec. 3; Algorithm 6 of Sec. 3.1), with options.
+ * G_is_device = 1: G is a device pointer (already resident in GPU memory on
+ * options->device, readable from the stream); 0: a host pointer, copied to
+ * the device inside the call.  On return *out is complete and G is no longer
+ * read.  Without histograms or a trace, the check that ends the run writes the
+ * result block to host memory and the call returns as soon as it has, while
+ * workgroups of the launch may still be retiring; the next call on this
+ * device waits for them (on the same stream by stream order, on another
+ * stream through an event).  With histograms or a trace the stream has been
+ * synchronised.  A call waits for the round in flight of every server on its
+ * device to yield (see bz_server_*) and keeps them from starting another
+ * until it returns: its persistent launch needs the whole device. */
 int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device,
                        const bz_options *o, bz_result *out);
+
+/* Releases what the library holds for a device (the library stream and
+ * events, the device workspace, pinned and mapped host buffers, the per-shape
+ * tables, the batch workspace) after waiting for its work; the next call on the
+ * device sets it up again.  BZ_ERR_ARG while a server runs on the device (stop
+ * it first).  Call it before the HIP runtime shuts down, e.g. at process exit. */
+int bz_release(int device);
 
 /* Human-readable name of a status code. */
 const char *bz_status_str(int status);
@@ -176,6 +203,9 @@ typedef struct {
                                 (default): an ordinary launch (the batched kernel hands out
                                 work dynamically, so it never waits for a workgroup that has
                                 not started) */
+    float *code_ms_out;      /* NULL, or a host array of ncodes floats: per code, the device
+                                time in ms from the start of the decomposition launch to the
+                                check that ended the code (its time to d within the batch) */
 } bz_batch_options;
 
 void bz_default_batch_options(bz_batch_options *o);

@@ -9,8 +9,10 @@ PyTorch is used only for device memory and streams: pass ``G`` as a CUDA
 (ROCm) uint8 tensor to hand the library a device pointer, and its current
 stream is used.
 """
+import atexit
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -23,7 +25,10 @@ CHECK_STAGE, CHECK_ROUND = 0, 1
 OP_ADD, OP_SUB, OP_DOUBLE, OP_ISO_ADD, OP_ISO_SUB, OP_KAT_ADD = range(6)
 ENC_NATURAL, ENC_KAT = 0, 1
 
+INFO_AHEAD = 1
+
 EXPORTS = ("bz_default_options", "bz_min_distance", "bz_min_distance_ex", "bz_status_str",
+           "bz_release",
            "bz_default_batch_options", "bz_min_distance_batch",
            "bz_mlp_forward", "bz_mlp_backward", "bz_mlp_adam",
            "bz_default_server_options", "bz_server_start", "bz_server_submit", "bz_server_poll", "bz_server_stats", "bz_server_stop",
@@ -40,7 +45,7 @@ class bz_result(ctypes.Structure):
     _fields_ = [("d", ctypes.c_int32), ("m", ctypes.c_int32), ("ranks", ctypes.c_int32 * MAX_M),
                 ("n_stages", ctypes.c_int32), ("terminated_by", ctypes.c_int32),
                 ("codewords_total", ctypes.c_uint64), ("stages", bz_stage * MAX_STAGES),
-                ("decompose_ms", ctypes.c_float), ("enum_ms", ctypes.c_float)]
+                ("decompose_ms", ctypes.c_float), ("enum_ms", ctypes.c_float), ("info", ctypes.c_int32)]
 
 
 class bz_options(ctypes.Structure):
@@ -50,7 +55,7 @@ class bz_options(ctypes.Structure):
                 ("hip_stream", ctypes.c_void_p), ("device", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("wait_timeout_s", ctypes.c_int32), ("trace_out", ctypes.POINTER(ctypes.c_uint64)),
-                ("cooperative", ctypes.c_int32)]
+                ("cooperative", ctypes.c_int32), ("no_ahead", ctypes.c_int32)]
 
 
 class bz_code(ctypes.Structure):
@@ -63,7 +68,8 @@ class bz_batch_options(ctypes.Structure):
                 ("identity_skip", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
                 ("max_codewords", ctypes.c_uint64), ("hip_stream", ctypes.c_void_p),
                 ("device", ctypes.c_int32), ("wait_timeout_s", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("decompose_ms", ctypes.c_float), ("enum_ms", ctypes.c_float), ("cooperative", ctypes.c_int32)]
+                ("decompose_ms", ctypes.c_float), ("enum_ms", ctypes.c_float), ("cooperative", ctypes.c_int32),
+                ("code_ms_out", ctypes.POINTER(ctypes.c_float))]
 
 
 class bz_server_options(ctypes.Structure):
@@ -76,10 +82,27 @@ class bz_server_options(ctypes.Structure):
 SERVE_FIFO, SERVE_PREDICTED = 0, 1
 
 _lib = None
+_devices_used = set()
+_live_servers = weakref.WeakSet()
 
 
 class LibraryMissing(RuntimeError):
     pass
+
+
+def _release_at_exit():
+    """Stop the servers still running and release the library's per-device
+    state (streams, events, device and host buffers) while the HIP runtime is
+    still up."""
+    if _lib is None:
+        return
+    for srv in list(_live_servers):
+        try:
+            srv.stop()
+        except Exception:
+            pass
+    for dev in sorted(_devices_used):
+        _lib.bz_release(int(dev))
 
 
 def lib():
@@ -96,6 +119,7 @@ def lib():
         L.bz_min_distance.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(bz_result)]
         L.bz_min_distance_ex.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int,
                                          ctypes.POINTER(bz_options), ctypes.POINTER(bz_result)]
+        L.bz_release.argtypes = [ctypes.c_int]
         L.bz_status_str.argtypes = [ctypes.c_int]
         L.bz_status_str.restype = ctypes.c_char_p
         L.bz_sliced_pack.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp]
@@ -123,6 +147,7 @@ def lib():
         L.bz_server_stop.argtypes = [vp]
         L.bz_server_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
         _lib = L
+        atexit.register(_release_at_exit)
     return _lib
 
 
@@ -153,14 +178,20 @@ def bz_min_distance_ex(p, G, options=None, out=None):
         if o.hip_stream is None:
             o.hip_stream = _stream_of(G)
         o.device = G.device.index or 0
+        _devices_used.add(o.device)
         st = lib().bz_min_distance_ex(p, n, k, ctypes.c_void_p(G.data_ptr()), 1, ctypes.byref(o),
                                       ctypes.byref(out))
     else:
         G = np.ascontiguousarray(G, dtype=np.uint8)
         k, n = G.shape
+        _devices_used.add(o.device)
         st = lib().bz_min_distance_ex(p, n, k, G.ctypes.data_as(ctypes.c_void_p), 0, ctypes.byref(o),
                                       ctypes.byref(out))
     return st, out
+
+
+def bz_release(device=0):
+    return lib().bz_release(int(device))
 
 
 def bz_min_distance(p, G):
@@ -175,18 +206,24 @@ def result_dict(st, r, hist=None):
     d = {"status": st, "d": r.d, "m": r.m, "ranks": [r.ranks[i] for i in range(r.m)],
          "terminated_by": r.terminated_by, "codewords_total": r.codewords_total,
          "stages": [(s.g, s.j, s.codewords, s.stage_min, s.upper_after, s.lower_after)
-                    for s in r.stages[:r.n_stages]]}
+                    for s in r.stages[:r.n_stages]], "info": r.info}
     if hist is not None:
         d["hist"] = hist[:r.n_stages].copy()
     return d
 
 
 def min_distance(p, G, *, check="stage", no_termination=False, identity_skip=True, max_codewords=0,
-                 histograms=False, blocks_per_cu=0, trace=False, cooperative=False):
+                 histograms=False, blocks_per_cu=0, trace=False, cooperative=False, ahead=True,
+                 wait_timeout_s=0, stream=None):
     """Convenience wrapper: same keys as the oracle's result dict (plus
-    ``trace``, the device timeline in ns, when asked for)."""
+    ``info`` and, when asked for, ``trace``, the device timeline in ns).
+    stream: a torch stream to run on (G on the device), else the current one."""
     o = bz_default_options()
     o.cooperative = int(bool(cooperative))
+    o.no_ahead = int(not ahead)
+    o.wait_timeout_s = int(wait_timeout_s)
+    if stream is not None:
+        o.hip_stream = ctypes.c_void_p(stream.cuda_stream)
     tr = None
     if trace:
         tr = np.zeros((MAX_STAGES + 2, 4), dtype=np.uint64)
@@ -244,10 +281,12 @@ def bz_min_distance_batch(buf, descs, options=None):
     nc = len(descs)
     out = (bz_result * max(nc, 1))()
     sts = (ctypes.c_int32 * max(nc, 1))()
+    _devices_used.add(o.device)
     if hasattr(buf, "is_cuda") and buf.is_cuda:
         if o.hip_stream is None:
             o.hip_stream = _stream_of(buf)
         o.device = buf.device.index or 0
+        _devices_used.add(o.device)
         st = lib().bz_min_distance_batch(nc, descs, ctypes.c_void_p(buf.data_ptr()), buf.numel(), 1,
                                          ctypes.byref(o), out, sts)
     else:
@@ -262,7 +301,8 @@ def min_distance_batch(codes, *, check="stage", no_termination=False, identity_s
                        cooperative=False):
     """Convenience wrapper: one result dict per code (same keys as
     min_distance).  sweep_ops: None, an int for every code, or a function
-    (p, W) -> int (e.g. the autotuner's table)."""
+    (p, W) -> int (e.g. the autotuner's table).  timing: also return the two
+    launches' times and every code's time to d within the batch (ms)."""
     buf, descs = pack_batch(codes, device=device)
     for i in range(len(codes)):
         if sweep_ops is None:
@@ -281,12 +321,15 @@ def min_distance_batch(codes, *, check="stage", no_termination=False, identity_s
     o.timing = int(bool(timing))
     o.wait_timeout_s = int(wait_timeout_s)
     o.cooperative = int(bool(cooperative))
+    code_ms = np.zeros(max(len(codes), 1), dtype=np.float32)
+    if timing:
+        o.code_ms_out = code_ms.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
     st, res, o = bz_min_distance_batch(buf, descs, o)
     if st != OK:
         raise RuntimeError(f"bz_min_distance_batch: {bz_status_str(st)}")
     out = [result_dict(s_i, r_i) for s_i, r_i in res]
     if timing:
-        return out, {"decompose_ms": o.decompose_ms, "enum_ms": o.enum_ms}
+        return out, {"decompose_ms": o.decompose_ms, "enum_ms": o.enum_ms, "code_ms": code_ms[:len(codes)].copy()}
     return out
 
 
@@ -317,6 +360,8 @@ class Server:
         h = ctypes.c_void_p()
         _check(lib().bz_server_start(ctypes.byref(o), ctypes.byref(h)), "bz_server_start")
         self._h = h
+        _devices_used.add(o.device)
+        _live_servers.add(self)
         self._max = int(max_out)
         self._tags = (ctypes.c_uint64 * self._max)()
         self._res = (bz_result * self._max)()

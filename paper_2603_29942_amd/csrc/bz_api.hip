@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -59,7 +60,19 @@ struct DevCtx {
     // decomposition launch, and the value its flag takes in this call
     SpecBuf *spec = nullptr;
     uint32_t spec_epoch = 0;
-    std::mutex mu;
+    // ordering of plain calls across streams: done_ev is recorded after the
+    // enumeration launch of the last plain call, on last_stream (its late
+    // workgroups may still update the workspace after the call returned)
+    hipEvent_t done_ev = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool have_last = false;
+    // servers running on this device (their rounds yield to plain calls),
+    // guarded by srv_mu; plain_active = 1 while a plain call runs, and no
+    // server starts a round meanwhile
+    std::vector<bz_server *> servers;
+    std::mutex srv_mu;
+    std::atomic<int> plain_active{0};
+    std::mutex mu;  // serialises the plain calls (and everything else) on the device
 };
 
 DevCtx g_ctx[MAX_DEV];
@@ -117,8 +130,55 @@ int init_ctx(int dev) {
     // timing only: no system-scope fence at the records (the results are read after a
     // stream synchronisation anyway), which otherwise writes back and invalidates caches
     for (auto &e : c.ev) HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
+    HIP_OK(hipEventCreateWithFlags(&c.done_ev, hipEventDisableTiming));
+    c.have_last = false;
     c.ready = true;
     return BZ_OK;
+}
+
+// Frees what init_ctx and later calls set up for the device (the caller holds
+// c.mu, the device is current and no server is registered).
+void release_ctx(DevCtx &c) {
+    // teardown: errors are not actionable here
+    if (c.stream) (void)hipStreamSynchronize(c.stream);
+    if (c.have_last && c.done_ev) (void)hipEventSynchronize(c.done_ev);
+    for (auto &kv : c.rounds) (void)hipFree(kv.second);
+    c.rounds.clear();
+    for (void *p : {(void *)c.g_buf, (void *)c.cs, (void *)c.rows, (void *)c.binom, (void *)c.hist, (void *)c.spec,
+                    (void *)c.b_cs, (void *)c.b_codes, (void *)c.b_rows, (void *)c.b_g, (void *)c.b_state})
+        if (p) (void)hipFree(p);
+    for (void *p : {(void *)c.host_res, (void *)c.host_hist, (void *)c.host_trace, (void *)c.res_map,
+                    (void *)c.flag_map, (void *)c.b_host_res, (void *)c.b_host_state})
+        if (p) (void)hipHostFree(p);
+    for (auto &e : c.ev)
+        if (e) (void)hipEventDestroy(e);
+    if (c.done_ev) (void)hipEventDestroy(c.done_ev);
+    if (c.stream) (void)hipStreamDestroy(c.stream);
+    c.g_buf = nullptr;
+    c.cs = nullptr;
+    c.rows = nullptr;
+    c.binom = nullptr;
+    c.hist = nullptr;
+    c.spec = nullptr;
+    c.b_cs = nullptr;
+    c.b_codes = nullptr;
+    c.b_rows = nullptr;
+    c.b_g = nullptr;
+    c.b_state = nullptr;
+    c.host_res = nullptr;
+    c.host_hist = nullptr;
+    c.host_trace = nullptr;
+    c.res_map = c.res_map_dev = nullptr;
+    c.flag_map = c.flag_map_dev = nullptr;
+    c.b_host_res = nullptr;
+    c.b_host_state = nullptr;
+    c.b_codes_cap = c.b_rows_cap = c.b_g_cap = 0;
+    for (auto &e : c.ev) e = nullptr;
+    c.done_ev = nullptr;
+    c.stream = nullptr;
+    c.last_stream = nullptr;
+    c.have_last = false;
+    c.ready = false;
 }
 
 int get_ctx(int dev, DevCtx **out) {
@@ -213,6 +273,18 @@ int enum_grid(int p, bool hist, int W, int cu, int bpc) {
     return hist ? grid_for_w<7, true>(W, cu, bpc) : grid_for_w<7, false>(W, cu, bpc);
 }
 
+// A plain call needs every workgroup of its persistent launch resident: it
+// holds the device's servers off while it runs (defined after bz_server).
+void servers_hold(DevCtx &c);
+void servers_release(DevCtx &c);
+struct PlainGuard {
+    DevCtx *c;
+    explicit PlainGuard(DevCtx *c_) : c(c_) { servers_hold(*c); }
+    ~PlainGuard() { servers_release(*c); }
+    PlainGuard(const PlainGuard &) = delete;
+    PlainGuard &operator=(const PlainGuard &) = delete;
+};
+
 int check_args(int p, int n, int k, const void *G, const void *out) {
     if (p != 3 && p != 7) return BZ_ERR_ARG;
     if (n < 1 || n > BZ_MAX_N || k < 1 || k > BZ_MAX_K || k > n) return BZ_ERR_ARG;
@@ -225,6 +297,7 @@ int finish(int p, int n, int k, int flags, u64 max_cw, const CodeResult &r, bz_r
            uint32_t sweep_ops = DEFAULT_SWEEP_OPS) {
     std::memset(out, 0, sizeof *out);
     out->m = r.m;
+    out->info = r.info;
     for (int j = 0; j < r.m && j < BZ_MAX_M; j++) out->ranks[j] = r.ranks[j];
     if (r.status != BZ_OK) return r.status;
     StageDesc st[BZ_MAX_STAGES];
@@ -349,6 +422,7 @@ int grow_batch(DevCtx &c, size_t ncodes, size_t row_words, size_t g_bytes) {
 __global__ void zero_batch_state(BatchState *bs) {
     bs->remaining = 0;
     bs->status = BZ_OK;
+    bs->t0 = ~0ull;
 }
 
 }  // namespace
@@ -391,6 +465,10 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, c
     std::lock_guard<std::mutex> lk(c->mu);
     HIP_OK(hipSetDevice(o.device));
     hipStream_t s = o.hip_stream ? (hipStream_t)o.hip_stream : c->stream;
+    PlainGuard guard(c);
+    // the previous plain call's late workgroups may still update the workspace
+    // (it returned at the final check): on another stream, wait for them
+    if (c->have_last && c->last_stream != s) HIP_OK(hipStreamWaitEvent(s, c->done_ev, 0));
 
     const int flags = (o.check == BZ_CHECK_ROUND ? FLAG_ROUND : 0) | (o.no_termination ? FLAG_NO_TERM : 0) |
                       (o.identity_skip ? FLAG_SKIP : 0) | (o.histograms ? FLAG_HIST : 0) |
@@ -442,7 +520,7 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, c
         a.rounds = it->second;
     }
     if (++c->spec_epoch == 0) c->spec_epoch = 1;
-    a.spec = c->spec;
+    a.spec = o.no_ahead ? nullptr : c->spec;
     a.epoch = c->spec_epoch;
     a.pad = 0;
     if (o.timing) HIP_OK(hipEventRecord(c->ev[0], s));
@@ -473,6 +551,9 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, c
     HIP_OK(p == 3 ? launch_enum<3>(o.histograms != 0, W, grid, c->cs, c->rows, c->binom, c->hist, ea, coop, s)
                   : launch_enum<7>(o.histograms != 0, W, grid, c->cs, c->rows, c->binom, c->hist, ea, coop, s));
     if (o.timing) HIP_OK(hipEventRecord(c->ev[2], s));
+    HIP_OK(hipEventRecord(c->done_ev, s));
+    c->last_stream = s;
+    c->have_last = true;
     bool have = false;
     if (mapped) {
         // the flag, or the end of the launch without it (no stage, a failed
@@ -636,6 +717,13 @@ int bz_min_distance_batch(int ncodes, const bz_code *codes, const uint8_t *G, ui
         const bz_code &cd = codes[i];
         status_out[i] = finish(cd.p, cd.n, cd.k, flags, max_cw, c->b_host_res[i], &out[i], bc[(size_t)i].sweep_ops);
     }
+    if (o.code_ms_out) {
+        const u64 t0 = c->b_host_state->t0;
+        for (int i = 0; i < ncodes; i++) {
+            const u64 t1 = c->b_host_res[i].t_end;
+            o.code_ms_out[i] = t1 > t0 ? (float)((double)(t1 - t0) * 1e3 / (double)c->ticks_per_s) : 0.0f;
+        }
+    }
     if (o.timing) {
         HIP_OK(hipEventElapsedTime(&o.decompose_ms, c->ev[0], c->ev[1]));
         HIP_OK(hipEventElapsedTime(&o.enum_ms, c->ev[1], c->ev[2]));
@@ -777,6 +865,22 @@ struct bz_server {
 
 namespace {
 
+void servers_hold(DevCtx &c) {
+    // under srv_mu for the whole wait: no server starts a round (or is freed)
+    // meanwhile; a round yields at the end of the part each workgroup holds
+    std::lock_guard<std::mutex> lk(c.srv_mu);
+    c.plain_active.store(1);
+    for (bz_server *s : c.servers) {
+        __atomic_store_n(s->yield_h, 1u, __ATOMIC_RELEASE);
+        (void)hipEventSynchronize(s->round_done);  // complete at once if no round was launched
+    }
+}
+
+void servers_release(DevCtx &c) {
+    std::lock_guard<std::mutex> lk(c.srv_mu);
+    c.plain_active.store(0);
+}
+
 void server_free(bz_server *s) {
     // teardown: errors are not actionable here
     if (s->run) (void)hipStreamSynchronize(s->run);
@@ -902,6 +1006,9 @@ int server_round(bz_server *s) {
         std::stable_sort(act.begin(), act.end(),
                          [&](int a, int b) { return s->slot[(size_t)a].seq < s->slot[(size_t)b].seq; });
     for (size_t j = 0; j < act.size(); j++) s->order_h[j] = act[j];
+    // a plain call on the device holds it: the round starts at a later poll
+    std::lock_guard<std::mutex> lk(s->c->srv_mu);
+    if (s->c->plain_active.load()) return BZ_OK;
     HIP_OK(hipMemcpyAsync(s->order_d, s->order_h, sizeof(int32_t) * act.size(), hipMemcpyHostToDevice, s->run));
     __atomic_store_n(s->yield_h, 0u, __ATOMIC_RELEASE);
     HIP_OK(wmax <= 2 && s->wmax <= 2 ? server_launch<2>(s, (int)act.size()) : server_launch<4>(s, (int)act.size()));
@@ -998,6 +1105,10 @@ int bz_server_start(const bz_server_options *opt, bz_server **out) {
         server_free(s);
         return BZ_ERR_DEVICE;
     }
+    {
+        std::lock_guard<std::mutex> lk(c->srv_mu);
+        c->servers.push_back(s);
+    }
     *out = s;
     return BZ_OK;
 }
@@ -1071,7 +1182,31 @@ int bz_server_stop(bz_server *s) {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->yield_h) __atomic_store_n(s->yield_h, 1u, __ATOMIC_RELEASE);
     }
+    {
+        std::lock_guard<std::mutex> lk(s->c->srv_mu);
+        auto &v = s->c->servers;
+        v.erase(std::remove(v.begin(), v.end(), s), v.end());
+    }
+    (void)hipSetDevice(s->dev);
     server_free(s);
+    return BZ_OK;
+}
+
+int bz_release(int device) {
+    if (device < 0 || device >= MAX_DEV) return BZ_ERR_ARG;
+    std::lock_guard<std::mutex> li(g_init_mu);
+    DevCtx &c = g_ctx[device];
+    std::lock_guard<std::mutex> lk(c.mu);
+    {
+        std::lock_guard<std::mutex> ls(c.srv_mu);
+        if (!c.servers.empty()) return BZ_ERR_ARG;
+    }
+    if (!c.ready) return BZ_OK;
+    int cur = 0;
+    const bool had = hipGetDevice(&cur) == hipSuccess;
+    HIP_OK(hipSetDevice(device));
+    release_ctx(c);
+    if (had) (void)hipSetDevice(cur);
     return BZ_OK;
 }
 

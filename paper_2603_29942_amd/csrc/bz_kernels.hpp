@@ -322,6 +322,7 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
         for (int w = 0; w < 4; w++) used[w] = firstk[w];
     }
     bool first_is_firstk = false;  // the first set's pivots are the columns 0 .. k-1
+    bool handed = false;           // the second set came from the workgroup ahead
 
     while (status == BZ_OK) {
         u32 unused[4];
@@ -358,6 +359,7 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
                 }
                 if (lane == 0) sranks[1] = kj2;
                 m = 2;
+                handed = true;
                 if (kj2 < k || m == BZ_MAX_M) break;
                 continue;
             }
@@ -635,6 +637,8 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
         res.status = status;
         res.m = m;
         res.W = W;
+        res.info = handed ? BZ_INFO_AHEAD : 0;
+        res.t_end = 0;
         res.ctl = ctl_make(0, -1, args.U0);
         res.n_table = ns;
         res.table_complete = complete;
@@ -751,11 +755,12 @@ __device__ __forceinline__ void complete_all(const u32 (&Pv)[NA][3][W], const u3
 }
 
 // Prefixes Q + h * Rs for the NA coefficients h = 1..NA of row s, then every
-// last row L = s+1..k-1 for all of them.
+// last row L = s+1..k-1 for all of them.  Returns the last rows combined
+// (each gives NA (p-1) combinations per lane).
 template <int P, int W, int NA, bool HIST>
-__device__ __forceinline__ void extend_and_sweep(const u32 *__restrict__ rows, int j, int s, int k,
-                                                 const u32 (&Q)[3][W], const Row<W> &Rs, u32 &lmin, u32 *lh,
-                                                 u32 woff, u32 cap) {
+__device__ __forceinline__ int extend_and_sweep(const u32 *__restrict__ rows, int j, int s, int k,
+                                                const u32 (&Q)[3][W], const Row<W> &Rs, u32 &lmin, u32 *lh,
+                                                u32 woff, u32 cap) {
     u32 Pv[NA][3][W], anyP[NA][W];
 #pragma unroll
     for (int a = 0; a < NA; a++) {
@@ -770,7 +775,7 @@ __device__ __forceinline__ void extend_and_sweep(const u32 *__restrict__ rows, i
     // UR rows per step, all loads issued before the first is used, so one wait
     // covers UR rows (rows past k-1 repeat row k-1 and are not combined)
     constexpr int UR = (W <= 2) ? 4 : 2;
-    for (int L = uni(s + 1); L < k; L += UR) {
+    return sweep_last_rows<UR>(uni(s), k, [&](int L, int nr) {
         Row<W> R[UR];
 #pragma unroll
         for (int u = 0; u < UR; u++) R[u] = load_row<P, W>(rows, j, min(L + u, k - 1));
@@ -778,8 +783,8 @@ __device__ __forceinline__ void extend_and_sweep(const u32 *__restrict__ rows, i
         for (int u = 0; u < UR; u++) pin_row<P, W>(R[u]);
 #pragma unroll
         for (int u = 0; u < UR; u++)
-            if (L + u < k) complete_all<P, W, NA, HIST>(Pv, anyP, R[u], lmin, lh, woff, cap);
-    }
+            if (u < nr) complete_all<P, W, NA, HIST>(Pv, anyP, R[u], lmin, lh, woff, cap);
+    });
 }
 
 // C(c, i) for c < crows and i < BIN_I into LDS: every load of a thread is
@@ -829,16 +834,19 @@ __device__ __forceinline__ void prefixes_then_complete(const u32 (&Q)[3][W], con
 // 1, the middle rows every multiplier (exact prefixes, two at a time to keep
 // the registers of F_7 in check), the top row every multiplier through
 // complete_all.
+// Adds the combinations completed to the lane's count ncomb.
 template <int P, int W, int G, bool HIST>
 __device__ __forceinline__ void run_subset(const u32 *__restrict__ rows, int j, const int (&r)[G], u32 &lmin,
-                                           u32 *lh, u32 woff, u32 cap) {
+                                           u32 &ncomb, u32 *lh, u32 woff, u32 cap) {
     constexpr int NA = 2;  // P - 1 is a multiple of 2
     const Row<W> R0 = load_row<P, W>(rows, j, r[0]);
     const Row<W> R1 = load_row<P, W>(rows, j, r[1]);
     const Row<W> R2 = load_row<P, W>(rows, j, r[2]);
     if constexpr (G == 3) {
-        for (int a0 = 1; a0 < P; a0 += NA)
+        for (int a0 = 1; a0 < P; a0 += NA) {
             prefixes_then_complete<P, W, NA, HIST>(R0.p, R1, a0, R2, lmin, lh, woff, cap);
+            ncomb += NA * (P - 1);
+        }
     } else {
         const Row<W> R3 = load_row<P, W>(rows, j, r[3]);
         for (int h = 1; h < P; h++) {
@@ -848,18 +856,21 @@ __device__ __forceinline__ void run_subset(const u32 *__restrict__ rows, int j, 
 #pragma unroll
                 for (int w = 0; w < W; w++) Q[b][w] = R0.p[b][w];
             add_scaled<P, W>(Q, R1.p, h);
-            for (int a0 = 1; a0 < P; a0 += NA)
+            for (int a0 = 1; a0 < P; a0 += NA) {
                 prefixes_then_complete<P, W, NA, HIST>(Q, R2, a0, R3, lmin, lh, woff, cap);
+                ncomb += NA * (P - 1);
+            }
         }
     }
 }
 
 // g <= SUBSET_G: one item per lane (a row, a pair of rows, a triple, a
-// quadruple; colex rank task * 64 + lane).  Returns the number of
-// combinations the wavefront evaluated (wave-uniform).
+// quadruple; colex rank task * 64 + lane).  Adds the combinations the lane
+// evaluated to lcnt.
 template <int P, int W, bool HIST>
-__device__ u64 run_small_task(int g, int k, int j, const u32 *__restrict__ rows, const u64 *sbin,
-                              const u64 *__restrict__ gbin, u64 task, u32 &lmin, u32 *lh, u32 woff, u32 cap) {
+__device__ void run_small_task(int g, int k, int j, const u32 *__restrict__ rows, const u64 *sbin,
+                               const u64 *__restrict__ gbin, u64 task, u32 &lmin, u64 &lcnt, u32 *lh, u32 woff,
+                               u32 cap) {
     const int lane = __lane_id();
     const u64 item = task * 64 + (u64)lane;
     if (g == 1) {
@@ -871,8 +882,9 @@ __device__ u64 run_small_task(int g, int k, int j, const u32 *__restrict__ rows,
             for (int w = 0; w < W; w++) wt += __builtin_popcount(r.any[w]);
             lmin = min(lmin, wt);
             if constexpr (HIST) count_hist<P, W, HIST>(lh, min(wt + woff, cap));
+            lcnt += 1;
         }
-        return (u64)__popcll(__ballot(valid));
+        return;
     }
     if (g == 2) {
         // a pair s < L; row s has coefficient 1, row L every multiplier
@@ -890,25 +902,25 @@ __device__ u64 run_small_task(int g, int k, int j, const u32 *__restrict__ rows,
 #pragma unroll
             for (int w = 0; w < W; w++) A1[0][w] = Rs.any[w];
             complete_all<P, W, 1, HIST>(Pv, A1, RL, lmin, lh, woff, cap);
+            lcnt += P - 1;
         }
-        return (u64)(P - 1) * (u64)__popcll(__ballot(pv));
+        return;
     }
     auto bin = [&](int c, int i) { return binom_at(sbin, gbin, c, i); };
     const bool valid = item < binom_sat(k, g);
+    u32 ncomb = 0;
     if (g == 3) {
         if (valid) {
             int r[3];
             decode_subset<3>(item, k, bin, r);
-            run_subset<P, W, 3, HIST>(rows, j, r, lmin, lh, woff, cap);
+            run_subset<P, W, 3, HIST>(rows, j, r, lmin, ncomb, lh, woff, cap);
         }
-        return (u64)((P - 1) * (P - 1)) * (u64)__popcll(__ballot(valid));
-    }
-    if (valid) {
+    } else if (valid) {
         int r[4];
         decode_subset<4>(item, k, bin, r);
-        run_subset<P, W, 4, HIST>(rows, j, r, lmin, lh, woff, cap);
+        run_subset<P, W, 4, HIST>(rows, j, r, lmin, ncomb, lh, woff, cap);
     }
-    return (u64)((P - 1) * (P - 1) * (P - 1)) * (u64)__popcll(__ballot(valid));
+    lcnt += ncomb;
 }
 
 // g > SUBSET_G: one task = (q, chunk of 64 lanes, block of rows s); see
@@ -916,11 +928,12 @@ __device__ u64 run_small_task(int g, int k, int j, const u32 *__restrict__ rows,
 // 2^vd bi + 2^vd - 1), vd > 0 only for F_3: they differ in the coefficients
 // (1 or 2) of the first vd rows in decoding order, the top row q first.  The
 // lane decodes the first of them and walks the others in Gray-code order, one
-// row added (coefficient 1 -> 2) or subtracted (2 -> 1) per step.
+// row added (coefficient 1 -> 2) or subtracted (2 -> 1) per step.  Adds the
+// combinations the lane evaluated (the rows its sweeps combined) to lcnt.
 template <int P, int W, bool HIST>
-__device__ u64 run_base_task(const StageDesc &sd, int k, int j, const u32 *__restrict__ rows, const u64 *sbin,
-                             const u64 *__restrict__ gbin, const QEntry *qtab, int nq, u64 task, u32 &lmin,
-                             u32 *lh, u32 woff, u32 cap) {
+__device__ void run_base_task(const StageDesc &sd, int k, int j, const u32 *__restrict__ rows, const u64 *sbin,
+                              const u64 *__restrict__ gbin, const QEntry *qtab, int nq, u64 task, u32 &lmin,
+                              u64 &lcnt, u32 *lh, u32 woff, u32 cap) {
     const int lane = __lane_id();
     const int g = uni(sd.g);
     const u64 M = uni(sd.coef_combos);
@@ -942,7 +955,10 @@ __device__ u64 run_base_task(const StageDesc &sd, int k, int j, const u32 *__res
     for (int b = 0; b < 3; b++)
 #pragma unroll
         for (int w = 0; w < W; w++) Q[b][w] = 0;
-    u64 cnt = 0;
+    // combinations this lane completes: p-1 coefficients of row s times p-1
+    // multipliers of every last row its sweeps combine
+    constexpr u32 PER_ROW = (u32)((P - 1) * (P - 1));
+    u32 ncomb = 0;
     if (vd == 0) {
         // one base per lane
         if (valid) {
@@ -952,14 +968,12 @@ __device__ u64 run_base_task(const StageDesc &sd, int k, int j, const u32 *__res
                                add_scaled<P, W>(Q, r.p, coef);
                            });
         }
-        const u64 nact = (u64)__popcll(__ballot(valid));
         for (int s = s_lo; s < s_hi; s++) {
-            // p-1 coefficients of row s, k-1-s last rows, p-1 multipliers, on nact lanes
-            cnt += nact * (u64)((P - 1) * (P - 1) * (k - 1 - s));
             const Row<W> Rs = load_row<P, W>(rows, j, uni(s));
-            if (valid) extend_and_sweep<P, W, P - 1, HIST>(rows, j, s, k, Q, Rs, lmin, lh, woff, cap);
+            if (valid) ncomb += PER_ROW * (u32)extend_and_sweep<P, W, P - 1, HIST>(rows, j, s, k, Q, Rs, lmin, lh, woff, cap);
         }
-        return cnt;
+        lcnt += ncomb;
+        return;
     }
     if constexpr (P == 3) {
         // a run of 2^vd bases per lane; the rows of digits 1 and 2 are held
@@ -976,8 +990,6 @@ __device__ u64 run_base_task(const StageDesc &sd, int k, int j, const u32 *__res
                                vi++;
                            });
         }
-        const u64 nact = (u64)__popcll(__ballot(valid)) << vd;
-        for (int s = s_lo; s < s_hi; s++) cnt += nact * (u64)((P - 1) * (P - 1) * (k - 1 - s));
         const int nv = 1 << vd;
         uint32_t cur = 0;  // bit t: digit t's row has coefficient 2 (wave-uniform)
         for (int v = 0; v < nv; v++) {
@@ -996,11 +1008,11 @@ __device__ u64 run_base_task(const StageDesc &sd, int k, int j, const u32 *__res
             }
             for (int s = s_lo; s < s_hi; s++) {
                 const Row<W> Rs = load_row<P, W>(rows, j, uni(s));
-                if (valid) extend_and_sweep<P, W, P - 1, HIST>(rows, j, s, k, Q, Rs, lmin, lh, woff, cap);
+                if (valid) ncomb += PER_ROW * (u32)extend_and_sweep<P, W, P - 1, HIST>(rows, j, s, k, Q, Rs, lmin, lh, woff, cap);
             }
         }
     }
-    return cnt;
+    lcnt += ncomb;
 }
 
 // Stage-completion check, run by one whole wavefront: lane i looks at stage
@@ -1153,7 +1165,7 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
         const u64 tiles = uni64(sd.tiles), tasks = uni64(sd.tasks);
         const u32 woff = skip ? (u32)sg : 0u;
         u32 lmin = BIG;
-        u64 cnt = 0;
+        u64 lcnt = 0;  // combinations this lane evaluated in the stage
         for (u64 r = 0;; r++) {
             const u64 tile = tile_of(r, b, grid, sd.rot);
             if (tile >= tiles) break;  // a missing tile only happens in the last round
@@ -1168,9 +1180,9 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
                 for (int w = lane; w <= n; w += 64) lh[w] = 0;
             }
             if (sg > SUBSET_G)
-                cnt += run_base_task<P, W, HIST>(sd, k, j, rows, sbin, gbin, qtab, nq, task, lmin, lh, woff, cap);
+                run_base_task<P, W, HIST>(sd, k, j, rows, sbin, gbin, qtab, nq, task, lmin, lcnt, lh, woff, cap);
             else
-                cnt += run_small_task<P, W, HIST>(sg, k, j, rows, sbin, gbin, task, lmin, lh, woff, cap);
+                run_small_task<P, W, HIST>(sg, k, j, rows, sbin, gbin, task, lmin, lcnt, lh, woff, cap);
             if constexpr (HIST) {
                 for (int w = lane; w <= n; w += 64) {
                     const u32 c = lh[w];
@@ -1179,10 +1191,13 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
             }
         }
         // workgroup reduction, then one set of atomics per workgroup and stage
-        for (int off = 32; off >= 1; off >>= 1) lmin = min(lmin, (u32)__shfl_xor((int)lmin, off));
+        for (int off = 32; off >= 1; off >>= 1) {
+            lmin = min(lmin, (u32)__shfl_xor((int)lmin, off));
+            lcnt += __shfl_xor(lcnt, off);
+        }
         if (lane == 0) {
             red_min[wid] = lmin;
-            red_cnt[wid] = cnt;
+            red_cnt[wid] = lcnt;
         }
         if constexpr (HIST) drain_vmem();  // this wave's histogram atomics are performed
         __syncthreads();
@@ -1228,6 +1243,7 @@ __global__ __launch_bounds__(64) void decompose_batch_kernel(const uint8_t *__re
                                                              const int32_t *__restrict__ slots, uint32_t *done_flags,
                                                              CodeResult *res_map) {
     __shared__ DecompLDS lds;
+    if (threadIdx.x == 0) atomicMin((unsigned long long *)&bs->t0, (unsigned long long)wall_clock64());
     const int c = slots ? slots[blockIdx.x] : (int)blockIdx.x;  // a list of slots, or every code
     const BatchCode bc = codes[c];
     CodeState *cs = css + c;
@@ -1267,6 +1283,7 @@ __global__ __launch_bounds__(64) void decompose_batch_kernel(const uint8_t *__re
         work = cs->res.status == BZ_OK && cs->res.n_table > 0;
         cs->claim = work ? claim_make(0, cs->stages[0].parts) : 0ull;
         if (work) atomicAdd(&bs->remaining, 1u);
+        else cs->res.t_end = (u64)wall_clock64();  // nothing to enumerate: ends here
     }
     // serving: a code with nothing to enumerate is done at once; its result
     // block (written by this wavefront with plain stores) goes to the device's
@@ -1294,26 +1311,25 @@ __global__ void features_kernel(const CodeState *__restrict__ css, const int32_t
 }
 
 // The tiles of one part of a stage: tile_of(r, part, parts, rot) for r = 0, 1, ...
+// The lane's combinations are added to lcnt.
 template <int P, int W>
-__device__ u64 run_part(const StageDesc &sd, int s, uint32_t part, int k, const u32 *__restrict__ rows,
-                        const u64 *sbin, const u64 *__restrict__ gbin, const QEntry *qtab, u32 woff, u32 cap,
-                        u32 &lmin) {
+__device__ void run_part(const StageDesc &sd, int s, uint32_t part, int k, const u32 *__restrict__ rows,
+                         const u64 *sbin, const u64 *__restrict__ gbin, const QEntry *qtab, u32 woff, u32 cap,
+                         u32 &lmin, u64 &lcnt) {
     const int wid = threadIdx.x >> 6;
     const int g = uni(sd.g), j = uni(sd.j - 1), nq = k - 2 - (g - 3);
     const u64 tiles = uni64(sd.tiles), tasks = uni64(sd.tasks);
     const uint32_t parts = uni(sd.parts);
-    u64 cnt = 0;
     for (u64 r = 0;; r++) {
         const u64 tile = tile_of(r, part, parts, sd.rot);
         if (tile >= tiles) break;
         const u64 task = tile * WAVES_PER_GROUP + (u64)wid;
         if (task >= tasks) continue;
         if (g > SUBSET_G)
-            cnt += run_base_task<P, W, false>(sd, k, j, rows, sbin, gbin, qtab, nq, task, lmin, nullptr, woff, cap);
+            run_base_task<P, W, false>(sd, k, j, rows, sbin, gbin, qtab, nq, task, lmin, lcnt, nullptr, woff, cap);
         else
-            cnt += run_small_task<P, W, false>(g, k, j, rows, sbin, gbin, task, lmin, nullptr, woff, cap);
+            run_small_task<P, W, false>(g, k, j, rows, sbin, gbin, task, lmin, lcnt, nullptr, woff, cap);
     }
-    return cnt;
 }
 
 // After the last part of stage s of a code: U takes the stage minimum, the
@@ -1329,6 +1345,7 @@ __device__ void batch_check(CodeState *cs, int s, const StageDesc &sd, BatchStat
         const int ns = cs->res.n_table;
         const bool stop = sd.check && sd.L >= U;
         last = stop || s + 1 >= ns;
+        if (last) __hip_atomic_store(&cs->res.t_end, (u64)wall_clock64(), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_exchange(&cs->res.ctl, stop ? ctl_make(s, s, U) : ctl_make(s + 1, -1, U), __ATOMIC_RELAXED,
                               __HIP_MEMORY_SCOPE_AGENT);
         drain_vmem();  // U is in place before the next stage can be claimed and checked
@@ -1451,22 +1468,25 @@ __global__ __launch_bounds__(256) void enum_batch_kernel(CodeState *css, const B
         const u32 cap = (u32)n;
         const u32 *r = rows + row_off;
         u32 lmin = BIG;
-        u64 cnt = 0;
+        u64 lcnt = 0;
         if (p == 3) {
-            if (W == 1) cnt = run_part<3, 1>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin);
-            if constexpr (WMAX >= 2) if (W == 2) cnt = run_part<3, 2>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin);
-            if constexpr (WMAX >= 3) if (W == 3) cnt = run_part<3, 3>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin);
-            if constexpr (WMAX >= 4) if (W == 4) cnt = run_part<3, 4>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin);
+            if (W == 1) run_part<3, 1>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin, lcnt);
+            if constexpr (WMAX >= 2) if (W == 2) run_part<3, 2>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin, lcnt);
+            if constexpr (WMAX >= 3) if (W == 3) run_part<3, 3>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin, lcnt);
+            if constexpr (WMAX >= 4) if (W == 4) run_part<3, 4>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin, lcnt);
         } else {
-            if (W == 1) cnt = run_part<7, 1>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin);
-            if constexpr (WMAX >= 2) if (W == 2) cnt = run_part<7, 2>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin);
-            if constexpr (WMAX >= 3) if (W == 3) cnt = run_part<7, 3>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin);
-            if constexpr (WMAX >= 4) if (W == 4) cnt = run_part<7, 4>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin);
+            if (W == 1) run_part<7, 1>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin, lcnt);
+            if constexpr (WMAX >= 2) if (W == 2) run_part<7, 2>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin, lcnt);
+            if constexpr (WMAX >= 3) if (W == 3) run_part<7, 3>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin, lcnt);
+            if constexpr (WMAX >= 4) if (W == 4) run_part<7, 4>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin, lcnt);
         }
-        for (int off = 32; off >= 1; off >>= 1) lmin = min(lmin, (u32)__shfl_xor((int)lmin, off));
+        for (int off = 32; off >= 1; off >>= 1) {
+            lmin = min(lmin, (u32)__shfl_xor((int)lmin, off));
+            lcnt += __shfl_xor(lcnt, off);
+        }
         if (lane == 0) {
             red_min[wid] = lmin;
-            red_cnt[wid] = cnt;
+            red_cnt[wid] = lcnt;
         }
         __syncthreads();
         if (wid == 0) {

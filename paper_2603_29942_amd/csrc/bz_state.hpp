@@ -79,8 +79,9 @@ struct CodeResult {
     int32_t n_table;      // stages in the schedule
     int32_t table_complete;  // 1: the schedule reaches g = k, j = m; 0: cut by the work limit
     u64 ctl;              // checker state, see ctl_make
+    u64 t_end;            // batches: wall_clock64() when the code ended (its last check)
     int32_t W;            // words per plane of the packed rows
-    int32_t pad;
+    int32_t info;         // BZ_INFO_* bits of bz_result.info
     int32_t ranks[BZ_MAX_M];
     int32_t stage_min[BZ_MAX_STAGES];
     u64 stage_count[BZ_MAX_STAGES];
@@ -135,10 +136,13 @@ struct BatchCode {
     uint32_t sweep_ops;  // VALU operations per lane and task
 };
 
-// Batch-wide state: codes with stages left, and the error flag of a time-out.
+// Batch-wide state: codes with stages left, the error flag of a time-out, and
+// the wall_clock64() start of the decomposition launch (the earliest
+// workgroup's), from which the codes' end times are counted.
 struct BatchState {
     uint32_t remaining;
     int32_t status;
+    u64 t0;
 };
 
 enum { FLAG_ROUND = 1, FLAG_NO_TERM = 2, FLAG_SKIP = 4, FLAG_HIST = 8, FLAG_TRACE = 16 };
@@ -427,6 +431,23 @@ BZ_HD int round_stages(int m, u64 cum, u64 cw, u64 combos, u64 max_codewords) {
     const u64 j = (max_codewords - cum) / cw;
     return j < (u64)m ? (int)j : m;
 }
+// The last-row sweep of a prefix built on row s: every row L = s+1 .. k-1 is
+// combined with it, UR rows at a time (the kernel issues the loads of a group
+// together).  group(L0, nr) combines rows L0 .. L0+nr-1 (nr <= UR).  Returns
+// the rows combined: the kernel's per-stage combination counts are taken from
+// this number, and the host replay drives the same loop, so a row skipped or
+// repeated here shows up in both.
+template <int UR, typename Group>
+BZ_HD int sweep_last_rows(int s, int k, Group &&group) {
+    int done = 0;
+    for (int L = s + 1; L < k; L += UR) {
+        const int nr = k - L < UR ? k - L : UR;
+        group(L, nr);
+        done += nr;
+    }
+    return done;
+}
+
 // Rounds g <= SUBSET_G give each lane one g-subset of the rows (all its
 // coefficient vectors); larger rounds give it a base of g-2 rows and sweep the
 // last two rows (see StageDesc).

@@ -505,19 +505,29 @@ static void check_unrank() {
                                     CHECK((int)rows.size() == g - 2);
                                     CHECK(rows[0] == q);
                                     for (size_t i = 1; i < rows.size(); i++) CHECK(rows[i] < rows[i - 1]);
-                                    for (int s = s_lo; s < s_hi; s++)
-                                        for (int a = 1; a < P; a++)
-                                            for (int L = s + 1; L < k; L++)
-                                                for (int h = 1; h < P; h++) {
-                                                    std::vector<int> r2(rows), c2(coefs);
-                                                    r2.push_back(s); c2.push_back(a);
-                                                    r2.push_back(L); c2.push_back(h);
-                                                    add(r2, c2);
-                                                }
+                                    // the kernel's last-row sweep (the same loop, groups of
+                                    // UR rows), each row with every coefficient a of row s and
+                                    // every multiplier h; the count is taken from the rows the
+                                    // sweep combined, as the kernel takes it
+                                    for (int s = s_lo; s < s_hi; s++) {
+                                        auto group = [&](int L0, int nr) {
+                                            for (int u = 0; u < nr; u++)
+                                                for (int a = 1; a < P; a++)
+                                                    for (int h = 1; h < P; h++) {
+                                                        std::vector<int> r2(rows), c2(coefs);
+                                                        r2.push_back(s); c2.push_back(a);
+                                                        r2.push_back(L0 + u); c2.push_back(h);
+                                                        add(r2, c2);
+                                                    }
+                                        };
+                                        const int done = (W <= 2) ? sweep_last_rows<4>(s, k, group)
+                                                                  : sweep_last_rows<2>(s, k, group);
+                                        counted += (u64)((P - 1) * (P - 1)) * (u64)done;
+                                    }
                                 }
                                 CHECK(walked == direct && (int)walked.size() == nv);
                             }
-                            for (int s = s_lo; s < s_hi; s++) counted += nvalid * (u64)((P - 1) * (P - 1) * (k - 1 - s));
+                            (void)nvalid;
                         }
                     }
                     u64 expect = C(k, g);

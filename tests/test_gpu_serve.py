@@ -49,15 +49,26 @@ def drain(srv, expect, limit_s=60.0):
     return out
 
 
-def check_alone(bz, reqs, results, label):
+def check_alone(bz, reqs, results, label, oracle=None):
+    """Each served result equals the plain path's on that code alone and, for
+    the requests with k <= 20 (the oracle finishes those in well under a
+    second), the oracle's: Algorithm 6 on that code alone."""
+    checked = 0
     for tag, (p, G) in enumerate(reqs):
         alone = bz.min_distance(p, G)
         for key in KEYS:
             assert results[tag][key] == alone[key], (label, tag, key, results[tag][key], alone[key])
+        if oracle is not None and G.shape[0] <= 20:
+            ref = oracle.min_distance(p, G)
+            for key in KEYS:
+                assert results[tag][key] == ref[key], (label, tag, key, "oracle", results[tag][key], ref[key])
+            checked += 1
+    if oracle is not None:
+        assert checked >= 20, checked
 
 
 @pytest.mark.parametrize("policy", ["fifo", "predicted"])
-def test_serve_all_at_once_equals_alone(bz, policy):
+def test_serve_all_at_once_equals_alone(bz, oracle, policy):
     from paper_2603_29942_amd import predictor
     reqs = requests(1, 120)
     say(f"case serve all at once policy={policy}: {len(reqs)} requests")
@@ -70,10 +81,10 @@ def test_serve_all_at_once_equals_alone(bz, policy):
         say(f"  {srv.stats()}")
     finally:
         srv.stop()
-    check_alone(bz, reqs, res, policy)
+    check_alone(bz, reqs, res, policy, oracle)
 
 
-def test_serve_arrivals_during_rounds_equal_alone(bz):
+def test_serve_arrivals_during_rounds_equal_alone(bz, oracle):
     """Requests arrive in waves while earlier ones run, more of them than
     slots: rounds yield, slots recycle, results never change."""
     reqs = requests(2, 300)
@@ -96,7 +107,7 @@ def test_serve_arrivals_during_rounds_equal_alone(bz):
         assert st["rounds"] > 1 and st["yields"] >= 1
     finally:
         srv.stop()
-    check_alone(bz, reqs, res, "waves")
+    check_alone(bz, reqs, res, "waves", oracle)
 
 
 def test_serve_rejects_oversize(bz):

@@ -29,6 +29,36 @@ def test_host_checks(tmp_path):
                                                    "OK parallel schedule", "OK unrank"]
 
 
+SWEEP_MUTANTS = {
+    "sweep_skips_first_row": ("for (int L = s + 1; L < k; L += UR) {", "for (int L = s + 2; L < k; L += UR) {"),
+    "sweep_drops_last_group_row": ("const int nr = k - L < UR ? k - L : UR;", "const int nr = k - L < UR ? k - L - 1 : UR;"),
+    "sweep_repeats_a_row": ("for (int L = s + 1; L < k; L += UR) {", "for (int L = s + 1; L < k; L += UR - 1) {"),
+    "sweep_counts_whole_groups": ("done += nr;", "done += UR;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(SWEEP_MUTANTS))
+def test_host_replay_catches_sweep_mutants(tmp_path, name):
+    """A row skipped, repeated or miscounted in the last-row sweep (the loop
+    the enumeration kernel and the host replay share) fails the replay."""
+    old, new = SWEEP_MUTANTS[name]
+    root = tmp_path / "tree"
+    (root / "pkg" / "csrc").mkdir(parents=True)
+    (root / "include").mkdir()
+    for f in ("bz_arith.hpp", "bz_state.hpp"):
+        src = open(os.path.join(CSRC, f)).read()
+        if f == "bz_state.hpp":
+            assert src.count(old) == 1, name
+            src = src.replace(old, new)
+        (root / "pkg" / "csrc" / f).write_text(src)
+    (root / "include" / "bz.h").write_text(open(HEADER).read())
+    exe = os.path.join(str(tmp_path), "host_checks")
+    subprocess.run(["g++", "-std=c++17", "-O1", "-DBZ_HD=inline", "-I", str(root / "pkg" / "csrc"), "-I",
+                    str(root / "include"), os.path.join(ROOT, "tests", "host_checks.cpp"), "-o", exe], check=True)
+    out = subprocess.run([exe], capture_output=True, text=True)
+    assert out.returncode != 0 and "OK unrank" not in out.stdout, name
+
+
 def _declared():
     src = open(HEADER).read()
     return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*(bz_\w+)\s*\(", src, re.M)))
@@ -65,7 +95,9 @@ def test_struct_layout(bzlib, tmp_path):
                 ' sizeof(bz_code), offsetof(bz_code, g_offset), sizeof(bz_batch_options),'
                 ' offsetof(bz_batch_options, hip_stream), offsetof(bz_batch_options, enum_ms));'
                 ' printf("%zu %zu %zu\\n", sizeof(bz_server_options), offsetof(bz_server_options, max_codewords),'
-                ' offsetof(bz_server_options, max_n)); return 0;}\n')
+                ' offsetof(bz_server_options, max_n));'
+                ' printf("%zu %zu %zu\\n", offsetof(bz_result, info), offsetof(bz_options, no_ahead),'
+                ' offsetof(bz_batch_options, code_ms_out)); return 0;}\n')
     exe = os.path.join(str(tmp_path), "layout")
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
     c_vals = [int(x) for x in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
@@ -75,7 +107,8 @@ def test_struct_layout(bzlib, tmp_path):
                ctypes.sizeof(bzlib.bz_code), bzlib.bz_code.g_offset.offset, ctypes.sizeof(bzlib.bz_batch_options),
                bzlib.bz_batch_options.hip_stream.offset, bzlib.bz_batch_options.enum_ms.offset,
                ctypes.sizeof(bzlib.bz_server_options), bzlib.bz_server_options.max_codewords.offset,
-               bzlib.bz_server_options.max_n.offset]
+               bzlib.bz_server_options.max_n.offset, bzlib.bz_result.info.offset, bzlib.bz_options.no_ahead.offset,
+               bzlib.bz_batch_options.code_ms_out.offset]
     assert c_vals == py_vals
 
 
@@ -141,3 +174,11 @@ def test_server_option_errors_need_no_device(bzlib):
         setattr(bad, field, value)  # policy 1 needs the network's parameters
         assert bzlib.lib().bz_server_start(ctypes.byref(bad), ctypes.byref(h)) == bzlib.ERR_ARG
     assert bzlib.lib().bz_server_submit(None, 3, 10, 4, None, 0) == bzlib.ERR_ARG
+
+
+def test_release_argument_errors_need_no_device(bzlib):
+    """Releasing a device that was never set up does nothing; a device
+    ordinal out of range is an argument error."""
+    L = bzlib.lib()
+    assert L.bz_release(-1) == bzlib.ERR_ARG and L.bz_release(16) == bzlib.ERR_ARG
+    assert L.bz_release(3) == bzlib.OK  # never set up
