@@ -1,21 +1,27 @@
 """Benchmark: exact minimum distance of random linear codes on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--config 4]
 
-A step is one whole run of the path on one code: information-set
-decomposition, packing, every enumeration stage with the isometric last
-addition, popcount weight and min-reduce, and the L >= U test, until the
-minimum distance is known.  The default workload is one random F_3 [72,36]
-code per step (seed = step index; generator entries i.i.d. uniform), its
-generator already resident in GPU memory when the timed region starts.
+Default workload (config 4): a step is one call of the batched path on 512
+random codes of mixed field and size (half F_3, half F_7, n uniform in
+[30, 90], rate 1/2 or 1/3; F_7 n <= 56 at rate 1/2 and n <= 63 at rate 1/3),
+their generators already resident in GPU memory: one information-set
+decomposition launch and one persistent enumeration launch compute every
+code's minimum distance (the stages of Algorithm 6 with the isometric last
+addition, popcount weights, min-reduce and the L >= U test).  The same codes
+then run on the plain path (one call per code), and the two are compared:
+combinations evaluated per second and each code's time to d (p50 / p99).
 
-Prints one JSON line: value = combinations evaluated per second over the
-timed steps (whole job), time-to-d percentiles, the roofline position of the
-enumeration kernel (device time from HIP events on the library's stream) and
-the oracle timed on the host cores on a bounded sample of the same workload.
+Prints one JSON line: value = combinations evaluated per second by the
+batched path over the timed steps (whole job), the plain path on the same
+codes, the roofline position of the persistent enumeration kernel (device
+time from HIP events on the launch's stream), two sub-blocks with the plain
+path on F_3 [72,36] and F_7 [48,24] (20 codes each, each with its own
+roofline), and the oracle timed on the host cores on a bounded sample of the
+same batch.  --config 1-3 time one workload of the plain path alone, 5 the
+serving loop.
 """
 import argparse
-import hashlib
 import json
 import math
 import os
@@ -44,11 +50,8 @@ def pct(xs, q):
 
 
 def kernel_source_hash():
-    h = hashlib.sha256()
-    for f in ("bz_kernels.hpp", "bz_arith.hpp", "bz_state.hpp"):
-        with open(os.path.join(ROOT, "paper_2603_29942_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
+    from paper_2603_29942_amd import autotune
+    return autotune.kernel_source_hash()
 
 
 def traffic_for(kernel, workload):
@@ -64,45 +67,103 @@ def traffic_for(kernel, workload):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(cfg, gpu_d, budget_s):
-    """The oracle as it stands, on the host cores, over whole codes of the same
-    workload (seeds 0, 1, ...) until about budget_s seconds have been spent."""
+def cpu_model():
+    """The host CPU as the kernel reports it: model name, family / model /
+    stepping, clock, and the hardware threads this process may use."""
+    info = {}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if ":" not in line:
+                    if info:
+                        break  # the first processor's block is enough
+                    continue
+                key, val = (x.strip() for x in line.split(":", 1))
+                if key in ("vendor_id", "model name", "cpu family", "model", "stepping", "cpu MHz") and key not in info:
+                    info[key] = val
+                if key == "flags":
+                    info["hypervisor"] = "hypervisor" in val.split()
+    except OSError:
+        pass
+    info["logical_cpus"] = os.cpu_count()
+    info["usable_cpus"] = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return info
+
+
+# The paper's own CPU timings of the method (another machine: context only).
+PAPER_CPU_CONTEXT = {
+    "processor": "AMD EPYC 7F52, 16 cores (the paper's Sec. 5)",
+    "F_7 [50,25,13], one core (Table 3)": {"SC8 s": 29.57, "SS64I s": 8.44, "SS64IN s": 5.15},
+    "F_7 [52,19,19] (Table 4)": {"SS64IN 1 core s": 21.90, "SS64IN 4 cores s": 5.69},
+    "note": "the paper's codes are not published; these figures are not on this workload",
+}
+
+
+def cpu_baseline_codes(codes, gpu, budget_s, budget_1t_s, max_cw):
+    """The oracle as it stands, on the host cores, over whole codes of the
+    benchmark's own workload, in order, skipping codes above max_cw
+    combinations (by the GPU's count) until about budget_s seconds have been
+    spent: its rate, its time to d per code (p50 / p99) and d equality with the
+    GPU.  Then the same codes on one thread for about budget_1t_s seconds."""
+    from oracle import bzref
+    threads = bzref.threads(0)
+
+    def run(nthreads, budget):
+        cw, spent, times, used, match = 0, 0.0, [], [], True
+        for i, (p, G) in enumerate(codes):
+            if gpu[i]["codewords_total"] > max_cw:
+                continue
+            t = time.perf_counter()
+            r = bzref.min_distance(p, G, nthreads=nthreads)
+            dt = time.perf_counter() - t
+            spent += dt
+            times.append(dt)
+            cw += r["codewords_total"]
+            used.append(i)
+            match &= (r["d"] == gpu[i]["d"] and r["codewords_total"] == gpu[i]["codewords_total"])
+            if spent >= budget:
+                break
+        return cw, spent, times, used, match
+
+    cw, spent, times, used, match = run(threads, budget_s)
+    cw1, spent1, times1, used1, match1 = run(1, budget_1t_s)
+    return {"value": cw / spent, "unit": "codewords/s", "cores": threads, "kind": "oracle",
+            "sample": f"the first {len(used)} codes of the timed batch of seed 0 with at most {max_cw:.0e} "
+                      f"combinations (codes {used[0]}..{used[-1]}), whole runs, {cw} combinations in {spent:.1f} s; "
+                      f"oracle d and counts equal the GPU's: {match}",
+            "d_match": bool(match and match1),
+            "time_to_d_ms": {"p50": pct(times, 50) * 1e3, "p99": pct(times, 99) * 1e3, "codes": len(times)},
+            "single_thread": {"value": cw1 / spent1, "unit": "codewords/s", "cores": 1,
+                              "time_to_d_ms": {"p50": pct(times1, 50) * 1e3, "p99": pct(times1, 99) * 1e3},
+                              "sample": f"the first {len(used1)} of those codes, whole runs on one thread: "
+                                        f"{cw1} combinations in {spent1:.1f} s"},
+            "cpu": cpu_model(), "paper_context": PAPER_CPU_CONTEXT}
+
+
+def cpu_baseline_plain(cfg, gpu_d, budget_s):
+    """The oracle on the host cores over whole codes of a single-code workload
+    (seeds 0, 1, ...) for about budget_s seconds."""
     from oracle import bzref
     from paper_2603_29942_amd import synth
     threads = bzref.threads(0)
-    cw, spent, seeds, match = 0, 0.0, [], True
+    cw, spent, seeds, match, times = 0, 0.0, [], True, []
     for seed in range(len(gpu_d)):
         p, G = synth.config_code(cfg, seed)
         t = time.perf_counter()
         r = bzref.min_distance(p, G, nthreads=threads)
-        spent += time.perf_counter() - t
+        dt = time.perf_counter() - t
+        spent += dt
+        times.append(dt)
         cw += r["codewords_total"]
         seeds.append(seed)
         match &= (r["d"] == gpu_d[seed])
         if spent >= budget_s:
             break
-    # one thread: the oracle's enumeration of one stage of the first code, the
-    # largest round with at most 1e7 combinations (a couple of seconds)
-    p, G = synth.config_code(cfg, 0)
-    k = G.shape[0]
-    _, gam, _, _ = bzref.decompose(p, G)
-    g1 = max(g for g in range(1, k + 1) if math.comb(k, g) * (p - 1) ** (g - 1) <= 10 ** 7)
-    t = time.perf_counter()
-    _, c1, _ = bzref.stage_enum(p, gam[0], g1, nthreads=1)
-    t1 = time.perf_counter() - t
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as f:
-            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
-    except OSError:
-        pass
     return {"value": cw / spent, "unit": "codewords/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(seeds)} whole {CONFIG_NAMES[cfg]} codes (seeds {seeds[0]}..{seeds[-1]}), "
                       f"{cw} combinations in {spent:.1f} s; oracle d equals GPU d: {match}",
-            "d_match": match, "cpu_model": model,
-            "single_thread": {"value": c1 / t1, "unit": "codewords/s", "cores": 1,
-                              "sample": f"stage g = {g1} of the first information set of seed 0: "
-                                        f"{c1} combinations in {t1:.2f} s"}}
+            "d_match": match, "time_to_d_ms": {"p50": pct(times, 50) * 1e3, "p99": pct(times, 99) * 1e3},
+            "cpu": cpu_model(), "paper_context": PAPER_CPU_CONTEXT}
 
 
 # The paper's arithmetic benchmark (Sec. 5, Tables 1-2): pairwise addition of
@@ -187,82 +248,32 @@ def micro(nvec=10000, nsym=512, reps=10000, passes=2000):
             "dtype": "u32", "data": "synthetic", "results": out}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", type=int, default=2, choices=[1, 2, 3, 4, 5],
-                    help="1-3: one code per step (plain path); 4: the 512-code mixed batch per step; "
-                         "5: serving under Poisson arrivals")
-    ap.add_argument("--requests", type=int, default=2000, help="config 5: requests per policy")
-    ap.add_argument("--blocks-per-cu", type=int, default=0)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--micro", action="store_true",
-                    help="only run the sliced-arithmetic benchmark (Tables 1-2 sizes) and print its JSON line")
-    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
-                    help="only run 5 device-to-device copies of MIB MiB (the known-size copy kernel that "
-                         "scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
-    args = ap.parse_args()
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
-              "sharding the stages over several GPUs is designed but not built.", file=sys.stderr)
-        sys.exit(2)
-
+def bench_plain(cfg, K, Wm, blocks_per_cu=0):
+    """The plain path on one single-code workload: K codes (seeds 0..K-1), one
+    call each, generators resident in HBM, Wm warm-up calls on other seeds.
+    The call's arguments are prepared once, as a C caller holding its inputs
+    in HBM would: a step is the library call."""
+    import ctypes
+    import numpy as np
     import torch
     from paper_2603_29942_amd import bz, synth
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-    if args.micro:
-        print(json.dumps(micro()), flush=True)
-        return
-    if args.copy_calibration:
-        nbytes = args.copy_calibration << 20
-        a = torch.ones(nbytes, dtype=torch.uint8, device=dev)
-        b = torch.empty_like(a)
-        for _ in range(5):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 5}), flush=True)
-        return
-    cfg = args.config
-    if cfg == 4:
-        print(json.dumps(bench_batch(args)), flush=True)
-        return
-    if cfg == 5:
-        print(json.dumps(bench_serve(args)), flush=True)
-        return
     p, n, k = synth.CONFIGS[cfg]
-    K, Wm = args.steps, args.warmup
-    # inputs resident in HBM before timing: timed seeds 0..K-1, warm-up seeds 10000+
-    Gt = torch.from_numpy(
-        __import__("numpy").stack([synth.config_code(cfg, s)[1] for s in range(K)])).to(dev)
-    Gw = torch.from_numpy(
-        __import__("numpy").stack([synth.config_code(cfg, 10000 + s)[1] for s in range(max(Wm, 1))])).to(dev)
+    Gt = torch.from_numpy(np.stack([synth.config_code(cfg, s)[1] for s in range(K)])).to(dev)
+    Gw = torch.from_numpy(np.stack([synth.config_code(cfg, 10000 + s)[1] for s in range(max(Wm, 1))])).to(dev)
     torch.cuda.synchronize()
-
-    # one options block for the whole run (as a caller issuing many codes
-    # would keep it): the library's stream is torch's current one
     o = bz.bz_default_options()
     o.timing = 1
-    o.blocks_per_cu = args.blocks_per_cu
+    o.blocks_per_cu = blocks_per_cu
     o.max_codewords = 1 << 40
     o.hip_stream = bz._stream_of(Gt)
-    out = bz.bz_result()
-
-    # the generators' device addresses and the call's arguments prepared once,
-    # as a C caller holding its inputs in HBM would: a step is the library call
-    import ctypes
     o.device = dev.index or 0
+    out = bz.bz_result()
     fn = bz.lib().bz_min_distance_ex
     o_ref, out_ref = ctypes.byref(o), ctypes.byref(out)
     ptr_t = [ctypes.c_void_p(Gt[i].data_ptr()) for i in range(K)]
     ptr_w = [ctypes.c_void_p(Gw[i].data_ptr()) for i in range(Gw.shape[0])]
-
-    # one result block per step, read after the timed loop
-    outs = [bz.bz_result() for _ in range(K)]
+    outs = [bz.bz_result() for _ in range(K)]  # one result block per step, read after the loop
     out_refs = [ctypes.byref(r) for r in outs]
 
     def run(ptr, ref):
@@ -284,65 +295,90 @@ def main():
     cws = [r.codewords_total for r in outs]
     enum_ms = [r.enum_ms for r in outs]
     dec_ms = [r.decompose_ms for r in outs]
-    ds = [r.d for r in outs]
-
     W = (n - k + 31) // 32  # words per plane over the non-pivot columns
     opc = ops_per_codeword(p, W)
     total_cw = sum(cws)
-    enum_s = sum(enum_ms) / 1e3
-    achieved = total_cw * opc / enum_s / 1e12
-    workload = f"f{p}_{n}_{k}"
-    line = {
-        "metric": "codewords evaluated/s (whole job, plain path: one code per call)",
-        "value": total_cw / elapsed,
-        "unit": "codewords/s",
-        "n_gpus": 1,
-        "steps": K,
-        "warmup": Wm,
-        "ms_per_step": elapsed / K * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32",
-        "data": "synthetic",
-        "config": {"workload": f"one random {CONFIG_NAMES[cfg]} code per step (seeds 0..{K - 1}), "
-                               "plain path, generator resident on the GPU",
-                   "p": p, "n": n, "k": k, "identity_skip": True,
-                   "blocks_per_cu": args.blocks_per_cu or "occupancy"},
+    achieved = total_cw * opc / (sum(enum_ms) / 1e3) / 1e12
+    return {
+        "workload": f"one random {CONFIG_NAMES[cfg]} code per step (seeds 0..{K - 1}), plain path, "
+                    "generator resident on the GPU",
+        "p": p, "n": n, "k": k, "steps": K, "warmup": Wm,
+        "value": total_cw / elapsed, "unit": "codewords/s", "ms_per_step": elapsed / K * 1e3,
         "time_to_d_ms": {"p50": pct(per_step, 50) * 1e3, "p99": pct(per_step, 99) * 1e3,
                          "mean": elapsed / K * 1e3},
         "codewords_per_step": {"mean": total_cw / K, "min": min(cws), "max": max(cws)},
-        "d": {"min": min(ds), "max": max(ds)},
+        "d": [r.d for r in outs],
         "kernel_ms_per_step": {"decompose": sum(dec_ms) / K, "enum": sum(enum_ms) / K},
         "roofline": {"kernel": "enum_kernel", "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "TOPS (int32 VALU lane-ops/s)", "frac": achieved / VALU_PEAK_TOPS,
-                     "traffic": traffic_for("enum_kernel", workload),
+                     "traffic": traffic_for("enum_kernel", f"f{p}_{n}_{k}"),
                      "ops_per_codeword": opc, "avg_launch_ms": sum(enum_ms) / K},
     }
-    # the same K codes as one batch: one decomposition launch and one persistent launch
-    codes_t = [(p, Gt[i]) for i in range(K)]
-    sweep_fn, bpc_tuned = autotune_table()
-    buf, descs = bz.pack_batch(codes_t, device=dev)
-    for i in range(K):
-        descs[i].sweep_ops = int(sweep_fn(p, W))
-    bz.min_distance_batch([(p, Gw[0])] * 4, device=dev, sweep_ops=sweep_fn, blocks_per_cu=bpc_tuned)
-    torch.cuda.synchronize()
-    o = bz.bz_default_batch_options()
-    o.timing = 1
-    o.blocks_per_cu = bpc_tuned
-    tb = time.perf_counter()
-    bst, bres, o = bz.bz_min_distance_batch(buf, descs, o)
-    tb = time.perf_counter() - tb
-    if bst != bz.OK:
-        raise RuntimeError(f"bz_min_distance_batch: {bz.bz_status_str(bst)}")
-    bcw = sum(r.codewords_total for _, r in bres)
-    line["batched_same_codes"] = {
-        "value": bcw / tb, "unit": "codewords/s", "ms_for_all_steps": tb * 1e3,
-        "speedup_vs_plain": (bcw / tb) / (total_cw / elapsed),
-        "d_equal_plain": [r.d for _, r in bres] == ds,
-        "kernel_ms": {"decompose": o.decompose_ms, "enum": o.enum_ms}}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", type=int, default=4, choices=[1, 2, 3, 4, 5],
+                    help="4 (default): the 512-code mixed batch per step, batched against plain; "
+                         "1-3: one code per step (plain path); 5: serving under Poisson arrivals")
+    ap.add_argument("--sub-steps", type=int, default=20, help="config 4: codes of each plain sub-block")
+    ap.add_argument("--no-plain", action="store_true", help="config 4: skip the plain path on the batch's codes")
+    ap.add_argument("--requests", type=int, default=2000, help="config 5: requests per policy")
+    ap.add_argument("--blocks-per-cu", type=int, default=0)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--micro", action="store_true",
+                    help="only run the sliced-arithmetic benchmark (Tables 1-2 sizes) and print its JSON line")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 device-to-device copies of MIB MiB (the known-size copy kernel that "
+                         "scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "sharding the stages over several GPUs is designed but not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    if args.micro:
+        print(json.dumps(micro()), flush=True)
+        return
+    if args.copy_calibration:
+        nbytes = args.copy_calibration << 20
+        a = torch.ones(nbytes, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 5}), flush=True)
+        return
+    cfg = args.config
+    if cfg == 4:
+        print(json.dumps(bench_batch(args)), flush=True)
+        return
+    if cfg == 5:
+        print(json.dumps(bench_serve(args)), flush=True)
+        return
+    K, Wm = args.steps, args.warmup
+    blk = bench_plain(cfg, K, Wm, args.blocks_per_cu)
+    line = {
+        "metric": "codewords evaluated/s (whole job, plain path: one code per call)",
+        "value": blk["value"], "unit": "codewords/s", "n_gpus": 1, "steps": K, "warmup": Wm,
+        "ms_per_step": blk["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32", "data": "synthetic",
+        "config": {"workload": blk["workload"], "p": blk["p"], "n": blk["n"], "k": blk["k"],
+                   "identity_skip": True, "blocks_per_cu": args.blocks_per_cu or "occupancy"},
+        "time_to_d_ms": blk["time_to_d_ms"], "codewords_per_step": blk["codewords_per_step"],
+        "d": {"min": min(blk["d"]), "max": max(blk["d"])}, "kernel_ms_per_step": blk["kernel_ms_per_step"],
+        "roofline": blk["roofline"],
+    }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(cfg, ds, args.cpu_seconds)
+        line["cpu_baseline"] = cpu_baseline_plain(cfg, blk["d"], args.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 
@@ -353,35 +389,53 @@ def autotune_table():
 
 def bench_serve(args):
     """Serving: Poisson arrivals of random F_3 / F_7 codes (k uniform in
-    [10, 40], F_7 k <= 28, n = 2k) at 0.7 x the measured batched capacity
-    (jobs/s, frozen before the run), through the continuous-batching server,
-    once in arrival order and once shortest-predicted-work first.  Latency is
-    arrival to result as seen by the polling loop."""
+    [10, 40], F_7 k <= 28, n = 2k) at 0.7 x the capacity of the server itself
+    (jobs/s with every request of a calibration set submitted at once,
+    measured before the run and frozen), through the continuous-batching
+    server: arrival order, shortest predicted work first, and the latter with
+    a per-round admission budget of predicted work.  The same arrival trace is
+    then served by the plain path, one call per request in arrival order.
+    Latency is arrival to result as seen by the polling loop."""
     import numpy as np
     import torch
     from paper_2603_29942_amd import bz, predictor, synth
     dev = torch.device("cuda:0")
-    # capacity: the batched path on 256 codes of the same distribution
-    cal = [(p, G) for _, p, G in synth.serving_requests(99, 256, 1.0)]
-    bz.min_distance_batch(cal[:32], device=dev)
-    torch.cuda.synchronize()
-    tc = time.perf_counter()
-    bz.min_distance_batch(cal, device=dev)
-    cap = len(cal) / (time.perf_counter() - tc)
-    lam = 0.7 * cap
-    N = args.requests
-    reqs = synth.serving_requests(0, N, lam)
     params = predictor.load()[0]
-    out = {}
-    ds = {}
-    for policy in ("fifo", "predicted"):
-        srv = bz.Server(policy=policy, mlp_params=params if policy == "predicted" else None, slots=1024, max_n=80)
+
+    def server(policy, budget=0.0):
+        return bz.Server(policy="predicted" if policy != "fifo" else "fifo",
+                         mlp_params=params if policy != "fifo" else None, slots=1024, max_n=80,
+                         admit_budget=budget)
+
+    def warm(srv):
         for t, (_, p, G) in enumerate(synth.serving_requests(98, 16, 1.0)):
             srv.submit(p, G, 10 ** 9 + t)
         got = 0
         while got < 16:
             got += len(srv.poll())
-        lat, cw, dvals = np.zeros(N), 0, [0] * N
+
+    # capacity of the server: a calibration set submitted at once
+    cal = synth.serving_requests(99, 1000, 1.0)
+    srv = server("fifo")
+    warm(srv)
+    tc = time.perf_counter()
+    for t, (_, p, G) in enumerate(cal):
+        srv.submit(p, G, t)
+    got = 0
+    while got < len(cal):
+        got += len(srv.poll())
+    cap = len(cal) / (time.perf_counter() - tc)
+    srv.stop()
+    lam = 0.7 * cap
+    N = args.requests
+    reqs = synth.serving_requests(0, N, lam)
+    offered = (N - 1) / (reqs[-1][0] - reqs[0][0])
+    out, ds = {}, {}
+    budget = 4e10
+    for policy in ("fifo", "predicted", "predicted_budget"):
+        srv = server(policy, budget if policy == "predicted_budget" else 0.0)
+        warm(srv)
+        lat, cw, dvals, done_at = np.zeros(N), 0, [0] * N, np.zeros(N)
         t0 = time.perf_counter()
         i, done = 0, 0
         while done < N:
@@ -390,41 +444,65 @@ def bench_serve(args):
                 srv.submit(reqs[i][1], reqs[i][2], i)
                 i += 1
             for tag, r in srv.poll():
-                lat[tag] = time.perf_counter() - t0 - reqs[tag][0]
+                done_at[tag] = time.perf_counter() - t0
+                lat[tag] = done_at[tag] - reqs[tag][0]
                 cw += r["codewords_total"]
                 dvals[tag] = r["d"]
                 done += 1
-        span = time.perf_counter() - t0
+        span = float(done_at.max() - reqs[0][0])
         st = srv.stats()
         srv.stop()
         ds[policy] = dvals
-        out[policy] = {"latency_ms": {"p50": float(np.percentile(lat, 50) * 1e3),
-                                      "p99": float(np.percentile(lat, 99) * 1e3),
+        out[policy] = {"latency_ms": {"p50": pct(lat.tolist(), 50) * 1e3, "p99": pct(lat.tolist(), 99) * 1e3,
                                       "mean": float(lat.mean() * 1e3)},
-                       "jobs_per_s": N / span, "codewords_per_s": cw / span, "seconds": span, **st}
+                       "served_jobs_per_s": N / span, "served_over_offered": (N / span) / offered,
+                       "codewords_per_s": cw / span, "seconds": span, **st}
+        if policy == "predicted_budget":
+            out[policy]["admit_budget_combinations"] = budget
+    # the plain path on the same arrival trace: one call per request, in order
+    o = bz.bz_default_options()
+    lat, dvals, done_at = np.zeros(N), [0] * N, np.zeros(N)
+    for _, p, G in synth.serving_requests(98, 8, 1.0):
+        bz.bz_min_distance_ex(p, G, o)
+    t0 = time.perf_counter()
+    for i, (ta, p, G) in enumerate(reqs):
+        while time.perf_counter() - t0 < ta:
+            pass
+        st, r = bz.bz_min_distance_ex(p, G, o)
+        done_at[i] = time.perf_counter() - t0
+        lat[i] = done_at[i] - ta
+        dvals[i] = r.d
+    span = float(done_at.max() - reqs[0][0])
+    out["plain_same_requests"] = {"latency_ms": {"p50": pct(lat.tolist(), 50) * 1e3,
+                                                 "p99": pct(lat.tolist(), 99) * 1e3, "mean": float(lat.mean() * 1e3)},
+                                  "served_jobs_per_s": N / span, "served_over_offered": (N / span) / offered,
+                                  "seconds": span, "note": "one bz_min_distance_ex call per request at its arrival"}
+    ds["plain"] = dvals
     return {
         "metric": "time-to-d under Poisson arrivals (continuous batching), p50/p99",
         "value": out["predicted"]["latency_ms"]["p50"], "unit": "ms", "n_gpus": 1, "steps": N, "warmup": 16,
         "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "u32", "data": "synthetic",
-        "config": {"workload": f"{N} requests, Poisson arrivals at {lam:.1f}/s = 0.7 x measured batched capacity "
-                               f"{cap:.1f} jobs/s; p uniform in {{3,7}}, k uniform in [10,40] (F_7 k <= 28), n = 2k",
-                   "slots": 1024, "arrival_rate_per_s": lam, "capacity_jobs_per_s": cap},
+        "config": {"workload": f"{N} requests, Poisson arrivals at {lam:.1f}/s = 0.7 x the server's capacity "
+                               f"{cap:.1f} jobs/s (1000 requests submitted at once); p uniform in {{3,7}}, k uniform "
+                               "in [10,40] (F_7 k <= 28), n = 2k",
+                   "slots": 1024, "arrival_rate_per_s": lam, "offered_jobs_per_s": offered,
+                   "capacity_jobs_per_s": cap},
         "policies": out,
-        "d_equal_between_policies": ds["fifo"] == ds["predicted"],
+        "d_equal_between_policies": ds["fifo"] == ds["predicted"] == ds["predicted_budget"] == ds["plain"],
     }
 
 
 def bench_batch(args):
     """The batched workload: each step is one call on a 512-code mixed batch
-    (half F_3, half F_7, n in [30, 90], rate 1/2 or 1/3, F_7 capped at n <= 56 /
-    63), its generators resident in HBM; compared with the plain path (one
-    call per code) on the same codes."""
+    (batch seed = step index), its generators resident in HBM; then the plain
+    path (one call per code, arguments prepared once) on the same codes."""
+    import ctypes
     import numpy as np
     import torch
-    from paper_2603_29942_amd import bz, synth
+    from paper_2603_29942_amd import autotune, bz, synth
     dev = torch.device("cuda:0")
     K, Wm = args.steps, args.warmup
-    sweep_fn, bpc_tuned = autotune_table()
+    sweep_fn, bpc_tuned, tune_note = autotune.load_checked()
     bpc = args.blocks_per_cu or bpc_tuned
     batches = [synth.batch_codes(s) for s in range(K)]
     warm = [synth.batch_codes(1000 + s, count=64) for s in range(max(Wm, 1))]
@@ -436,65 +514,104 @@ def bench_batch(args):
     for wb in warm[:Wm]:
         bz.min_distance_batch(wb, device=dev, sweep_ops=sweep_fn, blocks_per_cu=bpc)
     torch.cuda.synchronize()
-    times, cws, dec, enum, ops_total = [], [], [], [], 0.0
-    results = []
-    t0 = time.perf_counter()
-    for buf, descs in packed:
+    code_ms = [np.zeros(len(b), dtype=np.float32) for b in batches]
+    opts = []
+    for i in range(K):
         o = bz.bz_default_batch_options()
         o.timing = 1
         o.blocks_per_cu = bpc
+        o.code_ms_out = code_ms[i].ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        opts.append(o)
+    times, results = [], []
+    t0 = time.perf_counter()
+    for i, (buf, descs) in enumerate(packed):
         ts = time.perf_counter()
-        st, res, o = bz.bz_min_distance_batch(buf, descs, o)
+        st, res, _ = bz.bz_min_distance_batch(buf, descs, opts[i])
         times.append(time.perf_counter() - ts)
         if st != bz.OK:
             raise RuntimeError(f"bz_min_distance_batch: {bz.bz_status_str(st)}")
         results.append(res)
-        cws.append(sum(r.codewords_total for _, r in res))
-        dec.append(o.decompose_ms)
-        enum.append(o.enum_ms)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    cws = [sum(r.codewords_total for _, r in res) for res in results]
+    ops_total = 0.0
+    for (buf, descs), res in zip(packed, results):
         for i, (_, r) in enumerate(res):
             d = descs[i]
             ops_total += r.codewords_total * ops_per_codeword(d.p, max((d.n - d.k + 31) // 32, 1))
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    # the plain path on the same codes, one call per code
-    Gdev = [[torch.from_numpy(G).to(dev) for _, G in b] for b in batches]
-    torch.cuda.synchronize()
-    tp = time.perf_counter()
-    plain_d_equal = True
-    plain_lat = []
-    for bi, b in enumerate(batches):
-        for ci, (p, _) in enumerate(b):
-            tc = time.perf_counter()
-            r = bz.min_distance(p, Gdev[bi][ci])
-            plain_lat.append(time.perf_counter() - tc)
-            plain_d_equal &= (r["d"] == results[bi][ci][1].d and r["codewords_total"] == results[bi][ci][1].codewords_total)
-    torch.cuda.synchronize()
-    plain_s = time.perf_counter() - tp
+    dec = [o.decompose_ms for o in opts]
+    enum = [o.enum_ms for o in opts]
+    statuses = [s_i for res in results for s_i, _ in res]
     total_cw = sum(cws)
-    enum_s = sum(enum) / 1e3
-    achieved = ops_total / enum_s / 1e12
-    return {
-        "metric": "codewords evaluated/s (whole job, batched path: 512 codes per call)",
+    achieved = ops_total / (sum(enum) / 1e3) / 1e12
+    batched_code_ms = np.concatenate(code_ms).tolist()
+    gpu_first = [{"d": r.d, "codewords_total": r.codewords_total} for _, r in results[0]]
+    line = {
+        "metric": "codewords evaluated/s + time-to-d, batched vs plain (bit-exact d); p50/p99",
         "value": total_cw / elapsed, "unit": "codewords/s", "n_gpus": 1, "steps": K, "warmup": Wm,
         "ms_per_step": elapsed / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u32", "data": "synthetic",
-        "config": {"workload": "512 random codes per step (batch seeds 0..%d): half F_3, half F_7, n uniform in "
-                               "[30,90], rate 1/2 or 1/3, F_7 n <= 56 (rate 1/2) / 63 (rate 1/3); generators "
-                               "resident on the GPU" % (K - 1),
-                   "identity_skip": True, "blocks_per_cu": bpc or 4,
-                   "sweep_ops": "autotuner table" if bpc_tuned else "default"},
-        "batch_ms": {"p50": pct(times, 50) * 1e3, "max": max(times) * 1e3},
-        "codewords_per_step": {"mean": total_cw / K},
+        "config": {"workload": f"batched path, 512 random codes per step (batch seeds 0..{K - 1}): 256 over F_3 "
+                               "and 256 over F_7 in random order, n uniform in [30,90], rate 1/2 or 1/3 at random "
+                               "(k = n//2 or n//3), entries i.i.d. uniform; F_7 codes redrawn above n = 56 "
+                               "(rate 1/2) / 63 (rate 1/3); generators resident on the GPU",
+                   "codes_per_step": 512, "identity_skip": True, "blocks_per_cu": bpc or 4,
+                   "sweep_ops": tune_note, "rank_deficient_codes": sum(1 for x in statuses if x == bz.ERR_RANK)},
+        "time_to_d_ms": {"batched_per_code": {"p50": pct(batched_code_ms, 50), "p99": pct(batched_code_ms, 99),
+                                              "note": "device time from the start of the batch's decomposition "
+                                                      "launch to the check that ended the code"},
+                         "batched_call": {"p50": pct(times, 50) * 1e3, "p99": pct(times, 99) * 1e3,
+                                          "note": "host time of one 512-code call"}},
+        "codewords_per_step": {"mean": total_cw / K, "min": min(cws), "max": max(cws)},
         "kernel_ms_per_step": {"decompose": sum(dec) / K, "enum": sum(enum) / K},
-        "plain_same_codes": {"value": total_cw / plain_s, "seconds": plain_s,
-                             "time_to_d_ms": {"p50": pct(plain_lat, 50) * 1e3, "p99": pct(plain_lat, 99) * 1e3},
-                             "d_and_counts_equal_batched": bool(plain_d_equal)},
-        "speedup_vs_plain": plain_s / elapsed,
         "roofline": {"kernel": "enum_batch_kernel", "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
                      "unit": "TOPS (int32 VALU lane-ops/s)", "frac": achieved / VALU_PEAK_TOPS,
-                     "traffic": None, "avg_launch_ms": sum(enum) / K},
+                     "traffic": traffic_for("enum_batch_kernel", "mixed_512"),
+                     "ops_per_codeword": "3W+1 (F_3), 4W+1 (F_7), W = words over the n-k non-pivot columns",
+                     "avg_launch_ms": sum(enum) / K},
     }
+    if not args.no_plain:
+        # the plain path on the same codes: one call per code, device pointers
+        # and options prepared once; per-code time to d by the host clock
+        o = bz.bz_default_options()
+        o.blocks_per_cu = 0
+        o.device = dev.index or 0
+        o.hip_stream = bz._stream_of(packed[0][0])
+        fn = bz.lib().bz_min_distance_ex
+        o_ref = ctypes.byref(o)
+        outs = [bz.bz_result() for _ in range(512)]
+        out_refs = [ctypes.byref(r) for r in outs]
+        plain_lat, plain_cw, equal = [], 0, True
+        tp = time.perf_counter()
+        for bi, (buf, descs) in enumerate(packed):
+            base = buf.data_ptr()
+            for ci in range(len(descs)):
+                d = descs[ci]
+                tc = time.perf_counter()
+                st = fn(d.p, d.n, d.k, ctypes.c_void_p(base + d.g_offset), 1, o_ref, out_refs[ci])
+                plain_lat.append(time.perf_counter() - tc)
+                if st not in (bz.OK, bz.ERR_RANK):
+                    raise RuntimeError(f"bz_min_distance_ex: {bz.bz_status_str(st)}")
+            torch.cuda.synchronize()
+            for ci, (s_i, r) in enumerate(results[bi]):
+                q = outs[ci]
+                plain_cw += q.codewords_total
+                equal &= (q.d == r.d and q.codewords_total == r.codewords_total and q.n_stages == r.n_stages)
+        plain_s = time.perf_counter() - tp
+        line["plain_same_codes"] = {
+            "value": plain_cw / plain_s, "unit": "codewords/s", "seconds": plain_s,
+            "time_to_d_ms": {"p50": pct(plain_lat, 50) * 1e3, "p99": pct(plain_lat, 99) * 1e3,
+                             "note": "host time of one call per code"},
+            "d_and_counts_equal_batched": bool(equal)}
+        line["speedup_vs_plain"] = plain_s / elapsed
+    line["sub_blocks"] = {
+        "plain_f3_72_36": bench_plain(2, args.sub_steps, 2),
+        "plain_f7_48_24": bench_plain(3, args.sub_steps, 2),
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline_codes(batches[0], gpu_first, args.cpu_seconds, args.cpu_seconds / 2,
+                                                  max_cw=3e8)
+    return line
 
 
 if __name__ == "__main__":

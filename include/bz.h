@@ -227,7 +227,9 @@ int bz_min_distance_batch(int ncodes, const bz_code *codes, const uint8_t *G, ui
  * loop: a round admits queued requests into free slots (the device memory of
  * one code each: admission by memory), decomposes them, orders all active
  * codes (arrival order, or shortest predicted work first with the predictor
- * network) and runs them together in one persistent launch.  Requests that
+ * network) and runs them together in one persistent launch.  With the
+ * predicted policy, queued requests are admitted shortest predicted work first
+ * and within a per-round work budget (admit_budget).  Requests that
  * arrive while a round runs make it yield at the next part boundary and join
  * the next round with the unfinished codes, which keep their progress.  Codes
  * that end are returned by the next poll, also while their round runs.  Each
@@ -250,6 +252,11 @@ typedef struct {
     int32_t wait_timeout_s;   /* as in bz_batch_options */
     int32_t max_n;            /* largest n accepted, 0 = 128; sizes each slot */
     int32_t cooperative;      /* as in bz_batch_options */
+    double admit_budget;      /* BZ_SERVE_PREDICTED: predicted combinations admitted per round
+                                 (at least one request per round); 0 = no budget (slots only).
+                                 Queued requests are admitted shortest predicted work first;
+                                 their estimate uses p, n, k (the rank deficit is not known
+                                 before the decomposition and is taken as 0) */
 } bz_server_options;
 
 void bz_default_server_options(bz_server_options *o);

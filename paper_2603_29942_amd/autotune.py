@@ -12,17 +12,33 @@ group is timed as its own batch for every candidate; then the grid shape is
 timed on the whole sample with the chosen sizes.  Results never depend on
 these knobs (the tests check it); only time does.
 
-The table is JSON: {"sweep_ops": {"p,W": ops, ...}, "blocks_per_cu": b, ...}.
+The table is JSON: {"sweep_ops": {"p,W": ops, ...}, "blocks_per_cu": b,
+"kernel_source_hash": h, ...}; it is used only while the kernel sources hash
+to h (a table taken on other kernels is ignored, and load_checked says so).
+The persistent batched kernel fits at most 4 workgroups per compute unit
+(its registers), so that is the largest grid candidate.
 """
 import argparse
+import hashlib
 import json
 import os
 import time
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "tuning_gfx950.json")
-SWEEP_CANDIDATES = (1500, 3000, 6000, 12000, 24000, 48000)
-BPC_CANDIDATES = (2, 3, 4)
+SWEEP_CANDIDATES = (1500, 3000, 6000, 12000, 24000, 48000, 96000, 192000)
+BPC_CANDIDATES = (1, 2, 3, 4)
+KERNEL_SOURCES = ("bz_kernels.hpp", "bz_arith.hpp", "bz_state.hpp")
+
+
+def kernel_source_hash():
+    """Hash of the device code's sources (tables and profiles taken on other
+    kernels no longer apply)."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(HERE, "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def words(p, n, k, identity_skip=True):
@@ -38,6 +54,19 @@ def load(path=TABLE):
         t = json.load(f)
     ops = {tuple(int(x) for x in key.split(",")): int(v) for key, v in t["sweep_ops"].items()}
     return (lambda p, W: ops.get((p, W), 0)), int(t.get("blocks_per_cu", 0))
+
+
+def load_checked(path=TABLE):
+    """As load(), but only a table taken on the current kernel sources is used;
+    returns (sweep_ops function, blocks_per_cu, a note saying which)."""
+    if not os.path.exists(path):
+        return (lambda p, W: 0), 0, "defaults (no autotuner table)"
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("kernel_source_hash") != kernel_source_hash():
+        return (lambda p, W: 0), 0, "defaults (the autotuner table was taken on other kernel sources; ignored)"
+    fn, bpc = load(path)
+    return fn, bpc, f"autotuner table (kernel sources {t['kernel_source_hash']})"
 
 
 def _time_batch(bz, codes, dev, reps, **kw):
@@ -90,6 +119,7 @@ def main():
     t0 = time.perf_counter()
     table = tune(synth.batch_codes(args.seed, count=args.count), reps=args.reps)
     table["tuning_seconds"] = round(time.perf_counter() - t0, 1)
+    table["kernel_source_hash"] = kernel_source_hash()
     table["command"] = f"python -m paper_2603_29942_amd.autotune --seed {args.seed} --count {args.count}"
     with open(args.out, "w") as f:
         json.dump(table, f, indent=1)

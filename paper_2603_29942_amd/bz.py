@@ -76,7 +76,7 @@ class bz_server_options(ctypes.Structure):
     _fields_ = [("slots", ctypes.c_int32), ("policy", ctypes.c_int32), ("mlp_params", ctypes.c_void_p),
                 ("check", ctypes.c_int32), ("identity_skip", ctypes.c_int32), ("max_codewords", ctypes.c_uint64),
                 ("blocks_per_cu", ctypes.c_int32), ("device", ctypes.c_int32), ("wait_timeout_s", ctypes.c_int32),
-                ("max_n", ctypes.c_int32), ("cooperative", ctypes.c_int32)]
+                ("max_n", ctypes.c_int32), ("cooperative", ctypes.c_int32), ("admit_budget", ctypes.c_double)]
 
 
 SERVE_FIFO, SERVE_PREDICTED = 0, 1
@@ -111,44 +111,49 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise LibraryMissing(f"{LIB_PATH} is not built; run python -m paper_2603_29942_amd.build")
-        L = ctypes.CDLL(LIB_PATH)
-        u8p, u32p = ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_uint32)
-        vp = ctypes.c_void_p
-        L.bz_default_options.argtypes = [ctypes.POINTER(bz_options)]
-        L.bz_default_options.restype = None
-        L.bz_min_distance.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(bz_result)]
-        L.bz_min_distance_ex.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int,
-                                         ctypes.POINTER(bz_options), ctypes.POINTER(bz_result)]
-        L.bz_release.argtypes = [ctypes.c_int]
-        L.bz_status_str.argtypes = [ctypes.c_int]
-        L.bz_status_str.restype = ctypes.c_char_p
-        L.bz_sliced_pack.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp]
-        L.bz_sliced_unpack.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp]
-        L.bz_sliced_op.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp,
-                                   ctypes.c_int, vp]
-        del u8p, u32p
-        L.bz_default_batch_options.argtypes = [ctypes.POINTER(bz_batch_options)]
-        L.bz_default_batch_options.restype = None
-        L.bz_min_distance_batch.argtypes = [ctypes.c_int, ctypes.POINTER(bz_code), vp, ctypes.c_uint64,
-                                            ctypes.c_int, ctypes.POINTER(bz_batch_options),
-                                            ctypes.POINTER(bz_result), ctypes.POINTER(ctypes.c_int32)]
-        fp = ctypes.c_void_p
-        L.bz_mlp_forward.argtypes = [fp, fp, ctypes.c_int, fp, fp, vp]
-        L.bz_mlp_backward.argtypes = [fp, fp, fp, ctypes.c_int, fp, fp, fp, fp, fp, vp]
-        L.bz_mlp_adam.argtypes = [fp, fp, fp, fp, ctypes.c_int, ctypes.c_float, ctypes.c_float, ctypes.c_float,
-                                  ctypes.c_float, vp]
-        L.bz_default_server_options.argtypes = [ctypes.POINTER(bz_server_options)]
-        L.bz_default_server_options.restype = None
-        L.bz_server_start.argtypes = [ctypes.POINTER(bz_server_options), ctypes.POINTER(ctypes.c_void_p)]
-        L.bz_server_submit.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_uint64]
-        L.bz_server_poll.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(bz_result),
-                                     ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int),
-                                     ctypes.POINTER(ctypes.c_int)]
-        L.bz_server_stop.argtypes = [vp]
-        L.bz_server_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
-        _lib = L
+        _lib = load(LIB_PATH)
         atexit.register(_release_at_exit)
     return _lib
+
+
+def load(path):
+    """Bind the C ABI of the library built at ``path`` (argument and result types)."""
+    L = ctypes.CDLL(path)
+    u8p, u32p = ctypes.POINTER(ctypes.c_uint8), ctypes.POINTER(ctypes.c_uint32)
+    vp = ctypes.c_void_p
+    L.bz_default_options.argtypes = [ctypes.POINTER(bz_options)]
+    L.bz_default_options.restype = None
+    L.bz_min_distance.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(bz_result)]
+    L.bz_min_distance_ex.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int,
+                                     ctypes.POINTER(bz_options), ctypes.POINTER(bz_result)]
+    L.bz_release.argtypes = [ctypes.c_int]
+    L.bz_status_str.argtypes = [ctypes.c_int]
+    L.bz_status_str.restype = ctypes.c_char_p
+    L.bz_sliced_pack.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp]
+    L.bz_sliced_unpack.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp]
+    L.bz_sliced_op.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp,
+                               ctypes.c_int, vp]
+    del u8p, u32p
+    L.bz_default_batch_options.argtypes = [ctypes.POINTER(bz_batch_options)]
+    L.bz_default_batch_options.restype = None
+    L.bz_min_distance_batch.argtypes = [ctypes.c_int, ctypes.POINTER(bz_code), vp, ctypes.c_uint64,
+                                        ctypes.c_int, ctypes.POINTER(bz_batch_options),
+                                        ctypes.POINTER(bz_result), ctypes.POINTER(ctypes.c_int32)]
+    fp = ctypes.c_void_p
+    L.bz_mlp_forward.argtypes = [fp, fp, ctypes.c_int, fp, fp, vp]
+    L.bz_mlp_backward.argtypes = [fp, fp, fp, ctypes.c_int, fp, fp, fp, fp, fp, vp]
+    L.bz_mlp_adam.argtypes = [fp, fp, fp, fp, ctypes.c_int, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                              ctypes.c_float, vp]
+    L.bz_default_server_options.argtypes = [ctypes.POINTER(bz_server_options)]
+    L.bz_default_server_options.restype = None
+    L.bz_server_start.argtypes = [ctypes.POINTER(bz_server_options), ctypes.POINTER(ctypes.c_void_p)]
+    L.bz_server_submit.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_uint64]
+    L.bz_server_poll.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(bz_result),
+                                 ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int),
+                                 ctypes.POINTER(ctypes.c_int)]
+    L.bz_server_stop.argtypes = [vp]
+    L.bz_server_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)]
+    return L
 
 
 def bz_default_options():
@@ -341,7 +346,8 @@ class Server:
     the server and returns [(tag, result dict)] of the codes that finished."""
 
     def __init__(self, policy="fifo", mlp_params=None, slots=1024, max_n=0, check="stage", identity_skip=True,
-                 max_codewords=0, blocks_per_cu=0, wait_timeout_s=0, max_out=1024, cooperative=False):
+                 max_codewords=0, blocks_per_cu=0, wait_timeout_s=0, max_out=1024, cooperative=False,
+                 admit_budget=0.0):
         o = bz_server_options()
         lib().bz_default_server_options(ctypes.byref(o))
         o.slots = int(slots)
@@ -357,6 +363,7 @@ class Server:
         o.wait_timeout_s = int(wait_timeout_s)
         o.max_n = int(max_n)
         o.cooperative = int(bool(cooperative))
+        o.admit_budget = float(admit_budget)
         h = ctypes.c_void_p()
         _check(lib().bz_server_start(ctypes.byref(o), ctypes.byref(h)), "bz_server_start")
         self._h = h

@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <cstring>
 #include <deque>
@@ -840,12 +841,14 @@ struct bz_server {
     CodeResult *res_h = nullptr;    // mapped: a code's result block, written before its done flag
     CodeResult *res_dev = nullptr;
     int32_t *order_h = nullptr, *new_h = nullptr;
-    float *pred_h = nullptr;
+    float *pred_h = nullptr, *qfeat_h = nullptr;
     // bookkeeping
     struct Req {
         int p, n, k;
         u64 tag;
         std::vector<uint8_t> G;
+        float qpred = 0;         // predicted log10 work before the decomposition
+        bool has_qpred = false;
     };
     std::deque<Req> queue;
     struct Slot {
@@ -888,7 +891,7 @@ void server_free(bz_server *s) {
                     (void *)s->order_d, (void *)s->new_d, (void *)s->feat_d, (void *)s->pred_d, (void *)s->mlp_d})
         if (p) (void)hipFree(p);
     for (void *p : {(void *)s->codes_h, (void *)s->g_h, (void *)s->yield_h, (void *)s->done_h, (void *)s->res_h,
-                    (void *)s->order_h, (void *)s->new_h, (void *)s->pred_h})
+                    (void *)s->order_h, (void *)s->new_h, (void *)s->pred_h, (void *)s->qfeat_h})
         if (p) (void)hipHostFree(p);
     if (s->round_done) (void)hipEventDestroy(s->round_done);
     if (s->run) (void)hipStreamDestroy(s->run);
@@ -937,13 +940,56 @@ hipError_t server_launch(bz_server *s, int nactive) {
     return hipLaunchKernel((const void *)enum_batch_kernel<WMAX>, dim3(s->grid), dim3(256), args, 0, s->run);
 }
 
-// Admit queued requests into free slots, decompose them, order the active
-// slots and start the next round.
+// Predicted policy: the network's work estimate for the queued requests that
+// have none yet (inputs p, n, k; the rank deficit of the last information
+// set is only known after the decomposition and is taken as 0), then the
+// queue in ascending estimate (ties in arrival order).
+int server_queue_predictions(bz_server *s) {
+    std::vector<size_t> need;
+    for (size_t i = 0; i < s->queue.size(); i++)
+        if (!s->queue[i].has_qpred) need.push_back(i);
+    for (size_t lo = 0; lo < need.size(); lo += (size_t)s->slots) {
+        const int nq = (int)std::min(need.size() - lo, (size_t)s->slots);
+        for (int j = 0; j < nq; j++) {
+            const bz_server::Req &r = s->queue[need[lo + (size_t)j]];
+            mlp_features(r.p, r.n, r.k, 0, s->qfeat_h + 4 * j);
+        }
+        HIP_OK(hipMemcpyAsync(s->feat_d, s->qfeat_h, sizeof(float) * 4 * (size_t)nq, hipMemcpyHostToDevice, s->run));
+        mlp_forward_kernel<<<(nq + 255) / 256, 256, 0, s->run>>>(s->mlp_d, s->feat_d, nq, s->pred_d, nullptr);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipMemcpyAsync(s->pred_h, s->pred_d, sizeof(float) * (size_t)nq, hipMemcpyDeviceToHost, s->run));
+        HIP_OK(hipStreamSynchronize(s->run));
+        for (int j = 0; j < nq; j++) {
+            bz_server::Req &r = s->queue[need[lo + (size_t)j]];
+            r.qpred = s->pred_h[j];
+            r.has_qpred = true;
+        }
+    }
+    if (!need.empty())
+        std::stable_sort(s->queue.begin(), s->queue.end(),
+                         [](const bz_server::Req &a, const bz_server::Req &b) { return a.qpred < b.qpred; });
+    return BZ_OK;
+}
+
+// Admit queued requests into free slots (and, with a budget, while their
+// predicted work fits it), decompose them, order the active slots and start
+// the next round.
 int server_round(bz_server *s) {
     std::vector<int> fresh;
+    const bool predicted = s->o.policy == BZ_SERVE_PREDICTED;
+    if (predicted && !s->queue.empty()) {
+        const int st = server_queue_predictions(s);
+        if (st != BZ_OK) return st;
+    }
+    double admitted_work = 0.0;
     for (int i = 0; i < s->slots && !s->queue.empty(); i++) {
         bz_server::Slot &sl = s->slot[(size_t)i];
         if (sl.state != 0) continue;
+        if (predicted && s->o.admit_budget > 0) {
+            const double w = std::pow(10.0, (double)s->queue.front().qpred);
+            if (!fresh.empty() && admitted_work + w > s->o.admit_budget) break;
+            admitted_work += w;
+        }
         bz_server::Req r = std::move(s->queue.front());
         s->queue.pop_front();
         sl.state = 1;
@@ -1042,6 +1088,7 @@ int bz_server_start(const bz_server_options *opt, bz_server **out) {
     if (o.policy == BZ_SERVE_PREDICTED && !o.mlp_params) return BZ_ERR_ARG;
     if (o.check != BZ_CHECK_STAGE && o.check != BZ_CHECK_ROUND) return BZ_ERR_ARG;
     if (o.blocks_per_cu < 0 || o.blocks_per_cu > 64 || o.max_n < 0 || o.max_n > BZ_MAX_N) return BZ_ERR_ARG;
+    if (!(o.admit_budget >= 0.0)) return BZ_ERR_ARG;
     DevCtx *c = nullptr;
     int st = get_ctx(o.device, &c);
     if (st != BZ_OK) return st;
@@ -1082,7 +1129,8 @@ int bz_server_start(const bz_server_options *opt, bz_server **out) {
                   hipSuccess &&
               hipHostMalloc(&s->order_h, sizeof(int32_t) * ns, hipHostMallocDefault) == hipSuccess &&
               hipHostMalloc(&s->new_h, sizeof(int32_t) * ns, hipHostMallocDefault) == hipSuccess &&
-              hipHostMalloc(&s->pred_h, sizeof(float) * ns, hipHostMallocDefault) == hipSuccess;
+              hipHostMalloc(&s->pred_h, sizeof(float) * ns, hipHostMallocDefault) == hipSuccess &&
+              hipHostMalloc(&s->qfeat_h, sizeof(float) * 4 * ns, hipHostMallocDefault) == hipSuccess;
     if (!ok) {
         server_free(s);
         return BZ_ERR_NOMEM;

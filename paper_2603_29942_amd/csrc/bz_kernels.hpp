@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include "bz_arith.hpp"
+#include "bz_mlp.hpp"
 #include "bz_state.hpp"
 
 namespace bz {
@@ -1304,10 +1305,7 @@ __global__ void features_kernel(const CodeState *__restrict__ css, const int32_t
     const CodeState &cs = css[slots[i]];
     const int m = cs.res.m;
     const int km = m > 0 ? cs.res.ranks[m - 1] : cs.k;
-    feat[i * 4 + 0] = ((float)cs.p - 5.0f) / 2.0f;
-    feat[i * 4 + 1] = ((float)cs.n - 60.0f) / 30.0f;
-    feat[i * 4 + 2] = ((float)cs.k - 25.0f) / 15.0f;
-    feat[i * 4 + 3] = (float)(cs.k - km) / 8.0f;
+    mlp_features(cs.p, cs.n, cs.k, cs.k - km, feat + i * 4);
 }
 
 // The tiles of one part of a stage: tile_of(r, part, parts, rot) for r = 0, 1, ...

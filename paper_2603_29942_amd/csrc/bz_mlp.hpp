@@ -19,6 +19,15 @@
 namespace bz {
 
 constexpr int MLP_IN = 4, MLP_H = 64;
+
+// The network's inputs for a code: field, length, dimension and the rank
+// deficit k - k_m of its last information set, normalised as in training.
+__host__ __device__ inline void mlp_features(int p, int n, int k, int deficit, float *f) {
+    f[0] = ((float)p - 5.0f) / 2.0f;
+    f[1] = ((float)n - 60.0f) / 30.0f;
+    f[2] = ((float)k - 25.0f) / 15.0f;
+    f[3] = (float)deficit / 8.0f;
+}
 constexpr int MLP_W1 = 0, MLP_B1 = MLP_W1 + MLP_H * MLP_IN, MLP_W2 = MLP_B1 + MLP_H, MLP_B2 = MLP_W2 + MLP_H * MLP_H,
               MLP_W3 = MLP_B2 + MLP_H, MLP_B3 = MLP_W3 + MLP_H, MLP_NPARAM = MLP_B3 + 1;
 

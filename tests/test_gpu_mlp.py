@@ -100,32 +100,34 @@ def test_training_is_reproducible(bz):
     assert np.array_equal(run(), run())
 
 
-def queue_mean_latency(arrivals, service, order_key):
-    """Non-preemptive single server: when it frees, it serves the waiting job
-    with the smallest key (ties by arrival).  Returns the mean time from
-    arrival to completion."""
-    idx = np.argsort(arrivals, kind="stable")
-    t, i, done, waiting = 0.0, 0, [], []
-    import heapq
-    while i < len(idx) or waiting:
-        if not waiting and t < arrivals[idx[i]]:
-            t = arrivals[idx[i]]
-        while i < len(idx) and arrivals[idx[i]] <= t:
-            j = idx[i]
-            heapq.heappush(waiting, (order_key[j], arrivals[j], j))
-            i += 1
-        _, _, j = heapq.heappop(waiting)
-        t += service[j]
-        done.append(t - arrivals[j])
-    return float(np.mean(done))
+def serve_latencies(bz, reqs, policy, params, slots):
+    """Submits every request at once (a burst at t = 0, the same trace for
+    every policy) to a continuous-batching server and returns each request's
+    time to its result, as the polling loop sees it."""
+    import time
+    srv = bz.Server(policy=policy, mlp_params=params, slots=slots, max_n=80, wait_timeout_s=30)
+    lat = {}
+    try:
+        t0 = time.perf_counter()
+        for tag, (p, G) in enumerate(reqs):
+            srv.submit(p, G, tag)
+        while len(lat) < len(reqs):
+            for tag, r in srv.poll():
+                lat[tag] = time.perf_counter() - t0
+                assert r["status"] in (0, bz.ERR_RANK), r["status"]
+            assert time.perf_counter() - t0 < 120, "server stalled"
+    finally:
+        srv.stop()
+    return np.array([lat[i] for i in range(len(reqs))])
 
 
-def test_trained_predictor_gains_over_arrival_order(bz):
-    """Train on 2400 runs of the method, then on 600 held-out codes: the
-    predictions rank the work well, and serving shortest-predicted-first beats
-    arrival order on mean latency at 70% load (service time = the code's
-    combinations at a fixed rate)."""
-    from paper_2603_29942_amd import predictor
+def test_trained_predictor_gains_on_the_server(bz):
+    """Train the network on 2400 runs of the method, check how it ranks 600
+    held-out codes, then serve 400 other codes on the real continuous-batching
+    server (128 slots, all submitted at once) in arrival order and with the
+    trained network ordering the work: shortest predicted work first finishes
+    the requests much sooner on average."""
+    from paper_2603_29942_amd import predictor, synth
     X, Y = predictor.collect(3000, seed=7, log=say)
     split = int(0.8 * len(Y))
     net = predictor.Net(seed=1)
@@ -137,12 +139,10 @@ def test_trained_predictor_gains_over_arrival_order(bz):
     rho = np.corrcoef(np.argsort(np.argsort(pred)), np.argsort(np.argsort(y)))[0, 1]
     say(f"  held-out spearman {rho:.3f}, mae {np.mean(np.abs(pred - y)):.3f} decades")
     assert rho > 0.8
-    work = 10.0 ** y
-    service = work / work.mean()  # mean service time 1
-    rng = np.random.default_rng(11)
-    arrivals = np.cumsum(rng.exponential(1.0 / 0.7, len(work)))  # load 0.7
-    fifo = queue_mean_latency(arrivals, service, arrivals)
-    sjf = queue_mean_latency(arrivals, service, pred)
-    ideal = queue_mean_latency(arrivals, service, y)
-    say(f"  mean latency: arrival order {fifo:.3f}, predicted-shortest-first {sjf:.3f}, true shortest-first {ideal:.3f}")
-    assert sjf < 0.8 * fifo
+    reqs = [(p, G) for _, p, G in synth.serving_requests(8, 400, rate_per_s=1.0)]
+    fifo = serve_latencies(bz, reqs, "fifo", None, 128)
+    spf = serve_latencies(bz, reqs, "predicted", net.theta(), 128)
+    say(f"  served 400 requests: mean latency arrival order {fifo.mean() * 1e3:.1f} ms, "
+        f"shortest predicted first {spf.mean() * 1e3:.1f} ms (p50 {np.median(fifo) * 1e3:.1f} / "
+        f"{np.median(spf) * 1e3:.1f} ms)")
+    assert spf.mean() < 0.7 * fifo.mean()

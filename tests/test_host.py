@@ -97,7 +97,9 @@ def test_struct_layout(bzlib, tmp_path):
                 ' printf("%zu %zu %zu\\n", sizeof(bz_server_options), offsetof(bz_server_options, max_codewords),'
                 ' offsetof(bz_server_options, max_n));'
                 ' printf("%zu %zu %zu\\n", offsetof(bz_result, info), offsetof(bz_options, no_ahead),'
-                ' offsetof(bz_batch_options, code_ms_out)); return 0;}\n')
+                ' offsetof(bz_batch_options, code_ms_out));'
+                ' printf("%zu %zu\\n", offsetof(bz_server_options, admit_budget), sizeof(bz_server_options));'
+                ' return 0;}\n')
     exe = os.path.join(str(tmp_path), "layout")
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
     c_vals = [int(x) for x in subprocess.run([exe], capture_output=True, text=True).stdout.split()]
@@ -108,7 +110,8 @@ def test_struct_layout(bzlib, tmp_path):
                bzlib.bz_batch_options.hip_stream.offset, bzlib.bz_batch_options.enum_ms.offset,
                ctypes.sizeof(bzlib.bz_server_options), bzlib.bz_server_options.max_codewords.offset,
                bzlib.bz_server_options.max_n.offset, bzlib.bz_result.info.offset, bzlib.bz_options.no_ahead.offset,
-               bzlib.bz_batch_options.code_ms_out.offset]
+               bzlib.bz_batch_options.code_ms_out.offset, bzlib.bz_server_options.admit_budget.offset,
+               ctypes.sizeof(bzlib.bz_server_options)]
     assert c_vals == py_vals
 
 
@@ -168,7 +171,8 @@ def test_server_option_errors_need_no_device(bzlib):
     bzlib.lib().bz_default_server_options(ctypes.byref(o))
     assert (o.slots, o.policy, o.check, o.identity_skip) == (1024, 0, 0, 1)
     h = ctypes.c_void_p()
-    for field, value in [("policy", 1), ("slots", -1), ("check", 7), ("max_n", 129), ("blocks_per_cu", -1)]:
+    for field, value in [("policy", 1), ("slots", -1), ("check", 7), ("max_n", 129), ("blocks_per_cu", -1),
+                         ("admit_budget", -1.0)]:
         bad = bzlib.bz_server_options()
         ctypes.pointer(bad)[0] = o
         setattr(bad, field, value)  # policy 1 needs the network's parameters
