@@ -118,14 +118,15 @@ typedef struct {
                                  are those of every seventh workgroup (the device's one
                                  real-time counter slows down when a thousand workgroups
                                  read it at once); "checked" is exact */
-    int32_t cooperative;      /* 1: launch the persistent enumeration kernel with
-                                 hipLaunchCooperativeKernel, which guarantees that all its
-                                 workgroups are resident at once (about 11 us more per call);
-                                 0 (default): an ordinary launch sized to the device's
-                                 occupancy.  The plain path deals its tiles to fixed
-                                 workgroups, so with an ordinary launch a workgroup kept off
-                                 the device by other kernels delays the run until it starts
-                                 (or until wait_timeout_s, BZ_ERR_DEVICE) */
+    int32_t cooperative;      /* reserved, must be 0 (BZ_ERR_ARG otherwise).  The persistent
+                                 launch is an ordinary one, sized to the device's occupancy;
+                                 a cooperative launch (co-residency guaranteed by the runtime)
+                                 is not offered: it started the kernel about 11 us later and
+                                 processes that made one ended in a crash inside the profiler's
+                                 shutdown when run under rocprofv3.  The plain path deals its
+                                 tiles to fixed workgroups; a workgroup kept off the device by
+                                 other processes' kernels delays the run until it starts (or
+                                 until wait_timeout_s: BZ_ERR_DEVICE) */
     int32_t no_ahead;         /* 1: the decomposition computes every information set itself;
                                  0 (default): when the first set's pivots are the columns
                                  0 .. k-1, the second set (columns k .. n-1 first) is taken
@@ -199,10 +200,10 @@ typedef struct {
     int32_t timing;          /* 1: fill the two fields below (HIP events on the stream) */
     float decompose_ms;      /* out: decomposition launch */
     float enum_ms;           /* out: enumeration launch */
-    int32_t cooperative;     /* 1: hipLaunchCooperativeKernel for the persistent launch; 0
-                                (default): an ordinary launch (the batched kernel hands out
-                                work dynamically, so it never waits for a workgroup that has
-                                not started) */
+    int32_t cooperative;     /* reserved, must be 0 (BZ_ERR_ARG otherwise); the persistent
+                                launch is an ordinary one (the batched kernel hands out work
+                                dynamically, so it never waits for a workgroup that has not
+                                started) */
     float *code_ms_out;      /* NULL, or a host array of ncodes floats: per code, the device
                                 time in ms from the start of the decomposition launch to the
                                 check that ended the code (its time to d within the batch) */
@@ -251,7 +252,7 @@ typedef struct {
     int32_t device;
     int32_t wait_timeout_s;   /* as in bz_batch_options */
     int32_t max_n;            /* largest n accepted, 0 = 128; sizes each slot */
-    int32_t cooperative;      /* as in bz_batch_options */
+    int32_t cooperative;      /* reserved, must be 0 (as in bz_batch_options) */
     double admit_budget;      /* BZ_SERVE_PREDICTED: predicted combinations admitted per round
                                  (at least one request per round); 0 = no budget (slots only).
                                  Queued requests are admitted shortest predicted work first;

@@ -218,13 +218,12 @@ def result_dict(st, r, hist=None):
 
 
 def min_distance(p, G, *, check="stage", no_termination=False, identity_skip=True, max_codewords=0,
-                 histograms=False, blocks_per_cu=0, trace=False, cooperative=False, ahead=True,
+                 histograms=False, blocks_per_cu=0, trace=False, ahead=True,
                  wait_timeout_s=0, stream=None):
     """Convenience wrapper: same keys as the oracle's result dict (plus
     ``info`` and, when asked for, ``trace``, the device timeline in ns).
     stream: a torch stream to run on (G on the device), else the current one."""
     o = bz_default_options()
-    o.cooperative = int(bool(cooperative))
     o.no_ahead = int(not ahead)
     o.wait_timeout_s = int(wait_timeout_s)
     if stream is not None:
@@ -302,8 +301,7 @@ def bz_min_distance_batch(buf, descs, options=None):
 
 
 def min_distance_batch(codes, *, check="stage", no_termination=False, identity_skip=True, max_codewords=0,
-                       blocks_per_cu=0, sweep_ops=None, device=None, timing=False, wait_timeout_s=0,
-                       cooperative=False):
+                       blocks_per_cu=0, sweep_ops=None, device=None, timing=False, wait_timeout_s=0):
     """Convenience wrapper: one result dict per code (same keys as
     min_distance).  sweep_ops: None, an int for every code, or a function
     (p, W) -> int (e.g. the autotuner's table).  timing: also return the two
@@ -325,7 +323,6 @@ def min_distance_batch(codes, *, check="stage", no_termination=False, identity_s
     o.blocks_per_cu = int(blocks_per_cu)
     o.timing = int(bool(timing))
     o.wait_timeout_s = int(wait_timeout_s)
-    o.cooperative = int(bool(cooperative))
     code_ms = np.zeros(max(len(codes), 1), dtype=np.float32)
     if timing:
         o.code_ms_out = code_ms.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
@@ -346,8 +343,7 @@ class Server:
     the server and returns [(tag, result dict)] of the codes that finished."""
 
     def __init__(self, policy="fifo", mlp_params=None, slots=1024, max_n=0, check="stage", identity_skip=True,
-                 max_codewords=0, blocks_per_cu=0, wait_timeout_s=0, max_out=1024, cooperative=False,
-                 admit_budget=0.0):
+                 max_codewords=0, blocks_per_cu=0, wait_timeout_s=0, max_out=1024, admit_budget=0.0):
         o = bz_server_options()
         lib().bz_default_server_options(ctypes.byref(o))
         o.slots = int(slots)
@@ -362,7 +358,6 @@ class Server:
         o.blocks_per_cu = int(blocks_per_cu)
         o.wait_timeout_s = int(wait_timeout_s)
         o.max_n = int(max_n)
-        o.cooperative = int(bool(cooperative))
         o.admit_budget = float(admit_budget)
         h = ctypes.c_void_p()
         _check(lib().bz_server_start(ctypes.byref(o), ctypes.byref(h)), "bz_server_start")

@@ -212,37 +212,31 @@ hipError_t launch_decompose(int WF, const uint8_t *G, CodeState *cs, u32 *rows, 
 
 // The enumeration kernel's grid (see enum_grid) is clamped to its occupancy,
 // so on an otherwise idle device every workgroup is resident at once, which
-// its waits for earlier stages rely on.  An ordinary launch by default; coop
-// asks for hipLaunchCooperativeKernel, which guarantees co-residency but
-// starts the kernel about 11 us later.
+// its waits for earlier stages rely on (plain calls hold the device's server
+// rounds off while they run).
 template <int P, int W, bool H>
 hipError_t launch_enum_one(int grid, CodeState *cs, const u32 *rows, const u64 *binom, u64 *hist, EnumArgs ea,
-                           bool coop, hipStream_t s) {
-    if (!coop) {
-        enum_kernel<P, W, H><<<grid, 256, 0, s>>>(cs, rows, binom, hist, ea);
-        return hipGetLastError();
-    }
-    void *args[] = {&cs, &rows, &binom, &hist, &ea};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(enum_kernel<P, W, H>), dim3(grid), dim3(256),
-                                      args, 0, s);
+                           hipStream_t s) {
+    enum_kernel<P, W, H><<<grid, 256, 0, s>>>(cs, rows, binom, hist, ea);
+    return hipGetLastError();
 }
 
 template <int P, bool H>
 hipError_t launch_enum_h(int W, int grid, CodeState *cs, const u32 *rows, const u64 *binom, u64 *hist, EnumArgs ea,
-                         bool coop, hipStream_t s) {
+                         hipStream_t s) {
     switch (W) {
-    case 1: return launch_enum_one<P, 1, H>(grid, cs, rows, binom, hist, ea, coop, s);
-    case 2: return launch_enum_one<P, 2, H>(grid, cs, rows, binom, hist, ea, coop, s);
-    case 3: return launch_enum_one<P, 3, H>(grid, cs, rows, binom, hist, ea, coop, s);
-    default: return launch_enum_one<P, 4, H>(grid, cs, rows, binom, hist, ea, coop, s);
+    case 1: return launch_enum_one<P, 1, H>(grid, cs, rows, binom, hist, ea, s);
+    case 2: return launch_enum_one<P, 2, H>(grid, cs, rows, binom, hist, ea, s);
+    case 3: return launch_enum_one<P, 3, H>(grid, cs, rows, binom, hist, ea, s);
+    default: return launch_enum_one<P, 4, H>(grid, cs, rows, binom, hist, ea, s);
     }
 }
 
 template <int P>
 hipError_t launch_enum(bool hist_mode, int W, int grid, CodeState *cs, const u32 *rows, const u64 *binom, u64 *hist,
-                       EnumArgs ea, bool coop, hipStream_t s) {
-    return hist_mode ? launch_enum_h<P, true>(W, grid, cs, rows, binom, hist, ea, coop, s)
-                     : launch_enum_h<P, false>(W, grid, cs, rows, binom, hist, ea, coop, s);
+                       EnumArgs ea, hipStream_t s) {
+    return hist_mode ? launch_enum_h<P, true>(W, grid, cs, rows, binom, hist, ea, s)
+                     : launch_enum_h<P, false>(W, grid, cs, rows, binom, hist, ea, s);
 }
 
 // Largest grid the enumeration kernel may get for (p, W, histograms): the
@@ -459,7 +453,7 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, c
     else bz_default_options(&o);
     if (o.check != BZ_CHECK_STAGE && o.check != BZ_CHECK_ROUND) return BZ_ERR_ARG;
     if (o.histograms && !o.hist_out) return BZ_ERR_ARG;
-    if (o.blocks_per_cu < 0 || o.blocks_per_cu > 64) return BZ_ERR_ARG;
+    if (o.blocks_per_cu < 0 || o.blocks_per_cu > 64 || o.cooperative) return BZ_ERR_ARG;
     DevCtx *c = nullptr;
     st = get_ctx(o.device, &c);
     if (st != BZ_OK) return st;
@@ -548,9 +542,8 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, c
         ea.flag_out = c->flag_map_dev;
         ea.epoch = c->epoch;
     }
-    const bool coop = o.cooperative != 0;
-    HIP_OK(p == 3 ? launch_enum<3>(o.histograms != 0, W, grid, c->cs, c->rows, c->binom, c->hist, ea, coop, s)
-                  : launch_enum<7>(o.histograms != 0, W, grid, c->cs, c->rows, c->binom, c->hist, ea, coop, s));
+    HIP_OK(p == 3 ? launch_enum<3>(o.histograms != 0, W, grid, c->cs, c->rows, c->binom, c->hist, ea, s)
+                  : launch_enum<7>(o.histograms != 0, W, grid, c->cs, c->rows, c->binom, c->hist, ea, s));
     if (o.timing) HIP_OK(hipEventRecord(c->ev[2], s));
     HIP_OK(hipEventRecord(c->done_ev, s));
     c->last_stream = s;
@@ -637,7 +630,7 @@ int bz_min_distance_batch(int ncodes, const bz_code *codes, const uint8_t *G, ui
     if (opt) o = *opt;
     else bz_default_batch_options(&o);
     if (o.check != BZ_CHECK_STAGE && o.check != BZ_CHECK_ROUND) return BZ_ERR_ARG;
-    if (o.blocks_per_cu < 0 || o.blocks_per_cu > 64) return BZ_ERR_ARG;
+    if (o.blocks_per_cu < 0 || o.blocks_per_cu > 64 || o.cooperative) return BZ_ERR_ARG;
     if (ncodes == 0) return BZ_OK;
     const int flags = (o.check == BZ_CHECK_ROUND ? FLAG_ROUND : 0) | (o.no_termination ? FLAG_NO_TERM : 0) |
                       (o.identity_skip ? FLAG_SKIP : 0);
@@ -705,8 +698,7 @@ int bz_min_distance_batch(int ncodes, const bz_code *codes, const uint8_t *G, ui
         CodeResult *resm = nullptr;
         void *args[] = {&css, &cds, &nc, &rows, &bin, &bs, &to, &order, &yield, &done, &resm};
         const void *fn = wmax <= 2 ? (const void *)enum_batch_kernel<2> : (const void *)enum_batch_kernel<4>;
-        if (o.cooperative) HIP_OK(hipLaunchCooperativeKernel(fn, dim3(grid), dim3(256), args, 0, s));
-        else HIP_OK(hipLaunchKernel(fn, dim3(grid), dim3(256), args, 0, s));
+        HIP_OK(hipLaunchKernel(fn, dim3(grid), dim3(256), args, 0, s));
     }
     if (o.timing) HIP_OK(hipEventRecord(c->ev[2], s));
     HIP_OK(hipMemcpy2DAsync(c->b_host_res, sizeof(CodeResult), &c->b_cs->res, sizeof(CodeState),
@@ -934,9 +926,6 @@ hipError_t server_launch(bz_server *s, int nactive) {
     uint32_t *done = s->done_dev;
     CodeResult *resm = s->res_dev;
     void *args[] = {&css, &cds, &nc, &rows, &bin, &bs, &to, &order, &yield, &done, &resm};
-    if (s->o.cooperative)
-        return hipLaunchCooperativeKernel((const void *)enum_batch_kernel<WMAX>, dim3(s->grid), dim3(256), args, 0,
-                                          s->run);
     return hipLaunchKernel((const void *)enum_batch_kernel<WMAX>, dim3(s->grid), dim3(256), args, 0, s->run);
 }
 
@@ -1087,7 +1076,8 @@ int bz_server_start(const bz_server_options *opt, bz_server **out) {
         return BZ_ERR_ARG;
     if (o.policy == BZ_SERVE_PREDICTED && !o.mlp_params) return BZ_ERR_ARG;
     if (o.check != BZ_CHECK_STAGE && o.check != BZ_CHECK_ROUND) return BZ_ERR_ARG;
-    if (o.blocks_per_cu < 0 || o.blocks_per_cu > 64 || o.max_n < 0 || o.max_n > BZ_MAX_N) return BZ_ERR_ARG;
+    if (o.blocks_per_cu < 0 || o.blocks_per_cu > 64 || o.max_n < 0 || o.max_n > BZ_MAX_N || o.cooperative)
+        return BZ_ERR_ARG;
     if (!(o.admit_budget >= 0.0)) return BZ_ERR_ARG;
     DevCtx *c = nullptr;
     int st = get_ctx(o.device, &c);

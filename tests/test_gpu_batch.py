@@ -73,7 +73,10 @@ def test_batch_mixed_equals_plain_and_oracle(bz, oracle):
 
 
 @pytest.mark.parametrize("opts", [dict(check="round"), dict(identity_skip=False),
-                                  dict(no_termination=True, max_codewords=3_000_000), dict(cooperative=True)])
+                                  dict(no_termination=True, max_codewords=3_000_000),
+                                  pytest.param(dict(cooperative=True), marks=pytest.mark.skip(
+                                      reason="cooperative launches are no longer offered (BZ_ERR_ARG): processes "
+                                             "that made one ended in a crash inside rocprofv3's shutdown"))])
 def test_batch_options_equal_plain(bz, opts):
     import torch
     cs = mixed_codes()[:16] + synth.batch_codes(3, count=16)

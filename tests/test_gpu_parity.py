@@ -467,6 +467,8 @@ def test_device_input_and_determinism(bz, oracle):
             same(bz.min_distance(p, G, blocks_per_cu=bpc), ref)
 
 
+@pytest.mark.skip(reason="cooperative launches are no longer offered (BZ_ERR_ARG): processes that made one ended "
+                         "in a crash inside rocprofv3's shutdown, after the results were written")
 def test_cooperative_launch_same_results(bz, oracle):
     """The persistent kernel launched with co-residency guaranteed
     (hipLaunchCooperativeKernel) and as an ordinary launch: identical runs."""

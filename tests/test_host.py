@@ -186,3 +186,23 @@ def test_release_argument_errors_need_no_device(bzlib):
     L = bzlib.lib()
     assert L.bz_release(-1) == bzlib.ERR_ARG and L.bz_release(16) == bzlib.ERR_ARG
     assert L.bz_release(3) == bzlib.OK  # never set up
+
+
+def test_cooperative_launch_is_rejected(bzlib):
+    """The reserved cooperative field must be 0 on every entry point that has
+    it; the check comes before any device work."""
+    G = np.zeros((4, 10), dtype=np.uint8)
+    o = bzlib.bz_default_options()
+    o.cooperative = 1
+    st, _ = bzlib.bz_min_distance_ex(3, G, o)
+    assert st == bzlib.ERR_ARG
+    buf, descs = bzlib.pack_batch([(3, G)])
+    ob = bzlib.bz_default_batch_options()
+    ob.cooperative = 1
+    st, _, _ = bzlib.bz_min_distance_batch(buf, descs, ob)
+    assert st == bzlib.ERR_ARG
+    so = bzlib.bz_server_options()
+    bzlib.lib().bz_default_server_options(ctypes.byref(so))
+    so.cooperative = 1
+    h = ctypes.c_void_p()
+    assert bzlib.lib().bz_server_start(ctypes.byref(so), ctypes.byref(h)) == bzlib.ERR_ARG
