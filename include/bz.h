@@ -161,6 +161,24 @@ int bz_min_distance(int p, int n, int k, const uint8_t *G, bz_result *out);
 int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device,
                        const bz_options *o, bz_result *out);
 
+/* For callers that cannot allocate (code that runs under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): bz_min_distance_ex on a
+ * device generator G (G_is_device = 1) whose device state lives in one fixed
+ * array of the library (BZ_NOALLOC_SCRATCH_BYTES per device, held until the
+ * process ends; sized for the largest problem the library accepts: n <= BZ_MAX_N,
+ * k <= BZ_MAX_K, m <= BZ_MAX_M).  The call allocates nothing: no device, pinned
+ * or mapped memory, no stream, no event (the first call on a device looks up the
+ * array's address and fills its binomial table).  It runs on options->hip_stream
+ * (NULL: the null stream) and synchronises it before returning.  Supported
+ * options: check, no_termination, identity_skip, max_codewords, hip_stream,
+ * device, blocks_per_cu, wait_timeout_s, no_ahead; histograms, trace_out, timing
+ * or cooperative set, n > BZ_MAX_N, k > BZ_MAX_K or a NULL pointer give
+ * BZ_ERR_ARG.  Every such call on one device shares the one array: calls are
+ * serialised by the device's lock within a process, and calls that overlap on
+ * one device from several processes race.  Results equal bz_min_distance_ex's. */
+#define BZ_NOALLOC_SCRATCH_BYTES (640u * 1024u)
+int bz_min_distance_noalloc(int p, int n, int k, const uint8_t *G_dev, const bz_options *o, bz_result *out);
+
 /* Releases what the library holds for a device (the library stream and
  * events, the device workspace, pinned and mapped host buffers, the per-shape
  * tables, the batch workspace) after waiting for its work; the next call on the

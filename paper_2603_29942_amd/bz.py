@@ -26,9 +26,10 @@ OP_ADD, OP_SUB, OP_DOUBLE, OP_ISO_ADD, OP_ISO_SUB, OP_KAT_ADD = range(6)
 ENC_NATURAL, ENC_KAT = 0, 1
 
 INFO_AHEAD = 1
+NOALLOC_SCRATCH_BYTES = 640 * 1024
 
 EXPORTS = ("bz_default_options", "bz_min_distance", "bz_min_distance_ex", "bz_status_str",
-           "bz_release",
+           "bz_min_distance_noalloc", "bz_release",
            "bz_default_batch_options", "bz_min_distance_batch",
            "bz_mlp_forward", "bz_mlp_backward", "bz_mlp_adam",
            "bz_default_server_options", "bz_server_start", "bz_server_submit", "bz_server_poll", "bz_server_stats", "bz_server_stop",
@@ -126,6 +127,8 @@ def load(path):
     L.bz_min_distance.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(bz_result)]
     L.bz_min_distance_ex.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int,
                                      ctypes.POINTER(bz_options), ctypes.POINTER(bz_result)]
+    L.bz_min_distance_noalloc.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp,
+                                          ctypes.POINTER(bz_options), ctypes.POINTER(bz_result)]
     L.bz_release.argtypes = [ctypes.c_int]
     L.bz_status_str.argtypes = [ctypes.c_int]
     L.bz_status_str.restype = ctypes.c_char_p
@@ -192,6 +195,22 @@ def bz_min_distance_ex(p, G, options=None, out=None):
         _devices_used.add(o.device)
         st = lib().bz_min_distance_ex(p, n, k, G.ctypes.data_as(ctypes.c_void_p), 0, ctypes.byref(o),
                                       ctypes.byref(out))
+    return st, out
+
+
+def bz_min_distance_noalloc(p, G, options=None, out=None):
+    """The entry point that allocates nothing: G must be a contiguous torch
+    uint8 CUDA tensor (device memory); runs on the tensor's current stream.
+    Returns (status, bz_result)."""
+    out = out if out is not None else bz_result()
+    o = options if options is not None else bz_default_options()
+    if not (hasattr(G, "is_cuda") and G.is_cuda and G.is_contiguous()):
+        raise ValueError("G must be a contiguous device tensor")
+    k, n = G.shape
+    if o.hip_stream is None:
+        o.hip_stream = _stream_of(G)
+    o.device = G.device.index or 0
+    st = lib().bz_min_distance_noalloc(p, n, k, ctypes.c_void_p(G.data_ptr()), ctypes.byref(o), ctypes.byref(out))
     return st, out
 
 

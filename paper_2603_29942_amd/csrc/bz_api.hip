@@ -22,6 +22,11 @@
 
 using namespace bz;
 
+// The device state of bz_min_distance_noalloc (see there).  In host code this
+// name only stands for the array: its device address comes from
+// hipGetSymbolAddress, per device.
+static __device__ __align__(256) unsigned char scratch[BZ_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 constexpr int MAX_DEV = 16;
@@ -792,6 +797,150 @@ int bz_sliced_op(int p, int op, int nvec, int nsym, const uint32_t *a, const uin
 }
 
 }  // extern "C"
+
+// =====================================================================
+// The entry point that allocates nothing
+// =====================================================================
+//
+// Its device state (the code state, the packed rows of up to BZ_MAX_M
+// information sets, the set computed ahead and the binomial table) lives in
+// one static device array, `scratch`, of which every GPU holds its own copy.
+// Host code never uses the array's name as an address: the first call on a
+// device looks up that device's copy with hipGetSymbolAddress and keeps the
+// pointer.  The decomposition counts the rounds' tasks itself (no per-shape
+// table, which would be device memory of its own), and the result block is
+// copied back into the call's own stack frame.
+
+namespace {
+
+struct NoAllocScratch {
+    CodeState cs;
+    SpecBuf spec;
+    u64 binom[65 * 65];
+    u32 rows[BZ_MAX_M * BZ_MAX_K * ROW_WORDS];
+};
+static_assert(sizeof(NoAllocScratch) <= BZ_NOALLOC_SCRATCH_BYTES, "the no-allocation workspace fits its array");
+
+struct NoAllocDev {
+    bool ready = false;
+    NoAllocScratch *ws = nullptr;  // this device's copy of `scratch`
+    int cu = 0;
+    u64 ticks_per_s = 0;
+    uint32_t epoch = 0;  // the value of ws->spec.flag in the latest call
+};
+NoAllocDev g_na[MAX_DEV];
+
+// C(a, b), a, b <= 64, by Pascal's rule one row at a time (thread b owns column b).
+__global__ void binom_fill_kernel(u64 *tab) {
+    __shared__ u64 row[65];
+    const int b = threadIdx.x;
+    u64 v = (b == 0) ? 1u : 0u;
+    for (int a = 0; a <= 64; a++) {
+        if (a > 0) v = (b > 0 ? row[b - 1] : 0u) + row[b];
+        tab[a * 65 + b] = v;
+        __syncthreads();
+        row[b] = v;
+        __syncthreads();
+    }
+}
+
+__global__ void spec_reset_kernel(SpecBuf *sp) {
+    sp->flag = 0;
+    sp->ok = 0;
+}
+
+// Once per device, with the device current (the caller holds the device's lock).
+int noalloc_setup(int dev, NoAllocDev &na, hipStream_t s) {
+    hipDeviceProp_t prop;
+    HIP_OK(hipGetDeviceProperties(&prop, dev));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return BZ_ERR_DEVICE;
+    int rate_khz = 0;
+    HIP_OK(hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, dev));
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || ptr == nullptr) return BZ_ERR_DEVICE;
+    NoAllocScratch *ws = static_cast<NoAllocScratch *>(ptr);
+    binom_fill_kernel<<<1, 65, 0, s>>>(ws->binom);
+    HIP_OK(hipGetLastError());
+    spec_reset_kernel<<<1, 1, 0, s>>>(&ws->spec);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(s));
+    na.ws = ws;
+    na.cu = prop.multiProcessorCount;
+    na.ticks_per_s = (u64)(rate_khz > 0 ? rate_khz : 100000) * 1000ull;
+    na.epoch = 0;
+    na.ready = true;
+    return BZ_OK;
+}
+
+}  // namespace
+
+extern "C" int bz_min_distance_noalloc(int p, int n, int k, const uint8_t *G, const bz_options *opt,
+                                       bz_result *out) {
+    int st = check_args(p, n, k, G, out);
+    if (st != BZ_OK) return st;
+    bz_options o;
+    if (opt) o = *opt;
+    else bz_default_options(&o);
+    if (o.check != BZ_CHECK_STAGE && o.check != BZ_CHECK_ROUND) return BZ_ERR_ARG;
+    if (o.histograms || o.trace_out || o.timing || o.cooperative) return BZ_ERR_ARG;
+    if (o.blocks_per_cu < 0 || o.blocks_per_cu > 64 || o.device < 0 || o.device >= MAX_DEV) return BZ_ERR_ARG;
+    DevCtx &c = g_ctx[o.device];
+    std::lock_guard<std::mutex> lk(c.mu);
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || o.device >= ndev) return BZ_ERR_DEVICE;
+    HIP_OK(hipSetDevice(o.device));
+    hipStream_t s = (hipStream_t)o.hip_stream;  // NULL: the null stream
+    NoAllocDev &na = g_na[o.device];
+    if (!na.ready) {
+        st = noalloc_setup(o.device, na, s);
+        if (st != BZ_OK) return st;
+    }
+    PlainGuard guard(&c);
+    if (c.ready && c.have_last && c.last_stream != s) HIP_OK(hipStreamWaitEvent(s, c.done_ev, 0));
+
+    const int flags = (o.check == BZ_CHECK_ROUND ? FLAG_ROUND : 0) | (o.no_termination ? FLAG_NO_TERM : 0) |
+                      (o.identity_skip ? FLAG_SKIP : 0);
+    const u64 max_cw = o.max_codewords ? o.max_codewords : DEFAULT_LIMIT;
+    const int WF = (n + 31) / 32;
+    int W = o.identity_skip ? (n - k + 31) / 32 : WF;
+    if (W < 1) W = 1;
+    const int grid = enum_grid(p, false, W, na.cu, o.blocks_per_cu ? o.blocks_per_cu : 64);
+    if (grid < 1) return BZ_ERR_DEVICE;
+    const u64 timeout = na.ticks_per_s * (u64)(o.wait_timeout_s > 0 ? o.wait_timeout_s : 120);
+    NoAllocScratch *ws = na.ws;
+    RunArgs a;
+    a.n = n;
+    a.k = k;
+    a.flags = flags;
+    a.U0 = n - k + 1;
+    a.max_codewords = max_cw;
+    a.grid = (uint32_t)grid;
+    a.sweep_ops = DEFAULT_SWEEP_OPS;
+    a.timeout_ticks = timeout;
+    a.rounds = nullptr;  // counted by the decomposition
+    if (++na.epoch == 0) na.epoch = 1;
+    a.spec = o.no_ahead ? nullptr : &ws->spec;
+    a.epoch = na.epoch;
+    a.pad = 0;
+    HIP_OK(p == 3 ? launch_decompose<3>(WF, G, &ws->cs, ws->rows, a, s)
+                  : launch_decompose<7>(WF, G, &ws->cs, ws->rows, a, s));
+    EnumArgs ea;
+    ea.k = k;
+    ea.n = n;
+    ea.flags = flags;
+    ea.lookahead = LOOKAHEAD;
+    ea.timeout_ticks = timeout;
+    ea.res_out = nullptr;
+    ea.flag_out = nullptr;
+    ea.epoch = 0;
+    ea.pad = 0;
+    HIP_OK(p == 3 ? launch_enum<3>(false, W, grid, &ws->cs, ws->rows, ws->binom, nullptr, ea, s)
+                  : launch_enum<7>(false, W, grid, &ws->cs, ws->rows, ws->binom, nullptr, ea, s));
+    CodeResult r;
+    HIP_OK(hipMemcpyAsync(&r, &ws->cs.res, sizeof r, hipMemcpyDeviceToHost, s));
+    HIP_OK(hipStreamSynchronize(s));
+    return finish(p, n, k, flags, max_cw, r, out);
+}
 
 // =====================================================================
 // Serving: continuous batching over a yielding persistent launch

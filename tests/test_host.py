@@ -180,10 +180,26 @@ def test_server_option_errors_need_no_device(bzlib):
     assert bzlib.lib().bz_server_submit(None, 3, 10, 4, None, 0) == bzlib.ERR_ARG
 
 
-def test_release_argument_errors_need_no_device(bzlib):
-    """Releasing a device that was never set up does nothing; a device
-    ordinal out of range is an argument error."""
+def test_noalloc_and_release_argument_errors_need_no_device(bzlib):
+    """The entry point that allocates nothing rejects options it does not carry
+    and sizes beyond the library's limits before any device work; releasing a
+    device that was never set up does nothing."""
     L = bzlib.lib()
+    G = ctypes.c_void_p(8)  # never read: every call below fails its argument checks
+    out = bzlib.bz_result()
+    for field in ("histograms", "timing", "cooperative"):
+        o = bzlib.bz_default_options()
+        setattr(o, field, 1)
+        assert L.bz_min_distance_noalloc(3, 10, 4, G, ctypes.byref(o), ctypes.byref(out)) == bzlib.ERR_ARG
+    o = bzlib.bz_default_options()
+    o.trace_out = (ctypes.c_uint64 * 4)()
+    assert L.bz_min_distance_noalloc(3, 10, 4, G, ctypes.byref(o), ctypes.byref(out)) == bzlib.ERR_ARG
+    o = bzlib.bz_default_options()
+    for p, n, k in [(3, 129, 4), (7, 100, 65), (5, 10, 4), (3, 10, 11)]:
+        assert L.bz_min_distance_noalloc(p, n, k, G, ctypes.byref(o), ctypes.byref(out)) == bzlib.ERR_ARG
+    o.device = -1
+    assert L.bz_min_distance_noalloc(3, 10, 4, G, ctypes.byref(o), ctypes.byref(out)) == bzlib.ERR_ARG
+    assert L.bz_min_distance_noalloc(3, 10, 4, None, None, ctypes.byref(out)) == bzlib.ERR_ARG
     assert L.bz_release(-1) == bzlib.ERR_ARG and L.bz_release(16) == bzlib.ERR_ARG
     assert L.bz_release(3) == bzlib.OK  # never set up
 
