@@ -31,16 +31,41 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# int32 VALU peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz (lane-ops per second)
-VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+# MI355X int32 VALU rates from its unit counts and clock: 256 CUs x 4 SIMDs at
+# 2.4 GHz.  32-bit bitwise operations and adds issue at the fp32 FMA rate, 32
+# lanes per SIMD per clock (the chip's 157.3 TFLOP/s fp32 vector figure is 2
+# flops x 128 lanes x 256 CUs x 2.4 GHz): 78.6 T lane-ops/s.  Popcount and min
+# issue at half that rate, 16 lanes per SIMD per clock: 39.3 T lane-ops/s (both
+# rates checked with an issue-rate probe on the chip: 100 and 58 lane-ops per
+# CU per clock against 128 and 64).
+FULL_RATE_TOPS = 256 * 128 * 2.4e9 / 1e12
+HALF_RATE_TOPS = 256 * 64 * 2.4e9 / 1e12
 CONFIG_NAMES = {1: "F_3 [40,10]", 2: "F_3 [72,36]", 3: "F_7 [48,24]"}
 
 
+def op_mix(p, W):
+    """Algorithmic int32 VALU operations per combination for W words per plane,
+    as (bitwise, popcount + min): F_3: 2 boolean ops (isometric add or
+    subtract) + 1 popcount per word, + 1 min; F_7: 3 boolean + 1 popcount per
+    word (xors shared by the add/subtract pair), + 1 min."""
+    return (2 * W, W + 1) if p == 3 else (3 * W, W + 1)
+
+
 def ops_per_codeword(p, W):
-    """Algorithmic int32 VALU operations per combination for W words per plane:
-    F_3: 2 boolean ops (isometric add or subtract) + 1 popcount per word, + 1 min;
-    F_7: 3 boolean + 1 popcount per word (xors shared by the add/subtract pair), + 1 min."""
-    return 3 * W + 1 if p == 3 else 4 * W + 1
+    full, half = op_mix(p, W)
+    return full + half
+
+
+def peak_seconds_per_codeword(p, W):
+    """Time one combination's algorithmic operations take at the chip's peak
+    rates (bitwise at the full rate, popcount and min at half rate)."""
+    full, half = op_mix(p, W)
+    return full / (FULL_RATE_TOPS * 1e12) + half / (HALF_RATE_TOPS * 1e12)
+
+
+def peak_tops(p, W):
+    """Peak algorithmic operations per second for the op mix of (p, W), in T/s."""
+    return ops_per_codeword(p, W) / peak_seconds_per_codeword(p, W) / 1e12
 
 
 def pct(xs, q):
@@ -238,7 +263,7 @@ def micro(nvec=10000, nsym=512, reps=10000, passes=2000):
             "variant": label, "p": p,
             "chain": {"seconds_for_paper_workload": chain_s, "symbol_additions_per_s": adds / chain_s,
                       "bool_ops_per_s": words * reps * ops_word / chain_s,
-                      "frac_of_int32_valu_peak": words * reps * ops_word / chain_s / (VALU_PEAK_TOPS * 1e12),
+                      "frac_of_bitwise_peak": words * reps * ops_word / chain_s / (FULL_RATE_TOPS * 1e12),
                       "correct": ok_chain},
             "streaming": {"us_per_pass": pass_s * 1e6, "seconds_for_paper_workload": pass_s * reps,
                           "hbm_GBps": stream_bytes / pass_s / 1e9, "frac_of_hbm_peak": stream_bytes / pass_s / 8e12,
@@ -301,6 +326,7 @@ def bench_plain(cfg, K, Wm, blocks_per_cu=0):
     opc = ops_per_codeword(p, W)
     total_cw = sum(cws)
     achieved = total_cw * opc / (sum(enum_ms) / 1e3) / 1e12
+    peak = peak_tops(p, W)
     return {
         "workload": f"one random {CONFIG_NAMES[cfg]} code per step (seeds 0..{K - 1}), plain path, "
                     "generator resident on the GPU",
@@ -311,10 +337,12 @@ def bench_plain(cfg, K, Wm, blocks_per_cu=0):
         "codewords_per_step": {"mean": total_cw / K, "min": min(cws), "max": max(cws)},
         "d": [r.d for r in outs],
         "kernel_ms_per_step": {"decompose": sum(dec_ms) / K, "enum": sum(enum_ms) / K},
-        "roofline": {"kernel": "enum_kernel", "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                     "unit": "TOPS (int32 VALU lane-ops/s)", "frac": achieved / VALU_PEAK_TOPS,
+        "roofline": {"kernel": "enum_kernel", "bound": "alu", "achieved": achieved, "peak": peak,
+                     "unit": "T int32 VALU lane-ops/s (algorithmic)", "frac": achieved / peak,
                      "traffic": traffic_for("enum_kernel", f"f{p}_{n}_{k}"),
-                     "ops_per_codeword": opc, "avg_launch_ms": sum(enum_ms) / K},
+                     "ops_per_codeword": opc, "op_mix": {"bitwise": op_mix(p, W)[0], "popcount_min": op_mix(p, W)[1]},
+                     "peak_note": f"bitwise at {FULL_RATE_TOPS:.1f} T/s, popcount and min at {HALF_RATE_TOPS:.1f} T/s",
+                     "avg_launch_ms": sum(enum_ms) / K},
     }
 
 
@@ -334,6 +362,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--micro", action="store_true",
                     help="only run the sliced-arithmetic benchmark (Tables 1-2 sizes) and print its JSON line")
+    ap.add_argument("--valu-rates", action="store_true",
+                    help="only measure the VALU issue rate of the instructions the path uses and print it")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 device-to-device copies of MIB MiB (the known-size copy kernel that "
                          "scales the FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -349,6 +379,21 @@ def main():
     dev = torch.device("cuda:0")
     if args.micro:
         print(json.dumps(micro()), flush=True)
+        return
+    if args.valu_rates:
+        from paper_2603_29942_amd import bz
+        props = torch.cuda.get_device_properties(dev)
+        clk_hz = 2.4e9
+        rates = {}
+        for op, name in enumerate(bz.VALU_PROBE_OPS):
+            bz.valu_rate(op, iters=256)  # warm-up
+            r = max(bz.valu_rate(op) for _ in range(3))
+            rates[name] = {"lane_ops_per_s": r,
+                           "lane_ops_per_cu_per_clock": r / props.multi_processor_count / clk_hz}
+        print(json.dumps({"metric": "VALU issue rate (8 independent chains per thread, 8 waves per SIMD)",
+                          "cus": props.multi_processor_count, "clock_hz": clk_hz, "rates": rates,
+                          "peak_model": {"bitwise_and_add_lanes_per_cu_per_clock": 128,
+                                         "popcount_and_min_lanes_per_cu_per_clock": 64}}), flush=True)
         return
     if args.copy_calibration:
         nbytes = args.copy_calibration << 20
@@ -536,16 +581,20 @@ def bench_batch(args):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     cws = [sum(r.codewords_total for _, r in res) for res in results]
-    ops_total = 0.0
+    ops_total, ideal_s = 0.0, 0.0
     for (buf, descs), res in zip(packed, results):
         for i, (_, r) in enumerate(res):
             d = descs[i]
-            ops_total += r.codewords_total * ops_per_codeword(d.p, max((d.n - d.k + 31) // 32, 1))
+            W = max((d.n - d.k + 31) // 32, 1)
+            ops_total += r.codewords_total * ops_per_codeword(d.p, W)
+            ideal_s += r.codewords_total * peak_seconds_per_codeword(d.p, W)
     dec = [o.decompose_ms for o in opts]
     enum = [o.enum_ms for o in opts]
     statuses = [s_i for res in results for s_i, _ in res]
     total_cw = sum(cws)
-    achieved = ops_total / (sum(enum) / 1e3) / 1e12
+    enum_s = sum(enum) / 1e3
+    achieved = ops_total / enum_s / 1e12
+    frac = ideal_s / enum_s  # the batch's op mix at the peak rates, against the launches' time
     batched_code_ms = np.concatenate(code_ms).tolist()
     gpu_first = [{"d": r.d, "codewords_total": r.codewords_total} for _, r in results[0]]
     line = {
@@ -568,10 +617,13 @@ def bench_batch(args):
                                           "note": "host time of one 512-code call"}},
         "codewords_per_step": {"mean": total_cw / K, "min": min(cws), "max": max(cws)},
         "kernel_ms_per_step": {"decompose": sum(dec) / K, "enum": sum(enum) / K},
-        "roofline": {"kernel": "enum_batch_kernel", "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS,
-                     "unit": "TOPS (int32 VALU lane-ops/s)", "frac": achieved / VALU_PEAK_TOPS,
+        "roofline": {"kernel": "enum_batch_kernel", "bound": "alu", "achieved": achieved, "peak": achieved / frac,
+                     "unit": "T int32 VALU lane-ops/s (algorithmic)", "frac": frac,
                      "traffic": traffic_for("enum_batch_kernel", "mixed_512"),
-                     "ops_per_codeword": "3W+1 (F_3), 4W+1 (F_7), W = words over the n-k non-pivot columns",
+                     "ops_per_codeword": "3W+1 (F_3: 2W bitwise, W+1 popcount and min), 4W+1 (F_7: 3W bitwise, "
+                                         "W+1 popcount and min), W = words over the n-k non-pivot columns",
+                     "peak_note": f"the batch's op mix at bitwise {FULL_RATE_TOPS:.1f} T/s, popcount and min "
+                                  f"{HALF_RATE_TOPS:.1f} T/s",
                      "avg_launch_ms": sum(enum) / K},
     }
     if not args.no_plain:

@@ -248,7 +248,8 @@ int bz_min_distance_batch(int ncodes, const bz_code *codes, const uint8_t *G, ui
  * codes (arrival order, or shortest predicted work first with the predictor
  * network) and runs them together in one persistent launch.  With the
  * predicted policy, queued requests are admitted shortest predicted work first
- * and within a per-round work budget (admit_budget).  Requests that
+ * (when they outnumber the free slots) and within a per-round budget of
+ * predicted work (admit_budget) when one is set.  Requests that
  * arrive while a round runs make it yield at the next part boundary and join
  * the next round with the unfinished codes, which keep their progress.  Codes
  * that end are returned by the next poll, also while their round runs.  Each
@@ -356,6 +357,16 @@ int bz_sliced_unpack(int p, int encoding, int nvec, int nsym, const uint32_t *pl
  * p, op or sizes out of range. */
 int bz_sliced_op(int p, int op, int nvec, int nsym, const uint32_t *a, const uint32_t *b,
                  uint32_t *out, int reps, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* VALU issue-rate probe (not from the paper; it measures the rates behind the
+ * roofline): one launch of blocks_per_cu (1..8) workgroups of 256 threads per
+ * compute unit, each thread running eight independent chains of one VALU
+ * instruction `iters` times.  op: 0 v_xor_b32, 1 v_add_u32, 2 v_bitop3_b32,
+ * 3 v_bcnt_u32_b32, 4 v_min_u32, 5 v_fma_f32.  out: device buffer of
+ * blocks x 256 uint32 (one store per thread); *ms: the launch's time from HIP
+ * events on `stream`; *lane_ops: lane-operations executed.  Synchronous. */
+int bz_valu_rate(int op, int iters, int blocks_per_cu, uint32_t *out, float *ms, double *lane_ops, void *stream);
 
 #ifdef __cplusplus
 }

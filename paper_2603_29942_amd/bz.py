@@ -33,7 +33,7 @@ EXPORTS = ("bz_default_options", "bz_min_distance", "bz_min_distance_ex", "bz_st
            "bz_default_batch_options", "bz_min_distance_batch",
            "bz_mlp_forward", "bz_mlp_backward", "bz_mlp_adam",
            "bz_default_server_options", "bz_server_start", "bz_server_submit", "bz_server_poll", "bz_server_stats", "bz_server_stop",
-           "bz_sliced_pack", "bz_sliced_unpack", "bz_sliced_op")
+           "bz_sliced_pack", "bz_sliced_unpack", "bz_sliced_op", "bz_valu_rate")
 
 
 class bz_stage(ctypes.Structure):
@@ -136,6 +136,8 @@ def load(path):
     L.bz_sliced_unpack.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp]
     L.bz_sliced_op.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, vp,
                                ctypes.c_int, vp]
+    L.bz_valu_rate.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.POINTER(ctypes.c_float),
+                               ctypes.POINTER(ctypes.c_double), vp]
     del u8p, u32p
     L.bz_default_batch_options.argtypes = [ctypes.POINTER(bz_batch_options)]
     L.bz_default_batch_options.restype = None
@@ -481,3 +483,19 @@ def bz_sliced_op(p, op, a, b, nsym, reps=1, out=None):
     if st != OK:
         raise RuntimeError(bz_status_str(st))
     return out
+
+
+# ---------------------------------------------------------------- VALU issue rates
+VALU_PROBE_OPS = ("v_xor_b32", "v_add_u32", "v_bitop3_b32", "v_bcnt_u32_b32", "v_min_u32", "v_fma_f32")
+
+
+def valu_rate(op, iters=4096, blocks_per_cu=8):
+    """Issue rate of one VALU instruction (see bz_valu_rate): lane-ops per second."""
+    import torch
+    dev = torch.device("cuda:0")
+    props = torch.cuda.get_device_properties(dev)
+    out = torch.empty(props.multi_processor_count * blocks_per_cu * 256, dtype=torch.int32, device=dev)
+    ms, ops = ctypes.c_float(), ctypes.c_double()
+    _check(lib().bz_valu_rate(int(op), int(iters), int(blocks_per_cu), _ptr(out), ctypes.byref(ms), ctypes.byref(ops),
+                              _stream_of(out)), "bz_valu_rate")
+    return ops.value / (ms.value * 1e-3)

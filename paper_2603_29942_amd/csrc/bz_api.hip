@@ -53,6 +53,7 @@ struct DevCtx {
     // batch workspace, grown on demand and kept
     size_t b_codes_cap = 0, b_rows_cap = 0, b_g_cap = 0;
     CodeState *b_cs = nullptr;
+    u64 *b_claims = nullptr;  // the codes' claim words, contiguous
     BatchCode *b_codes = nullptr;
     u32 *b_rows = nullptr;
     uint8_t *b_g = nullptr;
@@ -151,7 +152,8 @@ void release_ctx(DevCtx &c) {
     for (auto &kv : c.rounds) (void)hipFree(kv.second);
     c.rounds.clear();
     for (void *p : {(void *)c.g_buf, (void *)c.cs, (void *)c.rows, (void *)c.binom, (void *)c.hist, (void *)c.spec,
-                    (void *)c.b_cs, (void *)c.b_codes, (void *)c.b_rows, (void *)c.b_g, (void *)c.b_state})
+                    (void *)c.b_cs, (void *)c.b_claims, (void *)c.b_codes, (void *)c.b_rows, (void *)c.b_g,
+                    (void *)c.b_state})
         if (p) (void)hipFree(p);
     for (void *p : {(void *)c.host_res, (void *)c.host_hist, (void *)c.host_trace, (void *)c.res_map,
                     (void *)c.flag_map, (void *)c.b_host_res, (void *)c.b_host_state})
@@ -167,6 +169,7 @@ void release_ctx(DevCtx &c) {
     c.hist = nullptr;
     c.spec = nullptr;
     c.b_cs = nullptr;
+    c.b_claims = nullptr;
     c.b_codes = nullptr;
     c.b_rows = nullptr;
     c.b_g = nullptr;
@@ -385,13 +388,16 @@ int grow_batch(DevCtx &c, size_t ncodes, size_t row_words, size_t g_bytes) {
         // (errors of the frees are not actionable here; every pointer is reset so
         // that a failed allocation below leaves nothing to free twice)
         if (c.b_cs) (void)hipFree(c.b_cs);
+        if (c.b_claims) (void)hipFree(c.b_claims);
         if (c.b_codes) (void)hipFree(c.b_codes);
         if (c.b_host_res) (void)hipHostFree(c.b_host_res);
         c.b_cs = nullptr;
+        c.b_claims = nullptr;
         c.b_codes = nullptr;
         c.b_host_res = nullptr;
         c.b_codes_cap = 0;
         if (hipMalloc(&c.b_cs, sizeof(CodeState) * ncodes) != hipSuccess) return BZ_ERR_NOMEM;
+        if (hipMalloc(&c.b_claims, sizeof(u64) * ncodes) != hipSuccess) return BZ_ERR_NOMEM;
         if (hipMalloc(&c.b_codes, sizeof(BatchCode) * ncodes) != hipSuccess) return BZ_ERR_NOMEM;
         if (hipHostMalloc(&c.b_host_res, sizeof(CodeResult) * ncodes, hipHostMallocDefault) != hipSuccess)
             return BZ_ERR_NOMEM;
@@ -685,12 +691,13 @@ int bz_min_distance_batch(int ncodes, const bz_code *codes, const uint8_t *G, ui
     zero_batch_state<<<1, 1, 0, s>>>(c->b_state);
     HIP_OK(hipGetLastError());
     if (o.timing) HIP_OK(hipEventRecord(c->ev[0], s));
-    decompose_batch_kernel<<<ncodes, 64, 0, s>>>(Gd, c->b_codes, c->b_cs, c->b_rows, (uint32_t)grid, c->b_state,
-                                                nullptr, nullptr, nullptr);
+    decompose_batch_kernel<<<ncodes, 64, 0, s>>>(Gd, c->b_codes, c->b_cs, c->b_claims, c->b_rows, (uint32_t)grid,
+                                                c->b_state, nullptr, nullptr, nullptr);
     HIP_OK(hipGetLastError());
     if (o.timing) HIP_OK(hipEventRecord(c->ev[1], s));
     {
         CodeState *css = c->b_cs;
+        u64 *clm = c->b_claims;
         const BatchCode *cds = c->b_codes;
         int nc = ncodes;
         const u32 *rows = c->b_rows;
@@ -701,7 +708,7 @@ int bz_min_distance_batch(int ncodes, const bz_code *codes, const uint8_t *G, ui
         const uint32_t *yield = nullptr;
         uint32_t *done = nullptr;
         CodeResult *resm = nullptr;
-        void *args[] = {&css, &cds, &nc, &rows, &bin, &bs, &to, &order, &yield, &done, &resm};
+        void *args[] = {&css, &clm, &cds, &nc, &rows, &bin, &bs, &to, &order, &yield, &done, &resm};
         const void *fn = wmax <= 2 ? (const void *)enum_batch_kernel<2> : (const void *)enum_batch_kernel<4>;
         HIP_OK(hipLaunchKernel(fn, dim3(grid), dim3(256), args, 0, s));
     }
@@ -756,6 +763,40 @@ int bz_mlp_adam(float *params, const float *grad, float *m, float *v, int step, 
     mlp_adam_kernel<<<(MLP_NPARAM + 255) / 256, 256, 0, (hipStream_t)stream>>>(params, grad, m, v, step, lr, beta1,
                                                                               beta2, eps);
     return hipGetLastError() == hipSuccess ? BZ_OK : BZ_ERR_DEVICE;
+}
+
+int bz_valu_rate(int op, int iters, int blocks_per_cu, uint32_t *out, float *ms, double *lane_ops, void *stream) {
+    if (op < 0 || op > 5 || iters < 1 || blocks_per_cu < 1 || blocks_per_cu > 8 || !out || !ms || !lane_ops)
+        return BZ_ERR_ARG;
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    hipDeviceProp_t prop;
+    HIP_OK(hipGetDeviceProperties(&prop, dev));
+    const int blocks = prop.multiProcessorCount * blocks_per_cu;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_OK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return BZ_ERR_DEVICE;
+    }
+    hipError_t err = hipEventRecord(e0, s);
+    switch (op) {
+    case 0: valu_rate_kernel<0><<<blocks, 256, 0, s>>>(out, iters, 1u); break;
+    case 1: valu_rate_kernel<1><<<blocks, 256, 0, s>>>(out, iters, 1u); break;
+    case 2: valu_rate_kernel<2><<<blocks, 256, 0, s>>>(out, iters, 1u); break;
+    case 3: valu_rate_kernel<3><<<blocks, 256, 0, s>>>(out, iters, 1u); break;
+    case 4: valu_rate_kernel<4><<<blocks, 256, 0, s>>>(out, iters, 1u); break;
+    default: valu_rate_kernel<5><<<blocks, 256, 0, s>>>(out, iters, 1u); break;
+    }
+    if (err == hipSuccess) err = hipGetLastError();
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    if (err == hipSuccess) err = hipEventElapsedTime(ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *lane_ops = (double)blocks * 256.0 * (double)iters * 8.0;
+    return err == hipSuccess ? BZ_OK : BZ_ERR_DEVICE;
 }
 
 int bz_sliced_pack(int p, int enc, int nvec, int nsym, const uint8_t *sym, uint32_t *planes, void *stream) {
@@ -968,6 +1009,7 @@ struct bz_server {
     u64 max_cw = 0, timeout = 0, rows_per_slot = 0, g_per_slot = 0;
     // device
     CodeState *cs = nullptr;
+    u64 *claims = nullptr;  // one claim word per slot, contiguous
     BatchCode *codes = nullptr;
     u32 *rows = nullptr;
     uint8_t *g = nullptr;
@@ -996,7 +1038,7 @@ struct bz_server {
         int state = 0;  // 0 free, 1 active
         int p = 0, n = 0, k = 0;
         u64 tag = 0;
-        float prio = 0;
+        float prio = 0;       // predicted log10 work after the decomposition
         u64 seq = 0;
     };
     std::vector<Slot> slot;
@@ -1028,7 +1070,7 @@ void servers_release(DevCtx &c) {
 void server_free(bz_server *s) {
     // teardown: errors are not actionable here
     if (s->run) (void)hipStreamSynchronize(s->run);
-    for (void *p : {(void *)s->cs, (void *)s->codes, (void *)s->rows, (void *)s->g, (void *)s->bs,
+    for (void *p : {(void *)s->cs, (void *)s->claims, (void *)s->codes, (void *)s->rows, (void *)s->g, (void *)s->bs,
                     (void *)s->order_d, (void *)s->new_d, (void *)s->feat_d, (void *)s->pred_d, (void *)s->mlp_d})
         if (p) (void)hipFree(p);
     for (void *p : {(void *)s->codes_h, (void *)s->g_h, (void *)s->yield_h, (void *)s->done_h, (void *)s->res_h,
@@ -1064,6 +1106,7 @@ int server_harvest(bz_server *s, int max_out, uint64_t *tags, bz_result *results
 template <int WMAX>
 hipError_t server_launch(bz_server *s, int nactive) {
     CodeState *css = s->cs;
+    u64 *clm = s->claims;
     const BatchCode *cds = s->codes;
     int nc = nactive;
     const u32 *rows = s->rows;
@@ -1074,7 +1117,7 @@ hipError_t server_launch(bz_server *s, int nactive) {
     const uint32_t *yield = s->yield_dev;
     uint32_t *done = s->done_dev;
     CodeResult *resm = s->res_dev;
-    void *args[] = {&css, &cds, &nc, &rows, &bin, &bs, &to, &order, &yield, &done, &resm};
+    void *args[] = {&css, &clm, &cds, &nc, &rows, &bin, &bs, &to, &order, &yield, &done, &resm};
     return hipLaunchKernel((const void *)enum_batch_kernel<WMAX>, dim3(s->grid), dim3(256), args, 0, s->run);
 }
 
@@ -1116,8 +1159,14 @@ int server_round(bz_server *s) {
     std::vector<int> fresh;
     const bool predicted = s->o.policy == BZ_SERVE_PREDICTED;
     if (predicted && !s->queue.empty()) {
-        const int st = server_queue_predictions(s);
-        if (st != BZ_OK) return st;
+        // an order is only needed when the queue does not fit the free slots or
+        // a work budget applies (otherwise every queued request is admitted)
+        int free_slots = 0;
+        for (const auto &sl : s->slot) free_slots += sl.state == 0;
+        if (s->o.admit_budget > 0 || (int)s->queue.size() > free_slots) {
+            const int st = server_queue_predictions(s);
+            if (st != BZ_OK) return st;
+        }
     }
     double admitted_work = 0.0;
     for (int i = 0; i < s->slots && !s->queue.empty(); i++) {
@@ -1161,8 +1210,9 @@ int server_round(bz_server *s) {
         HIP_OK(hipMemcpyAsync(s->codes, s->codes_h, sizeof(BatchCode) * (size_t)s->slots, hipMemcpyHostToDevice,
                               s->run));
         HIP_OK(hipMemcpyAsync(s->new_d, s->new_h, sizeof(int32_t) * (size_t)nf, hipMemcpyHostToDevice, s->run));
-        decompose_batch_kernel<<<nf, 64, 0, s->run>>>(s->g, s->codes, s->cs, s->rows, (uint32_t)s->decomp_grid, s->bs,
-                                                      s->new_d, s->done_dev, s->res_dev);
+        decompose_batch_kernel<<<nf, 64, 0, s->run>>>(s->g, s->codes, s->cs, s->claims, s->rows,
+                                                      (uint32_t)s->decomp_grid, s->bs, s->new_d, s->done_dev,
+                                                      s->res_dev);
         HIP_OK(hipGetLastError());
         if (s->o.policy == BZ_SERVE_PREDICTED) {
             features_kernel<<<(nf + 63) / 64, 64, 0, s->run>>>(s->cs, s->new_d, nf, s->feat_d);
@@ -1251,6 +1301,7 @@ int bz_server_start(const bz_server_options *opt, bz_server **out) {
     bool ok = s->grid > 0 && hipStreamCreateWithFlags(&s->run, hipStreamNonBlocking) == hipSuccess &&
               hipEventCreateWithFlags(&s->round_done, hipEventDisableTiming) == hipSuccess &&
               hipMalloc(&s->cs, sizeof(CodeState) * ns) == hipSuccess &&
+              hipMalloc(&s->claims, sizeof(u64) * ns) == hipSuccess &&
               hipMalloc(&s->codes, sizeof(BatchCode) * ns) == hipSuccess &&
               hipMalloc(&s->rows, sizeof(u32) * s->rows_per_slot * ns) == hipSuccess &&
               hipMalloc(&s->g, s->g_per_slot * ns) == hipSuccess && hipMalloc(&s->bs, sizeof(BatchState)) == hipSuccess &&

@@ -1240,9 +1240,9 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
 // BatchState::remaining.
 __global__ __launch_bounds__(64) void decompose_batch_kernel(const uint8_t *__restrict__ G,
                                                              const BatchCode *__restrict__ codes, CodeState *css,
-                                                             u32 *__restrict__ rows, uint32_t grid, BatchState *bs,
-                                                             const int32_t *__restrict__ slots, uint32_t *done_flags,
-                                                             CodeResult *res_map) {
+                                                             u64 *claims, u32 *__restrict__ rows, uint32_t grid,
+                                                             BatchState *bs, const int32_t *__restrict__ slots,
+                                                             uint32_t *done_flags, CodeResult *res_map) {
     __shared__ DecompLDS lds;
     if (threadIdx.x == 0) atomicMin((unsigned long long *)&bs->t0, (unsigned long long)wall_clock64());
     const int c = slots ? slots[blockIdx.x] : (int)blockIdx.x;  // a list of slots, or every code
@@ -1282,7 +1282,7 @@ __global__ __launch_bounds__(64) void decompose_batch_kernel(const uint8_t *__re
     if (threadIdx.x == 0) {
         // lane 0 wrote the status, the table size and stage 0 itself
         work = cs->res.status == BZ_OK && cs->res.n_table > 0;
-        cs->claim = work ? claim_make(0, cs->stages[0].parts) : 0ull;
+        claims[c] = work ? claim_make(0, cs->stages[0].parts) : 0ull;
         if (work) atomicAdd(&bs->remaining, 1u);
         else cs->res.t_end = (u64)wall_clock64();  // nothing to enumerate: ends here
     }
@@ -1334,8 +1334,8 @@ __device__ void run_part(const StageDesc &sd, int s, uint32_t part, int k, const
 // L >= U test (Alg. 6) ends the code or publishes the next stage's claim word.
 // Run by one whole wavefront; lane 0 applies the check.  done_flag (serving)
 // is raised when the code ends, after its result block went to res_out.
-__device__ void batch_check(CodeState *cs, int s, const StageDesc &sd, BatchState *bs, uint32_t *done_flag,
-                            CodeResult *res_out) {
+__device__ void batch_check(CodeState *cs, u64 *claim, int s, const StageDesc &sd, BatchState *bs,
+                            uint32_t *done_flag, CodeResult *res_out) {
     int last = 0;
     if (__lane_id() == 0) {
         const u64 st = rd_atomic(&cs->res.ctl);
@@ -1347,7 +1347,7 @@ __device__ void batch_check(CodeState *cs, int s, const StageDesc &sd, BatchStat
         __hip_atomic_exchange(&cs->res.ctl, stop ? ctl_make(s, s, U) : ctl_make(s + 1, -1, U), __ATOMIC_RELAXED,
                               __HIP_MEMORY_SCOPE_AGENT);
         drain_vmem();  // U is in place before the next stage can be claimed and checked
-        __hip_atomic_exchange(&cs->claim, last ? 0ull : claim_make(s + 1, cs->stages[s + 1].parts),
+        __hip_atomic_exchange(claim, last ? 0ull : claim_make(s + 1, cs->stages[s + 1].parts),
                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (last) __hip_atomic_fetch_sub(&bs->remaining, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
@@ -1366,7 +1366,8 @@ __device__ void batch_check(CodeState *cs, int s, const StageDesc &sd, BatchStat
 // progress in its claim word for the next launch) and done_flags (mapped host
 // flags raised as codes end).
 template <int WMAX>
-__global__ __launch_bounds__(256) void enum_batch_kernel(CodeState *css, const BatchCode *__restrict__ codes,
+__global__ __launch_bounds__(256) void enum_batch_kernel(CodeState *css, u64 *claims,
+                                                         const BatchCode *__restrict__ codes,
                                                          int ncodes, const u32 *__restrict__ rows,
                                                          const u64 *__restrict__ gbin, BatchState *bs,
                                                          u64 timeout_ticks, const int32_t *__restrict__ order,
@@ -1405,7 +1406,7 @@ __global__ __launch_bounds__(256) void enum_batch_kernel(CodeState *css, const B
                                         : (int)((scan + (uint32_t)(base + lane)) % (uint32_t)ncodes);
                     bool open = false;
                     if (in) {
-                        const u64 cw = ld_poll(&css[c].claim);
+                        const u64 cw = ld_poll(&claims[c]);
                         open = claim_stage(cw) >= 0 && claim_next(cw) < claim_parts(cw);
                     }
                     u64 cands = __ballot(open);
@@ -1415,7 +1416,7 @@ __global__ __launch_bounds__(256) void enum_batch_kernel(CodeState *css, const B
                         const int cc = __shfl(c, l);
                         u64 old = 0;
                         if (lane == 0)
-                            old = __hip_atomic_fetch_add(&css[cc].claim, 1ull, __ATOMIC_RELAXED,
+                            old = __hip_atomic_fetch_add(&claims[cc], 1ull, __ATOMIC_RELAXED,
                                                          __HIP_MEMORY_SCOPE_AGENT);
                         old = uni64(old);
                         if (claim_stage(old) >= 0 && claim_next(old) < claim_parts(old)) {
@@ -1502,10 +1503,43 @@ __global__ __launch_bounds__(256) void enum_batch_kernel(CodeState *css, const B
                 done = __hip_atomic_fetch_add(&cs->stage_done[s], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
             }
             if (uni(done) == sd.parts)
-                batch_check(cs, s, sd, bs, done_flags ? done_flags + code : nullptr, res_map ? res_map + code : nullptr);
+                batch_check(cs, claims + code, s, sd, bs, done_flags ? done_flags + code : nullptr,
+                            res_map ? res_map + code : nullptr);
         }
         __syncthreads();  // qtab, red_* and s_* are rewritten by the next claim
     }
+}
+
+// =====================================================================
+// VALU issue-rate probe (the roofline's peak rates)
+// =====================================================================
+// Eight independent chains of one VALU instruction per thread, `iters` times
+// eight instructions per thread, and one store per thread: the rate at which
+// the chip issues that instruction.  OP: 0 v_xor_b32, 1 v_add_u32,
+// 2 v_bitop3_b32, 3 v_bcnt_u32_b32, 4 v_min_u32, 5 v_fma_f32.
+template <int OP>
+__global__ __launch_bounds__(256) void valu_rate_kernel(u32 *out, int iters, u32 seed) {
+    const u32 t = blockIdx.x * blockDim.x + threadIdx.x;
+    u32 a[8];
+#pragma unroll
+    for (int i = 0; i < 8; i++) a[i] = t + (u32)i + seed;
+    const u32 b = seed * 3u + 1u, c = seed ^ 0x5555u;
+    for (int it = 0; it < iters; it++) {
+#pragma unroll
+        for (int i = 0; i < 8; i++) {
+            if constexpr (OP == 0) asm volatile("v_xor_b32 %0, %0, %1" : "+v"(a[i]) : "v"(b));
+            else if constexpr (OP == 1) asm volatile("v_add_u32 %0, %0, %1" : "+v"(a[i]) : "v"(b));
+            else if constexpr (OP == 2)
+                asm volatile("v_bitop3_b32 %0, %0, %1, %2 bitop3:0x96" : "+v"(a[i]) : "v"(b), "v"(c));
+            else if constexpr (OP == 3) asm volatile("v_bcnt_u32_b32 %0, %1, %0" : "+v"(a[i]) : "v"(b));
+            else if constexpr (OP == 4) asm volatile("v_min_u32 %0, %0, %1" : "+v"(a[i]) : "v"(b));
+            else asm volatile("v_fma_f32 %0, %0, %1, %2" : "+v"(a[i]) : "v"(b), "v"(c));
+        }
+    }
+    u32 x = 0;
+#pragma unroll
+    for (int i = 0; i < 8; i++) x ^= a[i];
+    out[t] = x;
 }
 
 // =====================================================================

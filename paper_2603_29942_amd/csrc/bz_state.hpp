@@ -110,8 +110,6 @@ struct CodeState {
     // last start
     u64 trace[BZ_MAX_STAGES + 2][4];
     StageDesc stages[BZ_MAX_STAGES];
-    // batched runs: the stage whose parts workgroups claim (see claim_make)
-    u64 claim;
     // copies of the checker's progress for the workgroups that wait on it,
     // one per 128-byte line (workgroup b reads copy b mod WAKE_COPIES), so
     // that a thousand pollers do not queue on one address; see wake_make
@@ -121,6 +119,8 @@ struct CodeState {
 // Claim word of a code in a batch: stage + 1 (bits 48-63, 0 = nothing to
 // claim), parts of that stage (bits 24-47) and the next part to hand out
 // (bits 0-23, advanced by atomic add; values >= parts are failed claims).
+// The claim words of a batch are one contiguous array (code i at [i]), so
+// that a wavefront scanning 64 codes reads 512 consecutive bytes.
 BZ_HD u64 claim_make(int stage, uint32_t parts) { return ((u64)(uint32_t)(stage + 1) << 48) | ((u64)parts << 24); }
 BZ_HD int claim_stage(u64 c) { return (int)(c >> 48) - 1; }
 BZ_HD uint32_t claim_parts(u64 c) { return (uint32_t)(c >> 24) & 0xffffffu; }

@@ -202,6 +202,9 @@ def test_noalloc_and_release_argument_errors_need_no_device(bzlib):
     assert L.bz_min_distance_noalloc(3, 10, 4, None, None, ctypes.byref(out)) == bzlib.ERR_ARG
     assert L.bz_release(-1) == bzlib.ERR_ARG and L.bz_release(16) == bzlib.ERR_ARG
     assert L.bz_release(3) == bzlib.OK  # never set up
+    ms, ops = ctypes.c_float(), ctypes.c_double()
+    for op, iters, bpc in [(6, 1, 1), (-1, 1, 1), (0, 0, 1), (0, 1, 9)]:
+        assert L.bz_valu_rate(op, iters, bpc, ctypes.c_void_p(8), ctypes.byref(ms), ctypes.byref(ops), None) == bzlib.ERR_ARG
 
 
 def test_cooperative_launch_is_rejected(bzlib):
