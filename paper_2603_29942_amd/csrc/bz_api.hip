@@ -505,7 +505,7 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, c
     a.U0 = n - k + 1;
     a.max_codewords = max_cw;
     a.grid = (uint32_t)grid;
-    a.sweep_ops = DEFAULT_SWEEP_OPS;
+    a.sweep_ops = plain_sweep_ops(p);
     a.timeout_ticks = timeout;
     {
         // (p, k, W, grid, task size) packed: 3 + 7 + 3 + 19 + 32 bits
@@ -592,7 +592,7 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, c
             HIP_OK(hipMemcpyAsync(c->host_trace, c->cs->trace, sizeof(c->cs->trace), hipMemcpyDeviceToHost, s));
         HIP_OK(hipStreamSynchronize(s));
     }
-    st = finish(p, n, k, flags, max_cw, *c->host_res, out);
+    st = finish(p, n, k, flags, max_cw, *c->host_res, out, plain_sweep_ops(p));
     if (o.timing) {
         HIP_OK(hipEventElapsedTime(&out->decompose_ms, c->ev[0], c->ev[1]));
         HIP_OK(hipEventElapsedTime(&out->enum_ms, c->ev[1], c->ev[2]));
@@ -956,7 +956,7 @@ extern "C" int bz_min_distance_noalloc(int p, int n, int k, const uint8_t *G, co
     a.U0 = n - k + 1;
     a.max_codewords = max_cw;
     a.grid = (uint32_t)grid;
-    a.sweep_ops = DEFAULT_SWEEP_OPS;
+    a.sweep_ops = plain_sweep_ops(p);
     a.timeout_ticks = timeout;
     a.rounds = nullptr;  // counted by the decomposition
     if (++na.epoch == 0) na.epoch = 1;
@@ -980,7 +980,7 @@ extern "C" int bz_min_distance_noalloc(int p, int n, int k, const uint8_t *G, co
     CodeResult r;
     HIP_OK(hipMemcpyAsync(&r, &ws->cs.res, sizeof r, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
-    return finish(p, n, k, flags, max_cw, r, out);
+    return finish(p, n, k, flags, max_cw, r, out, plain_sweep_ops(p));
 }
 
 // =====================================================================

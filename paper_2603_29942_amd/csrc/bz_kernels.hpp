@@ -645,6 +645,7 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
         res.table_complete = complete;
     }
     if (lane < WAKE_COPIES) cs->wake[lane][0] = wake_make(0, -1);
+    if (lane < (int)POOL_SLICES) cs->pool_next[lane][0] = 0;
 }
 
 template <int P, int WF>
@@ -1061,8 +1062,15 @@ __device__ void run_checker(CodeState *cs, const StageDesc *sdesc, int ns, const
     }
 }
 
+// Waves per SIMD the plain enumeration kernel is compiled for (its VGPR budget:
+// 512 / waves, in granules of 8): the occupancy the LDS of its workgroups
+// allows anyway.
+template <int P, int W>
+constexpr int enum_waves() { return (P == 3 && W <= 2) || (P == 7 && W == 1) ? 5 : 1; }
+
 template <int P, int W, bool HIST>
-__global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__restrict__ rows,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(enum_waves<P, W>())))
+void enum_kernel(CodeState *cs, const u32 *__restrict__ rows,
                                                    const u64 *__restrict__ gbin, u64 *__restrict__ hist,
                                                    EnumArgs ea) {
     const int lookahead = ea.lookahead;
@@ -1075,6 +1083,8 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
     __shared__ u64 red_cnt[WAVES_PER_GROUP];
     __shared__ int s_term;
     __shared__ int s_crit;
+    __shared__ u64 s_claim[2];
+    __shared__ int s_cterm[2];
     const int lane = __lane_id();
     const int wid = threadIdx.x >> 6;
     const uint32_t grid = gridDim.x, b = blockIdx.x;
@@ -1103,7 +1113,143 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
     u64 *wake = &cs->wake[b % WAKE_COPIES][0];
     u32 *lh = HIST ? &lhist[wid * (BZ_MAX_N + 1)] : nullptr;
     const u32 cap = (u32)n;
-    for (int s = 0; s < ns; s++) {
+    // the pool (see pool_stages): its stages complete when all their tiles
+    // are done, so their part count in this workgroup's copy is the tile count
+    u64 pool_tiles;
+    const int sp = uni(pool_stages(sdesc, ns, grid, &pool_tiles));
+    pool_tiles = uni64(pool_tiles);
+    if ((int)threadIdx.x < sp) sdesc[threadIdx.x].parts = (uint32_t)sdesc[threadIdx.x].tiles;
+    __syncthreads();
+
+    // one tile of stage s: wavefront wid runs task tile * 4 + wid
+    auto run_tile = [&](const StageDesc &sd, int s, u64 tile, u32 &lmin, u64 &lcnt) {
+        const int sg = uni(sd.g);
+        const u64 tasks = uni64(sd.tasks);
+        const u64 task = tile * WAVES_PER_GROUP + (u64)wid;
+        if (task >= tasks) return;  // a missing task only happens in the last tile
+        const u32 woff = skip ? (u32)sg : 0u;
+        if constexpr (HIST) {
+            for (int w = lane; w <= n; w += 64) lh[w] = 0;
+        }
+        if (sg > SUBSET_G)
+            run_base_task<P, W, HIST>(sd, k, uni(sd.j - 1), rows, sbin, gbin, qtab, k - 2 - (sg - 3), task, lmin,
+                                      lcnt, lh, woff, cap);
+        else
+            run_small_task<P, W, HIST>(sg, k, uni(sd.j - 1), rows, sbin, gbin, task, lmin, lcnt, lh, woff, cap);
+        if constexpr (HIST) {
+            for (int w = lane; w <= n; w += 64) {
+                const u32 c = lh[w];
+                if (c) atomicAdd((unsigned long long *)&hist[(size_t)s * (BZ_MAX_N + 1) + w], (unsigned long long)c);
+            }
+        }
+    };
+    // this workgroup's results for stage s: a workgroup reduction, then one set
+    // of atomics; `add` counts towards the stage's parts (the workgroup that
+    // completes them checks the stage and every done stage after it)
+    auto flush_stage = [&](int s, u32 lmin, u64 lcnt, uint32_t add) {
+        const StageDesc &sd = sdesc[s];
+        const u32 woff = skip ? (u32)uni(sd.g) : 0u;
+        for (int off = 32; off >= 1; off >>= 1) {
+            lmin = min(lmin, (u32)__shfl_xor((int)lmin, off));
+            lcnt += __shfl_xor(lcnt, off);
+        }
+        if (lane == 0) {
+            red_min[wid] = lmin;
+            red_cnt[wid] = lcnt;
+        }
+        if constexpr (HIST) drain_vmem();  // this wave's histogram atomics are performed
+        __syncthreads();
+        if (wid == 0) {
+            uint32_t done = 0;
+            if (lane == 0) {
+                u32 bm = red_min[0];
+                u64 bc = red_cnt[0];
+                for (int w = 1; w < WAVES_PER_GROUP; w++) {
+                    bm = min(bm, red_min[w]);
+                    bc += red_cnt[w];
+                }
+                if (bm != BIG) atomicMin(&cs->res.stage_min[s], (int)(bm + woff));
+                atomicAdd((unsigned long long *)&cs->res.stage_count[s], (unsigned long long)bc);
+                drain_vmem();  // minimum and count performed before done counts this workgroup
+                done = __hip_atomic_fetch_add(&cs->stage_done[s], add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + add;
+                if (tr_wg || (tracing && done == sd.parts))  // the last one always
+                    atomicMax((unsigned long long *)&cs->trace[2 + s][1], (unsigned long long)wall_clock64());
+            }
+            if (uni(done) == sd.parts) {
+                run_checker(cs, sdesc, ns, ea);
+                if (tracing && lane == 0)
+                    atomicMax((unsigned long long *)&cs->trace[2 + s][2], (unsigned long long)wall_clock64());
+            }
+        }
+        __syncthreads();  // qtab and red_* are rewritten next
+    };
+
+    if (sp > 0) {
+        // the pool: workgroup b runs pool tile b first, then claims the
+        // others (grid and up) from its slice, each claim issued before the
+        // tile in hand runs so that its latency is hidden, until the slice is
+        // empty or the run has ended before the claimed tile's stage.  Claims
+        // of one slice come in increasing order, so a workgroup's stages only
+        // move forward; it reports a stage when it moves past it.
+        const uint32_t C = pool_slices(grid), slice = b % C;
+        uint32_t *ctr = &cs->pool_next[slice][0];
+        int ps = -1;          // the stage whose results this workgroup holds
+        u64 pbase = 0;        // its first pool tile
+        uint32_t pheld = 0;   // its tiles done here
+        u32 lmin = BIG;
+        u64 lcnt = 0;
+        u64 u = (u64)b < pool_tiles ? (u64)b : ~0ull;
+        int t2 = -1;
+        for (uint32_t it = 0;; it++) {
+            uint32_t ci = 0;
+            if (threadIdx.x == 0 && u != ~0ull)
+                ci = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            int sn = ps < 0 ? 0 : ps;
+            bool end = u == ~0ull;
+            if (!end) {
+                sn = uni(pool_stage_of(sdesc, sp, sn, u, grid));
+                // the run ended before this stage (the claim just made is of a
+                // later stage still, and is dropped)
+                end = t2 >= 0 && sn > t2;
+            }
+            if (ps >= 0 && (end || sn != ps)) {
+                flush_stage(ps, lmin, lcnt, pheld);
+                lmin = BIG;
+                lcnt = 0;
+                pheld = 0;
+            }
+            if (end) break;
+            if (sn != ps) {
+                ps = sn;
+                pbase = nowait_offset(uni(sdesc[sn].rot), grid);
+                const StageDesc &sd = sdesc[sn];
+                if (wid == 0 && sd.g > SUBSET_G)
+                    wave_qtable(P, k, sd.g, sd.coef_combos, sd.sweep_cap, sd.vcap, sbin, gbin, qtab);
+                if (tr_wg && threadIdx.x == 0) {
+                    const unsigned long long now = (unsigned long long)wall_clock64();
+                    atomicMin((unsigned long long *)&cs->trace[2 + sn][0], now);
+                    atomicMax((unsigned long long *)&cs->trace[2 + sn][3], now);
+                }
+                __syncthreads();
+            }
+#ifdef BZ_POOL_PRIO
+            if (ps + 1 < sp) __builtin_amdgcn_s_setprio(2);
+            else __builtin_amdgcn_s_setprio(0);
+#endif
+            run_tile(sdesc[ps], ps, u - pbase, lmin, lcnt);
+            pheld++;
+            if (threadIdx.x == 0) {
+                const u64 nu = (u64)grid + pool_tile(slice, ci, C);
+                s_claim[it & 1] = nu < pool_tiles ? nu : ~0ull;
+                s_cterm[it & 1] = wake_term(ld_poll(wake));
+            }
+            __syncthreads();  // (double buffers: the pair written two rounds ago was read before the last barrier)
+            u = uni64(s_claim[it & 1]);
+            t2 = uni(s_cterm[it & 1]);
+        }
+    }
+
+    for (int s = sp; s < ns; s++) {
         const StageDesc &sd = sdesc[s];
         if (tile_of(0, b, grid, sd.rot) >= sd.tiles) continue;  // no tile of this stage here
         int term0 = 0;
@@ -1160,72 +1306,19 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
         // work on the earliest unchecked stage runs at a higher wave priority than run-ahead work
         if (crit) __builtin_amdgcn_s_setprio(2);
         else __builtin_amdgcn_s_setprio(0);
-        const int sg = uni(sd.g);
-        const int nq = k - 2 - (sg - 3);
-        const int j = uni(sd.j - 1);
-        const u64 tiles = uni64(sd.tiles), tasks = uni64(sd.tasks);
-        const u32 woff = skip ? (u32)sg : 0u;
         u32 lmin = BIG;
         u64 lcnt = 0;  // combinations this lane evaluated in the stage
         for (u64 r = 0;; r++) {
             const u64 tile = tile_of(r, b, grid, sd.rot);
-            if (tile >= tiles) break;  // a missing tile only happens in the last round
+            if (tile >= sd.tiles) break;  // a missing tile only happens in the last round
             if (r > 0) {
                 // a later stage after termination is abandoned (its results are never read)
                 const int t2 = uni(lane == 0 ? wake_term(ld_poll(wake)) : 0);
                 if (t2 >= 0 && s > t2) break;
             }
-            const u64 task = tile * WAVES_PER_GROUP + (u64)wid;
-            if (task >= tasks) continue;
-            if constexpr (HIST) {
-                for (int w = lane; w <= n; w += 64) lh[w] = 0;
-            }
-            if (sg > SUBSET_G)
-                run_base_task<P, W, HIST>(sd, k, j, rows, sbin, gbin, qtab, nq, task, lmin, lcnt, lh, woff, cap);
-            else
-                run_small_task<P, W, HIST>(sg, k, j, rows, sbin, gbin, task, lmin, lcnt, lh, woff, cap);
-            if constexpr (HIST) {
-                for (int w = lane; w <= n; w += 64) {
-                    const u32 c = lh[w];
-                    if (c) atomicAdd((unsigned long long *)&hist[(size_t)s * (BZ_MAX_N + 1) + w], (unsigned long long)c);
-                }
-            }
+            run_tile(sd, s, tile, lmin, lcnt);
         }
-        // workgroup reduction, then one set of atomics per workgroup and stage
-        for (int off = 32; off >= 1; off >>= 1) {
-            lmin = min(lmin, (u32)__shfl_xor((int)lmin, off));
-            lcnt += __shfl_xor(lcnt, off);
-        }
-        if (lane == 0) {
-            red_min[wid] = lmin;
-            red_cnt[wid] = lcnt;
-        }
-        if constexpr (HIST) drain_vmem();  // this wave's histogram atomics are performed
-        __syncthreads();
-        if (wid == 0) {
-            uint32_t done = 0;
-            if (lane == 0) {
-                u32 bm = red_min[0];
-                u64 bc = red_cnt[0];
-                for (int w = 1; w < WAVES_PER_GROUP; w++) {
-                    bm = min(bm, red_min[w]);
-                    bc += red_cnt[w];
-                }
-                if (bm != BIG) atomicMin(&cs->res.stage_min[s], (int)(bm + woff));
-                atomicAdd((unsigned long long *)&cs->res.stage_count[s], (unsigned long long)bc);
-                drain_vmem();  // minimum and count performed before done counts this workgroup
-                done = __hip_atomic_fetch_add(&cs->stage_done[s], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-                if (tr_wg || (tracing && done == sd.parts))  // the last one always
-                    atomicMax((unsigned long long *)&cs->trace[2 + s][1], (unsigned long long)wall_clock64());
-            }
-            // the last workgroup of a stage checks it (and every done stage after it)
-            if (uni(done) == sd.parts) {
-                run_checker(cs, sdesc, ns, ea);
-                if (tracing && lane == 0)
-                    atomicMax((unsigned long long *)&cs->trace[2 + s][2], (unsigned long long)wall_clock64());
-            }
-        }
-        __syncthreads();  // qtab and red_* are rewritten by the next stage
+        flush_stage(s, lmin, lcnt, 1u);
     }
     if (tr_wg && threadIdx.x == 0) atomicMax((unsigned long long *)&cs->trace[1][1], (unsigned long long)wall_clock64());
 }

@@ -72,6 +72,10 @@ struct QEntry {
     uint32_t vd;   // a lane takes 2^vd consecutive bases, see qgroup_digits
 };
 
+// The plain enumeration kernel hands out the stages that start at once as
+// one pool of tiles, claimed by POOL_SLICES counters (see pool_stages).
+constexpr uint32_t POOL_SLICES = 32;
+
 // Results the host reads back (kept contiguous and first in CodeState).
 struct CodeResult {
     int32_t status;       // BZ_OK or a negative status
@@ -114,6 +118,8 @@ struct CodeState {
     // one per 128-byte line (workgroup b reads copy b mod WAKE_COPIES), so
     // that a thousand pollers do not queue on one address; see wake_make
     u64 wake[WAKE_COPIES][16];
+    // claim counters of the pool, one per 128-byte line (see pool_stages)
+    uint32_t pool_next[POOL_SLICES][32];
 };
 
 // Claim word of a code in a batch: stage + 1 (bits 48-63, 0 = nothing to
@@ -209,6 +215,9 @@ BZ_HD int bound_c(int g, int k, int kj) {
 #define BZ_SWEEP_OPS 4500
 #endif
 constexpr uint32_t DEFAULT_SWEEP_OPS = BZ_SWEEP_OPS;
+// Task size of the plain path: F_3 tasks of 3000 operations (the F_3 [72,36]
+// codes run 3% faster than with 4500, F_7 [48,24] 4% slower).
+BZ_HD uint32_t plain_sweep_ops(int p) { return p == 3 ? 3000u : DEFAULT_SWEEP_OPS; }
 BZ_HD uint32_t sweep_cap_for(int p, int W, uint32_t ops = DEFAULT_SWEEP_OPS) {
     const uint32_t per = (p == 3) ? 2u * (6u * (uint32_t)W + 1u) : 6u * (25u * (uint32_t)W + 3u);
     const uint32_t cap = (ops ? ops : DEFAULT_SWEEP_OPS) / per;
@@ -592,6 +601,44 @@ BZ_HD void fill_round_table(int p, int k, int W, uint32_t grid, uint32_t sweep_o
 BZ_HD u64 tile_of(u64 r, uint32_t b, uint32_t grid, uint32_t rot) {
     const uint32_t bb = (uint32_t)(((u64)b + rot) % grid);
     return r * grid + ((r & 1) ? (grid - 1 - bb) : bb);
+}
+
+// The pool of the plain enumeration kernel.  The stages that start at once
+// (nowait) are a prefix of the schedule, and all of them but the last have
+// fewer tiles than the grid (each starts within the first pass).  These
+// stages, without the last one when it holds more than pool_stage_cap tiles,
+// are numbered as one sequence of "pool tiles" in schedule order (the tiles of
+// stage s are off_s .. off_s + tiles_s - 1).  Workgroup b runs pool tile b
+// first; the tiles from grid on are handed out one at a time while the
+// workgroups last: slice c of C = pool_slices(grid) counters hands out the
+// pool tiles grid + c, grid + c + C, grid + c + 2C, ... in this order, and
+// workgroup b claims from slice b mod C.  Every slice thus holds the same mix
+// of heavy and light tiles, no counter serves more than grid / C workgroups,
+// and a workgroup that drew light tiles simply claims more.
+BZ_HD uint32_t pool_slices(uint32_t grid) { return grid < POOL_SLICES ? grid : POOL_SLICES; }
+BZ_HD u64 pool_stage_cap(uint32_t grid) { return 32ull * grid; }
+// off_s of a stage that starts at once (off_s < grid), from its rotation
+BZ_HD u64 nowait_offset(uint32_t rot, uint32_t grid) { return (u64)((grid - rot) % grid); }
+// The number of pool stages; *tiles = their tiles (< grid + pool_stage_cap).
+BZ_HD int pool_stages(const StageDesc *st, int ns, uint32_t grid, u64 *tiles) {
+    int lo = 0, hi = ns;  // the first stage that waits (nowait is a prefix)
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (st[mid].nowait) lo = mid + 1;
+        else hi = mid;
+    }
+    int sp = lo;
+    if (sp > 0 && st[sp - 1].tiles > pool_stage_cap(grid)) sp--;
+    *tiles = sp > 0 ? nowait_offset(st[sp - 1].rot, grid) + st[sp - 1].tiles : 0;
+    return sp;
+}
+// pool tile number i of slice c, counted from the first claimed tile (grid)
+BZ_HD u64 pool_tile(uint32_t c, uint32_t i, uint32_t C) { return (u64)c + (u64)C * i; }
+// The pool stage of pool tile u (< the pool's tiles), searching upward from
+// stage s (a stage at or before it).
+BZ_HD int pool_stage_of(const StageDesc *st, int sp, int s, u64 u, uint32_t grid) {
+    while (s + 1 < sp && nowait_offset(st[s + 1].rot, grid) <= u) s++;
+    return s;
 }
 
 BZ_HD void fill_binomials(u64 *tab) {

@@ -123,6 +123,50 @@ static void check_arith() {
 static u64 C(int n, int r) { return binom_sat(n, r); }
 static u64 BINOM[65 * 65];
 
+// The pool of the plain enumeration kernel (pool_stages): the nowait prefix
+// (without its last stage when that one is over the cap), numbered from
+// off_0 = 0 on; the first tile of every workgroup plus the slices' claims hand
+// out every pool tile exactly once, and the stage walk finds each tile's stage.
+static void check_pool(const StageDesc *st, int ns, uint32_t grid) {
+    u64 ptiles = 0;
+    const int sp = pool_stages(st, ns, grid, &ptiles);
+    int nw = 0;
+    while (nw < ns && st[nw].nowait) nw++;
+    for (int s = nw; s < ns; s++) CHECK(!st[s].nowait);
+    CHECK(sp == nw || (nw > 0 && sp == nw - 1 && st[nw - 1].tiles > pool_stage_cap(grid)));
+    u64 off = 0;
+    for (int s = 0; s < sp; s++) {
+        CHECK(nowait_offset(st[s].rot, grid) == off);
+        if (s + 1 < sp) CHECK(st[s].tiles < grid);
+        CHECK(st[s].tiles >= 1 && st[s].tiles <= pool_stage_cap(grid));
+        off += st[s].tiles;
+    }
+    CHECK(ptiles == off);
+    if (ptiles > 4000000) return;
+    std::vector<int> seen(ptiles, 0);
+    const uint32_t C = pool_slices(grid);
+    for (u64 b = 0; b < grid && b < ptiles; b++) seen[b]++;
+    for (uint32_t c = 0; c < C; c++) {
+        u64 last = 0;
+        for (uint32_t i = 0;; i++) {
+            const u64 u = grid + pool_tile(c, i, C);
+            if (u >= ptiles) break;
+            CHECK(u > last);
+            last = u;
+            seen[u]++;
+        }
+    }
+    for (u64 u = 0; u < ptiles; u++) CHECK(seen[u] == 1);
+    int prev = 0;
+    for (u64 u = 0; u < ptiles; u++) {
+        const int s0 = pool_stage_of(st, sp, 0, u, grid);
+        const u64 o = nowait_offset(st[s0].rot, grid);
+        CHECK(s0 < sp && o <= u && u < o + st[s0].tiles);
+        CHECK(pool_stage_of(st, sp, prev, u, grid) == s0);
+        prev = s0;
+    }
+}
+
 static void check_schedule() {
     const int before = fails;
     struct Case { int p, k, m; std::vector<int> ranks; };
@@ -198,6 +242,15 @@ static void check_schedule() {
                 CHECK(d.check == ((flags & FLAG_NO_TERM) ? 0 : (flags & FLAG_ROUND) ? (d.j == c.m) : 1));
             }
             if (complete) CHECK(ns == c.k * c.m);
+            check_pool(st, ns, grid);
+            for (uint32_t g2 : {1u, 7u, 64u, 1280u, 1536u}) {
+                for (uint32_t ops : {plain_sweep_ops(c.p), 700u}) {
+                    StageDesc st2[BZ_MAX_STAGES];
+                    int ns2 = build_schedule(c.p, c.k, c.m, c.ranks.data(), flags, ~0ull, g2, 2, BINOM, st2, &complete,
+                                             true, ops);
+                    check_pool(st2, ns2, g2);
+                }
+            }
         }
         // the work limit cuts the schedule before the stage that would exceed it
         StageDesc st[BZ_MAX_STAGES];
