@@ -279,7 +279,10 @@ def bench_plain(cfg, K, Wm, blocks_per_cu=0):
     """The plain path on one single-code workload: K codes (seeds 0..K-1), one
     call each, generators resident in HBM, Wm warm-up calls on other seeds.
     The call's arguments are prepared once, as a C caller holding its inputs
-    in HBM would: a step is the library call."""
+    in HBM would: a step is the library call.  The timed pass runs without
+    timing events (the call returns when the final check hands the result
+    over); a second pass over the same codes with HIP events gives the kernel
+    durations for the roofline, and its results must equal the first's."""
     import ctypes
     import numpy as np
     import torch
@@ -290,7 +293,7 @@ def bench_plain(cfg, K, Wm, blocks_per_cu=0):
     Gw = torch.from_numpy(np.stack([synth.config_code(cfg, 10000 + s)[1] for s in range(max(Wm, 1))])).to(dev)
     torch.cuda.synchronize()
     o = bz.bz_default_options()
-    o.timing = 1
+    o.timing = 0
     o.blocks_per_cu = blocks_per_cu
     o.max_codewords = 1 << 40
     o.hip_stream = bz._stream_of(Gt)
@@ -320,8 +323,17 @@ def bench_plain(cfg, K, Wm, blocks_per_cu=0):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     cws = [r.codewords_total for r in outs]
-    enum_ms = [r.enum_ms for r in outs]
-    dec_ms = [r.decompose_ms for r in outs]
+    # the kernel durations: the same codes again, with HIP events on the stream
+    o.timing = 1
+    timed = [bz.bz_result() for _ in range(K)]
+    for i in range(K):
+        run(ptr_t[i], ctypes.byref(timed[i]))
+    torch.cuda.synchronize()
+    o.timing = 0
+    if [(r.d, r.codewords_total) for r in timed] != [(r.d, r.codewords_total) for r in outs]:
+        raise RuntimeError("the timed pass and the event pass disagree")
+    enum_ms = [r.enum_ms for r in timed]
+    dec_ms = [r.decompose_ms for r in timed]
     W = (n - k + 31) // 32  # words per plane over the non-pivot columns
     opc = ops_per_codeword(p, W)
     total_cw = sum(cws)
