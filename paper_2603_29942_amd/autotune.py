@@ -8,8 +8,9 @@ last-row sweeps add up to about `sweep_ops` VALU operations; small values cut
 stages into many short tasks (better balance, more per-task decoding), large
 values into few long ones.  The best value depends on the field and on W (the
 words per plane a combination takes), so codes are grouped by (p, W) and each
-group is timed as its own batch for every candidate; then the grid shape is
-timed on the whole sample with the chosen sizes.  Results never depend on
+group is timed as its own batch for every candidate (the smallest size within
+1% of the fastest is taken); then the grid shape is timed on the whole sample
+with the chosen sizes.  Results never depend on
 these knobs (the tests check it); only time does.
 
 The table is JSON: {"sweep_ops": {"p,W": ops, ...}, "blocks_per_cu": b,
@@ -92,7 +93,10 @@ def tune(codes, reps=2, sweep_candidates=SWEEP_CANDIDATES, bpc_candidates=BPC_CA
         row = {}
         for ops in sweep_candidates:
             row[ops] = _time_batch(bz, cs, dev, reps, sweep_ops=ops)
-        best = min(row, key=row.get)
+        # the smallest size within 1% of the fastest: the times are flat over a
+        # wide range, and smaller parts let a serving round yield sooner
+        tmin = min(row.values())
+        best = min(o for o, t in row.items() if t <= 1.01 * tmin)
         chosen[key] = best
         timings[f"{key[0]},{key[1]}"] = {str(o): round(t, 4) for o, t in row.items()}
         log(f"  p={key[0]} W={key[1]} ({len(cs)} codes): " +

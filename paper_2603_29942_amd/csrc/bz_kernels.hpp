@@ -1062,15 +1062,8 @@ __device__ void run_checker(CodeState *cs, const StageDesc *sdesc, int ns, const
     }
 }
 
-// Waves per SIMD the plain enumeration kernel is compiled for (its VGPR budget:
-// 512 / waves, in granules of 8): the occupancy the LDS of its workgroups
-// allows anyway.
-template <int P, int W>
-constexpr int enum_waves() { return (P == 3 && W <= 2) || (P == 7 && W == 1) ? 5 : 1; }
-
 template <int P, int W, bool HIST>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(enum_waves<P, W>())))
-void enum_kernel(CodeState *cs, const u32 *__restrict__ rows,
+__global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__restrict__ rows,
                                                    const u64 *__restrict__ gbin, u64 *__restrict__ hist,
                                                    EnumArgs ea) {
     const int lookahead = ea.lookahead;
