@@ -120,7 +120,7 @@ __device__ __forceinline__ u64 wave_qtable(int p, int k, int g, u64 M, uint32_t 
         bases = sat_mul(c, M);
         nb = qgroup_blocks(k, cap, q);
         vd = qgroup_digits(p, k, g, vcap, q, bases);
-        val = qgroup_tasks(bases, nb, vd);  // <= 2^58 * 62: no overflow
+        val = qgroup_tasks(p, bases, nb, vd);  // <= 2^58 * 62: no overflow
     }
     // inclusive scan of val over the lanes (saturating)
     u64 inc = val;
@@ -151,7 +151,7 @@ struct DecompLDS {
     uint32_t s_vcap[BZ_MAX_K];  // run budget of round g (0: no runs), at [g - 1]
     uint32_t s_combos[BZ_MAX_K];
     uint32_t s_nb[BZ_MAX_K];  // blocks of rows s of the q-group with top row q, at [q]
-    uint32_t s_dt[BZ_MAX_K];  // F_3: digits_by_steps of the q-group with top row q, at [q]
+    uint32_t s_dt[BZ_MAX_K];  // digits_by_steps of the q-group with top row q, at [q]
 };
 
 // One Gauss-Jordan step on the rows held one per lane: row pl (pivot value
@@ -535,7 +535,7 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
         const RoundTable *rt = args.rounds;
         if (rt == nullptr && lane <= k - 3) {
             lds.s_nb[lane] = qgroup_blocks(k, cap, lane);
-            if (P == 3) lds.s_dt[lane] = digits_by_steps(k, lane, budget);
+            lds.s_dt[lane] = digits_by_steps(P, k, lane, budget);
         }
         __syncthreads();
         const bool counted = in && g > SUBSET_G && g <= last_g;
@@ -557,12 +557,12 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
                 // (ceil64 <= 2^58 and nb <= 62: the product cannot overflow)
                 const u64 bases = sat_mul32(binom[q * 65 + (g - 3)], (uint32_t)combos);
                 const uint32_t nb = lds.s_nb[q];
-                tg = sat_add(tg, qgroup_tasks(bases, nb, 0));
-                if constexpr (P == 3) tgv = sat_add(tgv, qgroup_tasks(bases, nb, digits_of(g, lds.s_dt[q], bases)));
+                tg = sat_add(tg, qgroup_tasks(P, bases, nb, 0));
+                tgv = sat_add(tgv, qgroup_tasks(P, bases, nb, digits_of(P, g, lds.s_dt[q], bases)));
             }
             // the round takes runs of bases where they pay (qgroup_digits with
             // the run budget, as a table of digits_by_steps)
-            const bool runs = P == 3 && runs_pay(tgv, args.grid);
+            const bool runs = runs_pay(tgv, args.grid);
             s_tasks[lane] = runs ? tgv : tg;
             lds.s_vcap[lane] = runs ? budget : 0u;
         }
@@ -926,11 +926,12 @@ __device__ void run_small_task(int g, int k, int j, const u32 *__restrict__ rows
 }
 
 // g > SUBSET_G: one task = (q, chunk of 64 lanes, block of rows s); see
-// StageDesc.  A lane takes the 2^vd consecutive bases (2^vd bi, ...,
-// 2^vd bi + 2^vd - 1), vd > 0 only for F_3: they differ in the coefficients
-// (1 or 2) of the first vd rows in decoding order, the top row q first.  The
-// lane decodes the first of them and walks the others in Gray-code order, one
-// row added (coefficient 1 -> 2) or subtracted (2 -> 1) per step.  Adds the
+// StageDesc.  A lane takes the r = (p-1)^vd consecutive bases (r bi, ...,
+// r bi + r - 1): they differ in the coefficients of the first vd rows in
+// decoding order, the top row q first.  The lane decodes the first of them
+// and walks the others: F_3 in Gray-code order, one row added (coefficient
+// 1 -> 2) or subtracted (2 -> 1) per step; F_7 (vd = 1) through the
+// coefficients 1 .. 6 of row q, one addition of row q per step.  Adds the
 // combinations the lane evaluated (the rows its sweeps combined) to lcnt.
 template <int P, int W, bool HIST>
 __device__ void run_base_task(const StageDesc &sd, int k, int j, const u32 *__restrict__ rows, const u64 *sbin,
@@ -944,14 +945,14 @@ __device__ void run_base_task(const StageDesc &sd, int k, int j, const u32 *__re
     // the q-group's entry as wave-uniform (scalar) values
     const u64 e_first = uni64(qtab[qi].first), e_bases = uni64(qtab[qi].bases);
     const uint32_t e_nb = uni(qtab[qi].nb);
-    const int vd = (P == 3) ? uni(qtab[qi].vd) : 0;
+    const int vd = uni(qtab[qi].vd);
     const u64 local = task - e_first;
     const u64 chunk = local / e_nb;
     const int block = (int)(local - chunk * e_nb);
     const int s_lo = q + 1 + uni(qgroup_block_start(k, q, e_nb, (uint32_t)block));
     const int s_hi = q + 1 + uni(qgroup_block_start(k, q, e_nb, (uint32_t)block + 1));
-    const u64 bi = (chunk * 64 + (u64)lane) << vd;
-    const bool valid = bi < e_bases;  // the 2^vd bases of a lane are valid together (2^vd divides bases)
+    const u64 bi = (chunk * 64 + (u64)lane) * (u64)run_len(P, (uint32_t)vd);
+    const bool valid = bi < e_bases;  // the bases of a lane's run are valid together (its length divides bases)
     u32 Q[3][W];
 #pragma unroll
     for (int b = 0; b < 3; b++)
@@ -976,6 +977,26 @@ __device__ void run_base_task(const StageDesc &sd, int k, int j, const u32 *__re
         }
         lcnt += ncomb;
         return;
+    }
+    if constexpr (P == 7) {
+        // a run of 6 bases per lane: the first has coefficient 1 on row q (its
+        // digit 0 is 0, the run being aligned), the next ones 2, ..., 6, each
+        // one addition of row q (wave-uniform) away from the previous
+        if (valid) {
+            decode_base<P>(g, q, M, bi, [&](int c, int i) { return binom_at(sbin, gbin, c, i); },
+                           [&](int row, int coef) {
+                               const Row<W> r = load_row<P, W>(rows, j, row);
+                               add_scaled<P, W>(Q, r.p, coef);
+                           });
+        }
+        const Row<W> Rq = load_row<P, W>(rows, j, q);
+        for (int v = 0; v < P - 1; v++) {
+            if (v > 0 && valid) add_scaled<P, W>(Q, Rq.p, 1);
+            for (int s = s_lo; s < s_hi; s++) {
+                const Row<W> Rs = load_row<P, W>(rows, j, uni(s));
+                if (valid) ncomb += PER_ROW * (u32)extend_and_sweep<P, W, P - 1, HIST>(rows, j, s, k, Q, Rs, lmin, lh, woff, cap);
+            }
+        }
     }
     if constexpr (P == 3) {
         // a run of 2^vd bases per lane; the rows of digits 1 and 2 are held

@@ -58,7 +58,7 @@ struct StageDesc {
     uint32_t parts;        // workgroups that own at least one tile: min(grid, tiles)
     uint32_t sweep_cap;    // g >= 3: target (s, L) steps per lane and task
     uint32_t rot;          // (grid - off_s mod grid) mod grid, see tile_of
-    uint32_t vcap;         // F_3: step budget of a lane's run of bases (qgroup_digits);
+    uint32_t vcap;         // step budget of a lane's run of bases (qgroup_digits);
                            // 0: one base per lane
     uint32_t pad;
 };
@@ -69,7 +69,7 @@ struct QEntry {
     u64 first;     // first task of the group
     u64 bases;     // C(q, g-3) (p-1)^(g-3)
     uint32_t nb;   // blocks of rows s, see qgroup_blocks
-    uint32_t vd;   // a lane takes 2^vd consecutive bases, see qgroup_digits
+    uint32_t vd;   // a lane takes (p-1)^vd consecutive bases, see qgroup_digits
 };
 
 // The plain enumeration kernel hands out the stages that start at once as
@@ -249,37 +249,46 @@ BZ_HD int qgroup_block_start(int k, int q, uint32_t nb, uint32_t b) {
     }
     return (int)(lo > b ? lo : b);
 }
-// Low coefficient digits a lane runs through itself (F_3 only): 2^vd
-// consecutive bases differ only in the coefficients (1 or 2) of their first vd
-// rows in decoding order (the top row q first), so one decoding and one row
-// addition per further base serve them all (a Gray-code walk).  vd is the
-// largest d <= min(g-3, 3) with T 2^d <= vcap (the lane's (s, L) steps stay
-// within the run budget; with vcap <= cap the group is then one block) and
-// bases >= 64 2^d (the group still fills a wavefront); T = len (len + 1) / 2
-// as in qgroup_blocks.  vcap = 0: no runs.
+// Low coefficient digits a lane runs through itself: a lane takes
+// (p-1)^vd consecutive bases, which differ only in the coefficients of their
+// first vd rows in decoding order (the top row q first), so one decoding and
+// one row addition per further base serve them all.  F_3 (vd <= 3): the
+// coefficients 1 or 2 of vd rows, walked in Gray-code order.  F_7 (vd <= 1):
+// the coefficient 1, 2, ..., 6 of row q, one addition of row q per step.  vd
+// is the largest d <= min(g-3, max_digits(p)) with T (p-1)^d <= vcap (the
+// lane's (s, L) steps stay within the run budget; with vcap <= cap the group
+// is then one block) and bases >= 64 (p-1)^d (the group still fills a
+// wavefront); T = len (len + 1) / 2 as in qgroup_blocks.  vcap = 0: no runs.
 constexpr int BZ_MAX_VD = 3;
-// the largest d with T 2^d <= vcap, 0 if none (vcap >= 1)
-BZ_HD uint32_t digits_by_steps(int k, int q, uint32_t vcap) {
+BZ_HD uint32_t max_digits(int p) { return p == 3 ? (uint32_t)BZ_MAX_VD : 1u; }
+// bases per lane, (p-1)^vd
+BZ_HD uint32_t run_len(int p, uint32_t vd) { return p == 3 ? (1u << vd) : (vd ? (uint32_t)(p - 1) : 1u); }
+// the largest d with T (p-1)^d <= vcap, 0 if none (vcap >= 1)
+BZ_HD uint32_t digits_by_steps(int p, int k, int q, uint32_t vcap) {
     const uint32_t len = (uint32_t)(k - 2 - q), T = len * (len + 1) / 2;
-    return vcap >= T ? 31u - (uint32_t)__builtin_clz(vcap / T) : 0u;
+    if (p == 3) return vcap >= T ? 31u - (uint32_t)__builtin_clz(vcap / T) : 0u;
+    return vcap / T >= (uint32_t)(p - 1) ? 1u : 0u;  // (d = 1 is the most F_7 takes)
 }
-// the largest d with bases >= 64 2^d, 0 if none
-BZ_HD uint32_t digits_by_bases(u64 bases) { return bases >= 128 ? 57u - (uint32_t)__builtin_clzll(bases) : 0u; }
-BZ_HD uint32_t digits_of(int g, uint32_t by_steps, u64 bases) {
-    uint32_t d = (uint32_t)(g - 3 < BZ_MAX_VD ? g - 3 : BZ_MAX_VD);
+// the largest d with bases >= 64 (p-1)^d, 0 if none
+BZ_HD uint32_t digits_by_bases(int p, u64 bases) {
+    if (p == 3) return bases >= 128 ? 57u - (uint32_t)__builtin_clzll(bases) : 0u;
+    return bases >= 64u * (u64)(p - 1) ? 1u : 0u;
+}
+BZ_HD uint32_t digits_of(int p, int g, uint32_t by_steps, u64 bases) {
+    uint32_t d = (uint32_t)(g - 3) < max_digits(p) ? (uint32_t)(g - 3) : max_digits(p);
     d = by_steps < d ? by_steps : d;
-    const uint32_t b = digits_by_bases(bases);
+    const uint32_t b = digits_by_bases(p, bases);
     return b < d ? b : d;
 }
 BZ_HD uint32_t qgroup_digits(int p, int k, int g, uint32_t vcap, int q, u64 bases) {
-    if (p != 3 || vcap == 0) return 0;
-    return digits_of(g, digits_by_steps(k, q, vcap), bases);
+    if (vcap == 0) return 0;
+    return digits_of(p, g, digits_by_steps(p, k, q, vcap), bases);
 }
 // Run budget of a round: runs shorten the work of a stage but lengthen its
 // tasks and cut their number, so a round takes them only when its stages
 // still have a tile for every workgroup with them (measured: the stages that
 // leave workgroups idle run slower with runs).
-BZ_HD uint32_t run_budget(int p, uint32_t cap) { return p == 3 ? cap : 0u; }
+BZ_HD uint32_t run_budget(int p, uint32_t cap) { return cap; }
 BZ_HD bool runs_pay(u64 tasks_with_runs, uint32_t grid) {
     return (tasks_with_runs + WAVES_PER_GROUP - 1) / WAVES_PER_GROUP >= (u64)grid;
 }
@@ -291,8 +300,12 @@ BZ_HD void qgroup(int k, int g, u64 M, uint32_t cap, uint32_t vcap, const u64 *b
 }
 // chunks of 64 bases (no overflow at the saturated value)
 BZ_HD u64 ceil64(u64 bases) { return (bases >> 6) + ((bases & 63) != 0); }
-// tasks of a q-group: chunks of 64 lanes of 2^vd bases each, times the blocks
-BZ_HD u64 qgroup_tasks(u64 bases, uint32_t nb, uint32_t vd) { return ceil64(bases >> vd) * (u64)nb; }
+// tasks of a q-group: chunks of 64 lanes of (p-1)^vd bases each, times the
+// blocks ((p-1)^vd divides the bases whenever vd > 0)
+BZ_HD u64 qgroup_tasks(int p, u64 bases, uint32_t nb, uint32_t vd) {
+    const u64 lanes = p == 3 ? bases >> vd : (vd ? bases / (u64)(p - 1) : bases);
+    return ceil64(lanes) * (u64)nb;
+}
 
 // Number of tasks of a stage with g >= 3 (saturating); with tab != NULL also
 // fills the q-groups (entries for q = g-3 .. k-3, index q-(g-3)).
@@ -309,7 +322,7 @@ BZ_HD u64 fill_qtable(int p, int k, int g, u64 M, uint32_t cap, uint32_t vcap, c
             e.nb = nb;
             e.vd = vd;
         }
-        first = sat_add(first, qgroup_tasks(bases, nb, vd));
+        first = sat_add(first, qgroup_tasks(p, bases, nb, vd));
     }
     return first;
 }
@@ -485,7 +498,7 @@ BZ_HD void decode_subset(u64 r, int k, Bin bin, int (&rows)[G]) {
 // tasks < 2^62 counted without runs of bases; the last condition only when
 // count_tasks).  The deal of a stage starts at off_s = the tiles of all earlier
 // stages; stages with off_s < grid start at once (nowait), the others wait for
-// the checks.  F_3 rounds take runs of bases where runs_pay.  grid: workgroups
+// the checks.  Rounds take runs of bases where runs_pay.  grid: workgroups
 // of the enumeration launch; W: words per plane of the packed rows.  Returns the
 // number of stages; *complete = 1 if the schedule reaches (k, m).
 // binom[c*65+i] = C(c, i) for c, i <= 64.

@@ -323,15 +323,15 @@ static int lane_parallel_schedule(int p, int k, int m, const int *ranks, int fla
         for (int q = g - 3; q <= k - 3; q++) {
             const u64 bases = sat_mul32(BINOM[q * 65 + (g - 3)], combos[g - 1]);
             const uint32_t nb = qgroup_blocks(k, cap, q);
-            t = sat_add(t, qgroup_tasks(bases, nb, 0));
-            if (p == 3) tv = sat_add(tv, qgroup_tasks(bases, nb, digits_of(g, digits_by_steps(k, q, budget), bases)));
+            t = sat_add(t, qgroup_tasks(p, bases, nb, 0));
+            tv = sat_add(tv, qgroup_tasks(p, bases, nb, digits_of(p, g, digits_by_steps(p, k, q, budget), bases)));
         }
         if (t >= (1ull << 62)) {
             ns = std::min(ns, (g - 1) * m);
             *complete = 0;
             break;
         }
-        const bool runs = p == 3 && runs_pay(tv, grid);
+        const bool runs = runs_pay(tv, grid);
         tasks[g - 1] = runs ? tv : t;
         vcaps[g - 1] = runs ? budget : 0u;
     }
@@ -417,22 +417,21 @@ static void check_parallel_schedule() {
 // per-task counts the kernel adds up equal the combinations visited.
 static void check_unrank() {
     const int before = fails;
-    int vd_seen[BZ_MAX_VD + 1] = {0, 0, 0, 0};
+    int vd_seen[BZ_MAX_VD + 1] = {0, 0, 0, 0}, vd7_seen = 0;
     for (int P : {3, 7}) {
         for (int W : {1, 2, 4}) {
             for (int k = 3; k <= (P == 3 && W == 4 ? 13 : 10); k++) {
                 for (int g = 1; g <= k && g <= (P == 3 && W == 4 ? 7 : 6); g++) {
-                  // grid 1: every stage after the first waits (F_3: runs of bases);
+                  // grid 1: every stage after the first waits (runs of bases);
                   // a huge grid: every stage starts at once (one base per lane)
                   for (uint32_t grid : {1u, 1u << 30}) {
-                    if (P == 7 && grid == 1) continue;
                     StageDesc st[BZ_MAX_STAGES];
                     int complete;
                     int32_t ranks[1] = {k};
                     int ns = build_schedule(P, k, 1, ranks, FLAG_NO_TERM, ~0ull, grid, W, BINOM, st, &complete);
                     CHECK(ns == k);
                     const StageDesc &d = st[g - 1];
-                    CHECK(d.vcap == ((P == 3 && g > SUBSET_G && grid == 1) ? d.sweep_cap : 0u));
+                    CHECK(d.vcap == ((g > SUBSET_G && grid == 1) ? d.sweep_cap : 0u));
                     std::map<std::vector<int>, int> seen;
                     u64 counted = 0;
                     auto add = [&](std::vector<int> rows, std::vector<int> coefs) {
@@ -514,13 +513,15 @@ static void check_unrank() {
                             const int len = k - 2 - q, T = len * (len + 1) / 2;
                             CHECK(steps <= std::max(len, (T + (int)e.nb - 1) / (int)e.nb + len));
                             CHECK(s_hi - s_lo == 1 || steps <= 2 * (int)d.sweep_cap);
-                            // a lane's run of 2^vd bases: F_3 only, a whole group in one
-                            // block, within the step budget, every lane's run inside the group
-                            const int nv = 1 << e.vd;
-                            CHECK(e.vd <= (uint32_t)BZ_MAX_VD && (int)e.vd <= g - 3);
+                            // a lane's run of (p-1)^vd bases: a whole group in one block,
+                            // within the step budget, every lane's run inside the group
+                            const int nv = (int)run_len(P, e.vd);
+                            CHECK(e.vd <= max_digits(P) && (int)e.vd <= g - 3);
+                            CHECK(nv == (int)std::pow(P - 1, (int)e.vd));
                             if (e.vd > 0) {
-                                vd_seen[e.vd]++;
-                                CHECK(P == 3 && e.nb == 1 && (u64)nv * (u64)T <= d.sweep_cap);
+                                if (P == 3) vd_seen[e.vd]++;
+                                else vd7_seen++;
+                                CHECK(e.nb == 1 && (u64)nv * (u64)T <= d.sweep_cap);
                                 CHECK(e.bases % (u64)nv == 0 && e.bases >= 64 * (u64)nv);
                             }
                             u64 nvalid = 0;
@@ -533,23 +534,25 @@ static void check_unrank() {
                                 else decode_base<7>(g, q, d.coef_combos, bi, bin, visit);
                             };
                             for (int l = 0; l < 64; l++) {
-                                const u64 bi0 = (chunk * 64 + (u64)l) << e.vd;
+                                const u64 bi0 = (chunk * 64 + (u64)l) * (u64)nv;
                                 if (bi0 >= e.bases) continue;
                                 // the kernel's walk: decode the first base, then per step v
-                                // flip digit t = ctz(v) (coefficient 1 -> 2 or 2 -> 1 of the
-                                // t-th decoded row); the walk must meet the decodings of
-                                // bi0 .. bi0 + 2^vd - 1, each once
+                                // F_3: flip digit t = ctz(v) (coefficient 1 -> 2 or 2 -> 1 of
+                                // the t-th decoded row); F_7: add 1 to the coefficient of the
+                                // top row.  The walk must meet the decodings of bi0 ..
+                                // bi0 + (p-1)^vd - 1, each once
                                 std::vector<int> rows, coefs, r1, c1;
                                 decode(bi0, rows, coefs);
                                 std::set<std::vector<int>> walked, direct;
                                 uint32_t cur = 0;
                                 for (int v = 0; v < nv; v++) {
-                                    if (v > 0) {
+                                    if (v > 0 && P == 3) {
                                         const int t = __builtin_ctz((uint32_t)v);
                                         const int h = ((cur >> t) & 1u) ? 2 : 1;
                                         cur ^= 1u << t;
                                         coefs[t] = (coefs[t] + h) % 3;
                                     }
+                                    if (v > 0 && P == 7) coefs[0] = (coefs[0] + 1) % 7;
                                     nvalid++;
                                     decode(bi0 + (u64)v, r1, c1);
                                     CHECK(r1 == rows);
@@ -598,6 +601,7 @@ static void check_unrank() {
     }
     // every run length occurred (F_3 at W = 4 has the smallest step budget)
     for (int v = 1; v <= BZ_MAX_VD; v++) CHECK(vd_seen[v] > 0);
+    CHECK(vd7_seen > 0);
     if (fails == before) std::printf("OK unrank\n");
 }
 
@@ -605,7 +609,8 @@ static void check_unrank() {
 // masked bits of x in order, to the low end), the saturating products and
 // powers against step-by-step saturation.
 // The digit count of a run of bases (closed form) against its definition: the
-// largest d <= min(g-3, 3) with T 2^d <= vcap and bases >= 64 2^d.
+// largest d <= min(g-3, 3) (F_3; 1 for F_7) with T (p-1)^d <= vcap and
+// bases >= 64 (p-1)^d.
 static void check_digits() {
     const int before = fails;
     std::mt19937_64 rng(99);
@@ -618,7 +623,9 @@ static void check_digits() {
         if (vcap)
             while ((int)d < std::min(g - 3, BZ_MAX_VD) && (u64)T << (d + 1) <= vcap && (bases >> (d + 1)) >= 64) d++;
         CHECK(qgroup_digits(3, k, g, vcap, q, bases) == d);
-        CHECK(qgroup_digits(7, k, g, vcap, q, bases) == 0);
+        // F_7: one digit at most (6 bases per lane)
+        const uint32_t d7 = (vcap && g >= 4 && 6ull * T <= vcap && bases >= 384) ? 1u : 0u;
+        CHECK(qgroup_digits(7, k, g, vcap, q, bases) == d7);
     }
     if (fails == before) std::printf("OK digits\n");
 }
