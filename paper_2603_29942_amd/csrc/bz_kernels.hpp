@@ -1246,10 +1246,6 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
                 }
                 __syncthreads();
             }
-#ifdef BZ_POOL_PRIO
-            if (ps + 1 < sp) __builtin_amdgcn_s_setprio(2);
-            else __builtin_amdgcn_s_setprio(0);
-#endif
             run_tile(sdesc[ps], ps, u - pbase, lmin, lcnt);
             pheld++;
             if (threadIdx.x == 0) {
