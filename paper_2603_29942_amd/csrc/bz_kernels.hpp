@@ -209,13 +209,24 @@ __device__ __forceinline__ void eliminate(u32 (&x)[3][4], int v, int pl, int pv)
     }
 }
 
+// This lane's entries of the per-shape round table (the plain path), read by
+// the caller at the start of the launch so that the loads complete during
+// the elimination; have = false: the rounds are counted instead.
+struct RoundPrefetch {
+    bool have = false;
+    u64 tasks = 0;
+    uint32_t vcap = 0;
+    int cut = 0;
+};
+
 // One code on one wavefront (threads 0..63 of the workgroup).
 // ahead = true: the second workgroup of the plain path (see SpecBuf): the
 // elimination of one set with the columns 0 .. k-1 taken as used, packed into
 // args.spec, and nothing else.
 template <int P, int WF>
 __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32 *__restrict__ rows,
-                               const RunArgs args, DecompLDS &lds, bool ahead = false) {
+                               const RunArgs args, DecompLDS &lds, bool ahead = false,
+                               RoundPrefetch pre = RoundPrefetch()) {
     constexpr int R = (P == 3) ? 2 : 3;
     u64 *binom = lds.binom;
     int32_t *sranks = lds.sranks;
@@ -227,6 +238,10 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
     const bool tracing = !ahead && (flags & FLAG_TRACE) != 0;
     const u64 t_start = tracing ? (u64)wall_clock64() : 0;
     SpecBuf *spec = args.spec;
+    const bool have_rt = pre.have;
+    const u64 rt_tasks = pre.tasks;
+    const uint32_t rt_vcap = pre.vcap;
+    const int rt_cut = pre.cut;
     if (lane == 0 && !ahead) {
         cs->p = P;
         cs->n = n;
@@ -532,21 +547,20 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
         const int last_g = (ns + m - 1) / m;
         const uint32_t cap = sweep_cap_for(P, W, args.sweep_ops);
         const uint32_t budget = run_budget(P, cap);
-        const RoundTable *rt = args.rounds;
-        if (rt == nullptr && lane <= k - 3) {
+        if (!have_rt && lane <= k - 3) {
             lds.s_nb[lane] = qgroup_blocks(k, cap, lane);
             lds.s_dt[lane] = digits_by_steps(P, k, lane, budget);
         }
         __syncthreads();
         const bool counted = in && g > SUBSET_G && g <= last_g;
         u64 tg = 0, tgv = 0;  // without and with runs of bases
-        if (rt != nullptr) {
+        if (have_rt) {
             // the table of this shape (fill_round_table)
             if (counted) {
-                s_tasks[lane] = rt->tasks[lane];
-                lds.s_vcap[lane] = rt->vcap[lane];
+                s_tasks[lane] = rt_tasks;
+                lds.s_vcap[lane] = rt_vcap;
             }
-            tg = (counted && g >= rt->cut_g) ? (1ull << 62) : 0;  // the cut below, from cut_g
+            tg = (counted && g >= uni(rt_cut)) ? (1ull << 62) : 0;  // the cut below, from cut_g
         } else if (counted) {
             // q runs over a wave-uniform range (rows q < g-3 add nothing) so
             // that the unrolled LDS reads overlap
@@ -652,8 +666,16 @@ template <int P, int WF>
 __global__ __launch_bounds__(64) void decompose_kernel(const uint8_t *__restrict__ G, CodeState *cs,
                                                        u32 *__restrict__ rows, RunArgs args) {
     __shared__ DecompLDS lds;
+    RoundPrefetch pre;
+    if (args.rounds != nullptr && blockIdx.x == 0) {
+        const int lane = __lane_id();
+        pre.have = true;
+        pre.tasks = args.rounds->tasks[lane];
+        pre.vcap = args.rounds->vcap[lane];
+        pre.cut = args.rounds->cut_g;
+    }
     // workgroup 1 (only with args.spec): the second information set ahead
-    decompose_code<P, WF>(G, cs, rows, args, lds, blockIdx.x == 1);
+    decompose_code<P, WF>(G, cs, rows, args, lds, blockIdx.x == 1, pre);
 }
 
 // =====================================================================
