@@ -1166,6 +1166,23 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
     const int status0 = cs->res.status, ns0 = cs->res.n_table;
     constexpr int EARLY = 32;  // descriptors loaded before the table size is known
     if (threadIdx.x < EARLY) sdesc[threadIdx.x] = cs->stages[threadIdx.x];
+    if constexpr (P == 3) {
+        // the rows of the first LROW_SETS matrices (the row buffer holds every
+        // set, so the sets past m read unused rows): loads issued before any store
+        constexpr int NR = LROW_SETS * BZ_MAX_K * W, PER = (NR + 255) / 256;
+        uint4 v[PER];
+#pragma unroll
+        for (int r = 0; r < PER; r++) {
+            const int t = (int)threadIdx.x + r * 256;
+            const int jj = t / (BZ_MAX_K * W), rem = t - jj * (BZ_MAX_K * W), i = rem / W, w = rem - i * W;
+            if (t < NR) v[r] = reinterpret_cast<const uint4 *>(rows + (size_t)(jj * BZ_MAX_K + i) * ROW_WORDS)[w];
+        }
+#pragma unroll
+        for (int r = 0; r < PER; r++) {
+            const int t = (int)threadIdx.x + r * 256;
+            if (t < NR) lrow_buf[t] = v[r];
+        }
+    }
     stage_binomials(sbin, gbin, k);  // the rows c < k: every binomial the stages read
     if (threadIdx.x >= EARLY && (int)threadIdx.x < ns0) sdesc[threadIdx.x] = cs->stages[threadIdx.x];
     __syncthreads();
@@ -1176,15 +1193,7 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
     u32 *lh = HIST ? &lhist[wid * (BZ_MAX_N + 1)] : nullptr;
     const u32 cap = (u32)n;
     const uint4 *lrows = nullptr;
-    if constexpr (P == 3) {
-        const int mm = min(uni(cs->res.m), LROW_SETS);
-        const int nr = mm * BZ_MAX_K * W;
-        for (int t = threadIdx.x; t < nr; t += blockDim.x) {
-            const int jj = t / (BZ_MAX_K * W), rem = t - jj * (BZ_MAX_K * W), i = rem / W, w = rem - i * W;
-            if (i < k) lrow_buf[t] = reinterpret_cast<const uint4 *>(rows + (size_t)(jj * BZ_MAX_K + i) * ROW_WORDS)[w];
-        }
-        lrows = lrow_buf;  // (read after the barrier below)
-    }
+    if constexpr (P == 3) lrows = lrow_buf;  // (filled before the first barrier)
     // the pool (see pool_stages): its stages complete when all their tiles
     // are done, so their part count in this workgroup's copy is the tile count
     u64 pool_tiles;
