@@ -400,9 +400,10 @@ def test_runs_of_bases(bz, oracle):
     """F_3 rounds whose stages give every workgroup a tile take runs of bases
     (one decoding per lane, a Gray-code walk over the low coefficient digits).
     With one workgroup per CU (256 workgroups), k = 17 takes runs from round 10
-    and k = 18 from round 9; with six per CU, k = 18 only from round 12.  The
-    full weight distribution of every stage equals the oracle's (k = 17) or
-    the other grid's (k = 18, where rounds 9-11 run with and without runs)."""
+    and k = 18 from round 9; with five per CU (1280), k = 18 only from round
+    11.  The full weight distribution of every stage equals the oracle's
+    (k = 17) or the other grid's (k = 18, where rounds 9-10 run with and
+    without runs)."""
     from math import comb
     G = synth.random_generator(3, 34, 17, 0, stream=800)
     r = run_both(bz, oracle, 3, G, "runs of bases k=17", hist=True, no_termination=True, blocks_per_cu=1)
