@@ -1227,7 +1227,9 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
     // this workgroup's results for stage s: a workgroup reduction, then one set
     // of atomics; `add` counts towards the stage's parts (the workgroup that
     // completes them checks the stage and every done stage after it)
-    auto flush_stage = [&](int s, u32 lmin, u64 lcnt, uint32_t add) {
+    // next >= 0: wavefront 1 builds the q-groups of stage next meanwhile (the
+    // workgroup moves on to it)
+    auto flush_stage = [&](int s, u32 lmin, u64 lcnt, uint32_t add, int next) {
         const StageDesc &sd = sdesc[s];
         const u32 woff = skip ? (u32)uni(sd.g) : 0u;
         for (int off = 32; off >= 1; off >>= 1) {
@@ -1261,6 +1263,9 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
                 if (tracing && lane == 0)
                     atomicMax((unsigned long long *)&cs->trace[2 + s][2], (unsigned long long)wall_clock64());
             }
+        } else if (wid == 1 && next >= 0 && sdesc[next].g > SUBSET_G) {
+            const StageDesc &nd = sdesc[next];
+            wave_qtable(P, k, nd.g, nd.coef_combos, nd.sweep_cap, nd.vcap, sbin, gbin, qtab);
         }
         __syncthreads();  // qtab and red_* are rewritten next
     };
@@ -1282,9 +1287,13 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
         u64 u = (u64)b < pool_tiles ? (u64)b : ~0ull;
         int t2 = -1;
         for (uint32_t it = 0;; it++) {
+            // the next claim and the progress word, read while the tile runs
             uint32_t ci = 0;
-            if (threadIdx.x == 0 && u != ~0ull)
+            u64 wk = 0;
+            if (threadIdx.x == 0 && u != ~0ull) {
                 ci = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                wk = ld_poll(wake);
+            }
             int sn = ps < 0 ? 0 : ps;
             bool end = u == ~0ull;
             if (!end) {
@@ -1294,31 +1303,33 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
                 end = t2 >= 0 && sn > t2;
             }
             if (ps >= 0 && (end || sn != ps)) {
-                flush_stage(ps, lmin, lcnt, pheld);
+                flush_stage(ps, lmin, lcnt, pheld, end ? -1 : sn);  // (with the q-groups of sn)
                 lmin = BIG;
                 lcnt = 0;
                 pheld = 0;
+            } else if (!end && sn != ps) {
+                // the first stage of this workgroup
+                const StageDesc &sd = sdesc[sn];
+                if (wid == 0 && sd.g > SUBSET_G)
+                    wave_qtable(P, k, sd.g, sd.coef_combos, sd.sweep_cap, sd.vcap, sbin, gbin, qtab);
+                __syncthreads();
             }
             if (end) break;
             if (sn != ps) {
                 ps = sn;
                 pbase = nowait_offset(uni(sdesc[sn].rot), grid);
-                const StageDesc &sd = sdesc[sn];
-                if (wid == 0 && sd.g > SUBSET_G)
-                    wave_qtable(P, k, sd.g, sd.coef_combos, sd.sweep_cap, sd.vcap, sbin, gbin, qtab);
                 if (tr_wg && threadIdx.x == 0) {
                     const unsigned long long now = (unsigned long long)wall_clock64();
                     atomicMin((unsigned long long *)&cs->trace[2 + sn][0], now);
                     atomicMax((unsigned long long *)&cs->trace[2 + sn][3], now);
                 }
-                __syncthreads();
             }
             run_tile(sdesc[ps], ps, u - pbase, lmin, lcnt);
             pheld++;
             if (threadIdx.x == 0) {
                 const u64 nu = (u64)grid + pool_tile(slice, ci, C);
                 s_claim[it & 1] = nu < pool_tiles ? nu : ~0ull;
-                s_cterm[it & 1] = wake_term(ld_poll(wake));
+                s_cterm[it & 1] = wake_term(wk);
             }
             __syncthreads();  // (double buffers: the pair written two rounds ago was read before the last barrier)
             u = uni64(s_claim[it & 1]);
@@ -1395,7 +1406,7 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
             }
             run_tile(sd, s, tile, lmin, lcnt);
         }
-        flush_stage(s, lmin, lcnt, 1u);
+        flush_stage(s, lmin, lcnt, 1u, -1);
     }
     if (tr_wg && threadIdx.x == 0) atomicMax((unsigned long long *)&cs->trace[1][1], (unsigned long long)wall_clock64());
 }
