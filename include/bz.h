@@ -9,7 +9,10 @@
  * matrices Gamma_j, the bit-sliced packing in the natural encoding (Sec. 2 and
  * 4.1), the enumeration of all g-row combinations with the lowest coefficient
  * fixed to 1 (Sec. 4.2), exact prefix sums with the F_3 / F_7 additions of
- * Algorithms 3 and 4, the isometric last addition (Sec. 4.3), the popcount
+ * Algorithms 3 and 4 (for the rounds g >= 5 of the batched calls and of F_7
+ * plain calls, the sums of the two highest rows of a combination come from
+ * a per-set table of all row pairs that the decomposition builds), the
+ * isometric last addition (Sec. 4.3), the popcount
  * weight, the min-reduce against the upper bound U, and the stage-by-stage
  * lower-bound test with early termination (Sec. 4.4).
  *
@@ -236,7 +239,9 @@ void bz_default_batch_options(bz_batch_options *o);
  * RANK, LIMIT).  Returns BZ_OK when the batch ran, BZ_ERR_ARG for an invalid
  * batch or code descriptor (nothing runs), BZ_ERR_NOMEM, or BZ_ERR_DEVICE.
  * The library keeps a batch workspace per device that grows to the largest
- * batch seen (about 28 KB per code plus the packed rows). */
+ * batch seen (about 28 KB per code plus the packed rows and the pair tables:
+ * (n/k + 1) k(k-1)/2 W 16 bytes per code for F_3, six times that for F_7,
+ * W = ceil((n-k)/32) with the identity skip, else ceil(n/32)). */
 int bz_min_distance_batch(int ncodes, const bz_code *codes, const uint8_t *G, uint64_t g_bytes, int G_is_device,
                           bz_batch_options *o, bz_result *out, int32_t *status_out);
 

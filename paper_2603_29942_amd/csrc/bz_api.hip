@@ -39,6 +39,7 @@ struct DevCtx {
     uint8_t *g_buf = nullptr;
     CodeState *cs = nullptr;
     u32 *rows = nullptr;
+    uint4 *pairs = nullptr;  // the pair tables of the sets (pair_table_units per set)
     u64 *binom = nullptr;
     u64 *hist = nullptr;
     CodeResult *host_res = nullptr;
@@ -51,11 +52,12 @@ struct DevCtx {
     u64 (*host_trace)[4] = nullptr;
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     // batch workspace, grown on demand and kept
-    size_t b_codes_cap = 0, b_rows_cap = 0, b_g_cap = 0;
+    size_t b_codes_cap = 0, b_rows_cap = 0, b_g_cap = 0, b_pairs_cap = 0;
     CodeState *b_cs = nullptr;
     u64 *b_claims = nullptr;  // the codes' claim words, contiguous
     BatchCode *b_codes = nullptr;
     u32 *b_rows = nullptr;
+    uint4 *b_pairs = nullptr;
     uint8_t *b_g = nullptr;
     BatchState *b_state = nullptr;
     CodeResult *b_host_res = nullptr;
@@ -98,6 +100,29 @@ const u64 *host_binom() {
         if ((expr) != hipSuccess) return BZ_ERR_DEVICE; \
     } while (0)
 
+// 16-byte units of the pair tables of one code: every set it can produce
+// (slots 0 .. pair_sets - 1), plus, on the plain path, the slot pair_sets
+// that the workgroup computing the second set ahead builds its table in
+u64 code_pair_units(int p, int n, int k, int W, bool ahead_slot) {
+    return (u64)(pair_sets(n, k) + (ahead_slot ? 1 : 0)) * pair_table_units(p, k, W);
+}
+
+// the largest plain-path code_pair_units of any code the library accepts (p =
+// 7 has the larger tables; W as the enumeration takes it, with or without the
+// identity skip)
+u64 max_pair_units() {
+    u64 best = 0;
+    for (int n = 1; n <= BZ_MAX_N; n++)
+        for (int k = 1; k <= n && k <= BZ_MAX_K; k++) {
+            const int WF = (n + 31) / 32, Ws = (n - k + 31) / 32;
+            for (int W : {WF, Ws < 1 ? 1 : Ws}) {
+                const u64 u = code_pair_units(7, n, k, W, true);
+                if (u > best) best = u;
+            }
+        }
+    return best;
+}
+
 int init_ctx(int dev) {
     DevCtx &c = g_ctx[dev];
     if (c.ready) return BZ_OK;
@@ -117,6 +142,7 @@ int init_ctx(int dev) {
     if (hipMalloc(&c.g_buf, (size_t)BZ_MAX_K * BZ_MAX_N) != hipSuccess) return BZ_ERR_NOMEM;
     if (hipMalloc(&c.cs, sizeof(CodeState)) != hipSuccess) return BZ_ERR_NOMEM;
     if (hipMalloc(&c.rows, sizeof(u32) * BZ_MAX_M * BZ_MAX_K * ROW_WORDS) != hipSuccess) return BZ_ERR_NOMEM;
+    if (hipMalloc(&c.pairs, sizeof(uint4) * max_pair_units()) != hipSuccess) return BZ_ERR_NOMEM;
     if (hipMalloc(&c.binom, sizeof(u64) * 65 * 65) != hipSuccess) return BZ_ERR_NOMEM;
     if (hipMalloc(&c.hist, sizeof(u64) * BZ_MAX_STAGES * (BZ_MAX_N + 1)) != hipSuccess) return BZ_ERR_NOMEM;
     if (hipMalloc(&c.spec, sizeof(SpecBuf)) != hipSuccess) return BZ_ERR_NOMEM;
@@ -151,9 +177,9 @@ void release_ctx(DevCtx &c) {
     if (c.have_last && c.done_ev) (void)hipEventSynchronize(c.done_ev);
     for (auto &kv : c.rounds) (void)hipFree(kv.second);
     c.rounds.clear();
-    for (void *p : {(void *)c.g_buf, (void *)c.cs, (void *)c.rows, (void *)c.binom, (void *)c.hist, (void *)c.spec,
-                    (void *)c.b_cs, (void *)c.b_claims, (void *)c.b_codes, (void *)c.b_rows, (void *)c.b_g,
-                    (void *)c.b_state})
+    for (void *p : {(void *)c.g_buf, (void *)c.cs, (void *)c.rows, (void *)c.pairs, (void *)c.binom, (void *)c.hist,
+                    (void *)c.spec, (void *)c.b_cs, (void *)c.b_claims, (void *)c.b_codes, (void *)c.b_rows,
+                    (void *)c.b_pairs, (void *)c.b_g, (void *)c.b_state})
         if (p) (void)hipFree(p);
     for (void *p : {(void *)c.host_res, (void *)c.host_hist, (void *)c.host_trace, (void *)c.res_map,
                     (void *)c.flag_map, (void *)c.b_host_res, (void *)c.b_host_state})
@@ -165,6 +191,7 @@ void release_ctx(DevCtx &c) {
     c.g_buf = nullptr;
     c.cs = nullptr;
     c.rows = nullptr;
+    c.pairs = nullptr;
     c.binom = nullptr;
     c.hist = nullptr;
     c.spec = nullptr;
@@ -172,6 +199,7 @@ void release_ctx(DevCtx &c) {
     c.b_claims = nullptr;
     c.b_codes = nullptr;
     c.b_rows = nullptr;
+    c.b_pairs = nullptr;
     c.b_g = nullptr;
     c.b_state = nullptr;
     c.host_res = nullptr;
@@ -181,7 +209,7 @@ void release_ctx(DevCtx &c) {
     c.flag_map = c.flag_map_dev = nullptr;
     c.b_host_res = nullptr;
     c.b_host_state = nullptr;
-    c.b_codes_cap = c.b_rows_cap = c.b_g_cap = 0;
+    c.b_codes_cap = c.b_rows_cap = c.b_g_cap = c.b_pairs_cap = 0;
     for (auto &e : c.ev) e = nullptr;
     c.done_ev = nullptr;
     c.stream = nullptr;
@@ -208,7 +236,9 @@ __global__ void zero_u64(u64 *p, size_t n) {
 template <int P>
 hipError_t launch_decompose(int WF, const uint8_t *G, CodeState *cs, u32 *rows, RunArgs a,
                             hipStream_t s) {
-    const int nb = a.spec ? 2 : 1;  // workgroup 1 computes the second information set ahead
+    // workgroup 1 computes the second information set ahead; one more builds
+    // the first set's pair table (see ROLE_TABLE0)
+    const int nb = 1 + (a.spec ? 1 : 0) + (a.pairs && a.pair_t0 ? 1 : 0);
     switch (WF) {
     case 1: decompose_kernel<P, 1><<<nb, 64, 0, s>>>(G, cs, rows, a); break;
     case 2: decompose_kernel<P, 2><<<nb, 64, 0, s>>>(G, cs, rows, a); break;
@@ -223,28 +253,28 @@ hipError_t launch_decompose(int WF, const uint8_t *G, CodeState *cs, u32 *rows, 
 // its waits for earlier stages rely on (plain calls hold the device's server
 // rounds off while they run).
 template <int P, int W, bool H>
-hipError_t launch_enum_one(int grid, CodeState *cs, const u32 *rows, const u64 *binom, u64 *hist, EnumArgs ea,
-                           hipStream_t s) {
-    enum_kernel<P, W, H><<<grid, 256, 0, s>>>(cs, rows, binom, hist, ea);
+hipError_t launch_enum_one(int grid, CodeState *cs, const u32 *rows, const uint4 *pairs, const u64 *binom, u64 *hist,
+                           EnumArgs ea, hipStream_t s) {
+    enum_kernel<P, W, H><<<grid, 256, 0, s>>>(cs, rows, pairs, binom, hist, ea);
     return hipGetLastError();
 }
 
 template <int P, bool H>
-hipError_t launch_enum_h(int W, int grid, CodeState *cs, const u32 *rows, const u64 *binom, u64 *hist, EnumArgs ea,
-                         hipStream_t s) {
+hipError_t launch_enum_h(int W, int grid, CodeState *cs, const u32 *rows, const uint4 *pairs, const u64 *binom,
+                         u64 *hist, EnumArgs ea, hipStream_t s) {
     switch (W) {
-    case 1: return launch_enum_one<P, 1, H>(grid, cs, rows, binom, hist, ea, s);
-    case 2: return launch_enum_one<P, 2, H>(grid, cs, rows, binom, hist, ea, s);
-    case 3: return launch_enum_one<P, 3, H>(grid, cs, rows, binom, hist, ea, s);
-    default: return launch_enum_one<P, 4, H>(grid, cs, rows, binom, hist, ea, s);
+    case 1: return launch_enum_one<P, 1, H>(grid, cs, rows, pairs, binom, hist, ea, s);
+    case 2: return launch_enum_one<P, 2, H>(grid, cs, rows, pairs, binom, hist, ea, s);
+    case 3: return launch_enum_one<P, 3, H>(grid, cs, rows, pairs, binom, hist, ea, s);
+    default: return launch_enum_one<P, 4, H>(grid, cs, rows, pairs, binom, hist, ea, s);
     }
 }
 
 template <int P>
-hipError_t launch_enum(bool hist_mode, int W, int grid, CodeState *cs, const u32 *rows, const u64 *binom, u64 *hist,
-                       EnumArgs ea, hipStream_t s) {
-    return hist_mode ? launch_enum_h<P, true>(W, grid, cs, rows, binom, hist, ea, s)
-                     : launch_enum_h<P, false>(W, grid, cs, rows, binom, hist, ea, s);
+hipError_t launch_enum(bool hist_mode, int W, int grid, CodeState *cs, const u32 *rows, const uint4 *pairs,
+                       const u64 *binom, u64 *hist, EnumArgs ea, hipStream_t s) {
+    return hist_mode ? launch_enum_h<P, true>(W, grid, cs, rows, pairs, binom, hist, ea, s)
+                     : launch_enum_h<P, false>(W, grid, cs, rows, pairs, binom, hist, ea, s);
 }
 
 // Largest grid the enumeration kernel may get for (p, W, histograms): the
@@ -383,7 +413,7 @@ u64 batch_row_words(int n, int k) {
     return (u64)m * 64 * ROW_WORDS;
 }
 
-int grow_batch(DevCtx &c, size_t ncodes, size_t row_words, size_t g_bytes) {
+int grow_batch(DevCtx &c, size_t ncodes, size_t row_words, size_t pair_units, size_t g_bytes) {
     if (ncodes > c.b_codes_cap) {
         // (errors of the frees are not actionable here; every pointer is reset so
         // that a failed allocation below leaves nothing to free twice)
@@ -409,6 +439,13 @@ int grow_batch(DevCtx &c, size_t ncodes, size_t row_words, size_t g_bytes) {
         c.b_rows_cap = 0;
         if (hipMalloc(&c.b_rows, sizeof(u32) * row_words) != hipSuccess) return BZ_ERR_NOMEM;
         c.b_rows_cap = row_words;
+    }
+    if (pair_units > c.b_pairs_cap) {
+        if (c.b_pairs) (void)hipFree(c.b_pairs);
+        c.b_pairs = nullptr;
+        c.b_pairs_cap = 0;
+        if (hipMalloc(&c.b_pairs, sizeof(uint4) * pair_units) != hipSuccess) return BZ_ERR_NOMEM;
+        c.b_pairs_cap = pair_units;
     }
     if (g_bytes > c.b_g_cap) {
         if (c.b_g) (void)hipFree(c.b_g);
@@ -529,6 +566,12 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, c
     a.spec = o.no_ahead ? nullptr : c->spec;
     a.epoch = c->spec_epoch;
     a.pad = 0;
+    // pair tables for F_7 only: the plain F_3 runs measured no faster with
+    // them (their enumeration is bound by latency, not by the prefixes)
+    a.pairs = p == 7 ? c->pairs : nullptr;
+    a.pair_stride = (uint32_t)pair_table_units(p, k, W);
+    a.pair_w = W;
+    a.pair_t0 = 1;  // a workgroup of the decomposition launch of its own builds set 0's table
     if (o.timing) HIP_OK(hipEventRecord(c->ev[0], s));
     HIP_OK(p == 3 ? launch_decompose<3>(WF, Gd, c->cs, c->rows, a, s)
                   : launch_decompose<7>(WF, Gd, c->cs, c->rows, a, s));
@@ -546,15 +589,15 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, c
     ea.res_out = nullptr;
     ea.flag_out = nullptr;
     ea.epoch = 0;
-    ea.pad = 0;
+    ea.pair_stride = a.pair_stride;
     if (mapped) {
         if (++c->epoch == 0) c->epoch = 1;
         ea.res_out = c->res_map_dev;
         ea.flag_out = c->flag_map_dev;
         ea.epoch = c->epoch;
     }
-    HIP_OK(p == 3 ? launch_enum<3>(o.histograms != 0, W, grid, c->cs, c->rows, c->binom, c->hist, ea, s)
-                  : launch_enum<7>(o.histograms != 0, W, grid, c->cs, c->rows, c->binom, c->hist, ea, s));
+    HIP_OK(p == 3 ? launch_enum<3>(o.histograms != 0, W, grid, c->cs, c->rows, a.pairs, c->binom, c->hist, ea, s)
+                  : launch_enum<7>(o.histograms != 0, W, grid, c->cs, c->rows, a.pairs, c->binom, c->hist, ea, s));
     if (o.timing) HIP_OK(hipEventRecord(c->ev[2], s));
     HIP_OK(hipEventRecord(c->done_ev, s));
     c->last_stream = s;
@@ -648,7 +691,7 @@ int bz_min_distance_batch(int ncodes, const bz_code *codes, const uint8_t *G, ui
     const u64 max_cw = o.max_codewords ? o.max_codewords : DEFAULT_LIMIT;
     // validate every code and lay out its rows
     std::vector<BatchCode> bc((size_t)ncodes);
-    u64 row_words = 0;
+    u64 row_words = 0, pair_units = 0;
     int wmax = 1;
     for (int i = 0; i < ncodes; i++) {
         const bz_code &cd = codes[i];
@@ -667,8 +710,11 @@ int bz_min_distance_batch(int ncodes, const bz_code *codes, const uint8_t *G, ui
         b.W = o.identity_skip ? (cd.n - cd.k + 31) / 32 : b.WF;
         if (b.W < 1) b.W = 1;
         b.sweep_ops = cd.sweep_ops > 0 ? (uint32_t)cd.sweep_ops : DEFAULT_SWEEP_OPS;
+        b.pair_stride = (uint32_t)pair_table_units(cd.p, cd.k, b.W);
+        b.pair_offset = pair_units;
         if (b.W > wmax) wmax = b.W;
         row_words += batch_row_words(cd.n, cd.k);
+        pair_units += code_pair_units(cd.p, cd.n, cd.k, b.W, false);
     }
     DevCtx *c = nullptr;
     int st = get_ctx(o.device, &c);
@@ -676,7 +722,7 @@ int bz_min_distance_batch(int ncodes, const bz_code *codes, const uint8_t *G, ui
     std::lock_guard<std::mutex> lk(c->mu);
     HIP_OK(hipSetDevice(o.device));
     hipStream_t s = o.hip_stream ? (hipStream_t)o.hip_stream : c->stream;
-    st = grow_batch(*c, (size_t)ncodes, (size_t)row_words, G_is_device ? 0 : (size_t)g_bytes);
+    st = grow_batch(*c, (size_t)ncodes, (size_t)row_words, (size_t)pair_units, G_is_device ? 0 : (size_t)g_bytes);
     if (st != BZ_OK) return st;
     const int bpc = o.blocks_per_cu ? o.blocks_per_cu : 4;
     const int grid = batch_grid(wmax, c->cu, bpc);
@@ -691,8 +737,8 @@ int bz_min_distance_batch(int ncodes, const bz_code *codes, const uint8_t *G, ui
     zero_batch_state<<<1, 1, 0, s>>>(c->b_state);
     HIP_OK(hipGetLastError());
     if (o.timing) HIP_OK(hipEventRecord(c->ev[0], s));
-    decompose_batch_kernel<<<ncodes, 64, 0, s>>>(Gd, c->b_codes, c->b_cs, c->b_claims, c->b_rows, (uint32_t)grid,
-                                                c->b_state, nullptr, nullptr, nullptr);
+    decompose_batch_kernel<<<ncodes, 64, 0, s>>>(Gd, c->b_codes, c->b_cs, c->b_claims, c->b_rows, c->b_pairs,
+                                                (uint32_t)grid, c->b_state, nullptr, nullptr, nullptr);
     HIP_OK(hipGetLastError());
     if (o.timing) HIP_OK(hipEventRecord(c->ev[1], s));
     {
@@ -701,6 +747,7 @@ int bz_min_distance_batch(int ncodes, const bz_code *codes, const uint8_t *G, ui
         const BatchCode *cds = c->b_codes;
         int nc = ncodes;
         const u32 *rows = c->b_rows;
+        const uint4 *prs = c->b_pairs;
         const u64 *bin = c->binom;
         BatchState *bs = c->b_state;
         u64 to = timeout;
@@ -708,7 +755,7 @@ int bz_min_distance_batch(int ncodes, const bz_code *codes, const uint8_t *G, ui
         const uint32_t *yield = nullptr;
         uint32_t *done = nullptr;
         CodeResult *resm = nullptr;
-        void *args[] = {&css, &clm, &cds, &nc, &rows, &bin, &bs, &to, &order, &yield, &done, &resm};
+        void *args[] = {&css, &clm, &cds, &nc, &rows, &prs, &bin, &bs, &to, &order, &yield, &done, &resm};
         const void *fn = wmax <= 2 ? (const void *)enum_batch_kernel<2> : (const void *)enum_batch_kernel<4>;
         HIP_OK(hipLaunchKernel(fn, dim3(grid), dim3(256), args, 0, s));
     }
@@ -974,9 +1021,9 @@ extern "C" int bz_min_distance_noalloc(int p, int n, int k, const uint8_t *G, co
     ea.res_out = nullptr;
     ea.flag_out = nullptr;
     ea.epoch = 0;
-    ea.pad = 0;
-    HIP_OK(p == 3 ? launch_enum<3>(false, W, grid, &ws->cs, ws->rows, ws->binom, nullptr, ea, s)
-                  : launch_enum<7>(false, W, grid, &ws->cs, ws->rows, ws->binom, nullptr, ea, s));
+    ea.pair_stride = 0;
+    HIP_OK(p == 3 ? launch_enum<3>(false, W, grid, &ws->cs, ws->rows, nullptr, ws->binom, nullptr, ea, s)
+                  : launch_enum<7>(false, W, grid, &ws->cs, ws->rows, nullptr, ws->binom, nullptr, ea, s));
     CodeResult r;
     HIP_OK(hipMemcpyAsync(&r, &ws->cs.res, sizeof r, hipMemcpyDeviceToHost, s));
     HIP_OK(hipStreamSynchronize(s));
@@ -1110,6 +1157,7 @@ hipError_t server_launch(bz_server *s, int nactive) {
     const BatchCode *cds = s->codes;
     int nc = nactive;
     const u32 *rows = s->rows;
+    const uint4 *prs = nullptr;  // no pair tables: the lanes build their prefixes
     const u64 *bin = s->c->binom;
     BatchState *bs = s->bs;
     u64 to = s->timeout;
@@ -1117,7 +1165,7 @@ hipError_t server_launch(bz_server *s, int nactive) {
     const uint32_t *yield = s->yield_dev;
     uint32_t *done = s->done_dev;
     CodeResult *resm = s->res_dev;
-    void *args[] = {&css, &clm, &cds, &nc, &rows, &bin, &bs, &to, &order, &yield, &done, &resm};
+    void *args[] = {&css, &clm, &cds, &nc, &rows, &prs, &bin, &bs, &to, &order, &yield, &done, &resm};
     return hipLaunchKernel((const void *)enum_batch_kernel<WMAX>, dim3(s->grid), dim3(256), args, 0, s->run);
 }
 
@@ -1199,6 +1247,8 @@ int server_round(bz_server *s) {
         b.W = s->o.identity_skip ? (r.n - r.k + 31) / 32 : b.WF;
         if (b.W < 1) b.W = 1;
         b.sweep_ops = DEFAULT_SWEEP_OPS;
+        b.pair_stride = 0;
+        b.pair_offset = ~0ull;
         s->new_h[fresh.size()] = i;
         fresh.push_back(i);
     }
@@ -1210,7 +1260,7 @@ int server_round(bz_server *s) {
         HIP_OK(hipMemcpyAsync(s->codes, s->codes_h, sizeof(BatchCode) * (size_t)s->slots, hipMemcpyHostToDevice,
                               s->run));
         HIP_OK(hipMemcpyAsync(s->new_d, s->new_h, sizeof(int32_t) * (size_t)nf, hipMemcpyHostToDevice, s->run));
-        decompose_batch_kernel<<<nf, 64, 0, s->run>>>(s->g, s->codes, s->cs, s->claims, s->rows,
+        decompose_batch_kernel<<<nf, 64, 0, s->run>>>(s->g, s->codes, s->cs, s->claims, s->rows, nullptr,
                                                       (uint32_t)s->decomp_grid, s->bs, s->new_d, s->done_dev,
                                                       s->res_dev);
         HIP_OK(hipGetLastError());

@@ -3,13 +3,15 @@
 //   decompose_kernel  one wavefront per code: validates G, packs it into bit
 //                     planes, computes the information-set decomposition
 //                     Gamma_1..Gamma_m by Gauss-Jordan on bit-sliced rows (one
-//                     row per lane), packs each Gamma_j for the enumeration, and
+//                     row per lane), packs each Gamma_j for the enumeration
+//                     (with its table of pair sums, see pair_units), and
 //                     writes the stage schedule and the initial completion state.
 //   enum_kernel       persistent: every workgroup walks the stages in order and
 //                     takes its share of each stage's tiles; a lane builds the
-//                     exact prefix sums of its item in registers, finishes every
-//                     combination with the isometric addition, takes the weight
-//                     by popcount and min-reduces it.  The workgroup that
+//                     exact prefix sums of its item in registers (the two
+//                     highest rows from the pair table when there is one),
+//                     finishes every combination with the isometric addition,
+//                     takes the weight by popcount and min-reduces it.  The workgroup that
 //                     completes a stage last applies the L >= U test; workgroups
 //                     that already moved on to later stages stop when it holds.
 //
@@ -69,7 +71,8 @@ struct EnumArgs {
     // memory) and then stores epoch to *flag_out
     CodeResult *res_out;
     uint32_t *flag_out;
-    uint32_t epoch, pad;
+    uint32_t epoch;
+    uint32_t pair_stride;  // 16-byte units between the pair tables of two sets (with a table)
 };
 
 // A code's result block to mapped host memory by one whole wavefront:
@@ -100,7 +103,21 @@ struct RunArgs {
     const RoundTable *rounds;  // the rounds' task counts for this shape, or NULL: counted here
     SpecBuf *spec;             // the second information set computed ahead, or NULL
     uint32_t epoch, pad;       // this call's value of spec->flag
+    // the pair table of set j at pairs + j * pair_stride (16-byte units), for
+    // pair_w words per plane; NULL: no tables (the enumeration then builds
+    // its prefixes itself)
+    uint4 *pairs = nullptr;
+    uint32_t pair_stride = 0;
+    int32_t pair_w = 0;
+    int32_t pair_t0 = 0;  // 1: a workgroup of its own builds the first set's table (ROLE_TABLE0)
 };
+
+// Workgroups of a decomposition launch: the one that decomposes the code
+// (MAIN); on the plain path also one that computes the second information set
+// ahead (AHEAD, see SpecBuf) and builds its pair table in a slot of its own,
+// and one that repeats the first set's elimination only to build its pair
+// table (TABLE0), so that neither table lengthens the main workgroup's path.
+enum { ROLE_MAIN = 0, ROLE_AHEAD = 1, ROLE_TABLE0 = 2 };
 
 // q-groups of a stage with g >= 3 computed by the 64 lanes of a wavefront
 // (lane = q - (g-3)); the same values as fill_qtable.  Returns the number of
@@ -152,7 +169,42 @@ struct DecompLDS {
     uint32_t s_combos[BZ_MAX_K];
     uint32_t s_nb[BZ_MAX_K];  // blocks of rows s of the q-group with top row q, at [q]
     uint32_t s_dt[BZ_MAX_K];  // digits_by_steps of the q-group with top row q, at [q]
+    uint4 prow[BZ_MAX_K * 4];  // the packed rows of the set whose pair table is built, row i word w at [i * 4 + w]
 };
+
+// The pair table of one information set (see pair_units) from its packed rows
+// in LDS, lane t taking the pairs t, t + 64, ...  Plain stores: the
+// enumeration reads the table in a later launch.
+template <int P>
+__device__ void build_pair_table(uint4 *__restrict__ ptab, int k, int W, const uint4 *prow) {
+    const int lane = threadIdx.x;
+    const int np = k * (k - 1) / 2;
+    // (s, rem): pair e is (s, s + 1 + rem); advanced by 64 pairs per step
+    int s = 0, rem = 0;
+    pair_advance(k, s, rem, lane);
+    for (int e = lane; e < np; e += 64) {
+        const int L = s + 1 + rem;
+        for (int w = 0; w < W; w++) {
+            const uint4 a = prow[s * 4 + w], b = prow[L * 4 + w];
+            if constexpr (P == 3) {
+                u32 t0, t1, u0, u1;
+                f3_add(a.x, a.y, b.x, b.y, t0, t1);  // R_s + R_L
+                f3_add(a.x, a.y, b.y, b.x, u0, u1);  // R_s - R_L (= R_s + 2 R_L: planes swapped)
+                ptab[(size_t)e * W + w] = make_uint4(t0, t1, u0, u1);
+            } else {
+                const u32 bl[3] = {b.x, b.y, b.z};
+#pragma unroll
+                for (int c = 1; c < 7; c++) {
+                    u32 sc[3], t[3];
+                    scale<7>(c, bl, sc);
+                    f7_add(a.x, a.y, a.z, sc[0], sc[1], sc[2], t[0], t[1], t[2]);
+                    ptab[((size_t)e * 6 + (c - 1)) * W + w] = make_uint4(t[0], t[1], t[2], t[0] | t[1] | t[2]);
+                }
+            }
+        }
+        pair_advance(k, s, rem, 64);
+    }
+}
 
 // One Gauss-Jordan step on the rows held one per lane: row pl (pivot value
 // pv in the pivot column) becomes pv^-1 times itself, every other row i
@@ -220,13 +272,15 @@ struct RoundPrefetch {
 };
 
 // One code on one wavefront (threads 0..63 of the workgroup).
-// ahead = true: the second workgroup of the plain path (see SpecBuf): the
-// elimination of one set with the columns 0 .. k-1 taken as used, packed into
-// args.spec, and nothing else.
+// role ROLE_AHEAD: the elimination of one set with the columns 0 .. k-1 taken
+// as used, packed into args.spec, then (with tables) its pair table in slot
+// pair_sets(n, k), and nothing else.  ROLE_TABLE0: the first set's
+// elimination and its pair table in slot 0, and nothing else.
 template <int P, int WF>
 __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32 *__restrict__ rows,
-                               const RunArgs args, DecompLDS &lds, bool ahead = false,
+                               const RunArgs args, DecompLDS &lds, int role = ROLE_MAIN,
                                RoundPrefetch pre = RoundPrefetch()) {
+    const bool ahead = role == ROLE_AHEAD, main_wg = role == ROLE_MAIN;
     constexpr int R = (P == 3) ? 2 : 3;
     u64 *binom = lds.binom;
     int32_t *sranks = lds.sranks;
@@ -235,19 +289,24 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
     // to scalars so that everything derived from them is wave-uniform
     const int n = uni(args.n), k = uni(args.k), flags = uni(args.flags);
     CodeResult &res = cs->res;
-    const bool tracing = !ahead && (flags & FLAG_TRACE) != 0;
+    const bool tracing = main_wg && (flags & FLAG_TRACE) != 0;
     const u64 t_start = tracing ? (u64)wall_clock64() : 0;
     SpecBuf *spec = args.spec;
+    uint4 *const pairs = args.pairs;
+    const int pair_w = uni(args.pair_w);
+    const uint32_t pair_stride = uni(args.pair_stride);
+    const bool t0_elsewhere = uni(args.pair_t0) != 0;
     const bool have_rt = pre.have;
     const u64 rt_tasks = pre.tasks;
     const uint32_t rt_vcap = pre.vcap;
     const int rt_cut = pre.cut;
-    if (lane == 0 && !ahead) {
+    if (lane == 0 && main_wg) {
         cs->p = P;
         cs->n = n;
         cs->k = k;
         cs->flags = flags;
         cs->U0 = args.U0;
+        cs->pair_slot1 = 1;
         cs->max_codewords = args.max_codewords;
     }
 
@@ -349,7 +408,7 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
             anyu |= unused[w] != 0;
         }
         if (!anyu) break;
-        if (!ahead && spec != nullptr && m == 1 && first_is_firstk) {
+        if (main_wg && spec != nullptr && m == 1 && first_is_firstk) {
             // the second set from the workgroup that computed it ahead, when it
             // has finished (a bounded wait; else it is computed here)
             u32 f = 0;
@@ -368,6 +427,8 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
                         drow[w] = __hip_atomic_load(const_cast<u32 *>(srow + w), __ATOMIC_RELAXED,
                                                     __HIP_MEMORY_SCOPE_AGENT);
                 }
+                // its pair table is built by that workgroup, in slot pair_sets(n, k)
+                if (lane == 0 && pairs != nullptr) cs->pair_slot1 = pair_sets(n, k);
 #pragma unroll
                 for (int w = 0; w < 4; w++) {
                     const u32 pm = uni(__hip_atomic_load(&spec->pivmask[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
@@ -469,13 +530,34 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
 #pragma unroll
                     for (int w = 0; w < 4; w++) out[b][w] = (w < WF) ? x[b][w] : 0u;
             }
+            if (role != ROLE_TABLE0) {
 #pragma unroll
-            for (int w = 0; w < 4; w++) {
-                dst[w * 4 + 0] = out[0][w];
-                dst[w * 4 + 1] = out[1][w];
-                dst[w * 4 + 2] = out[2][w];
-                dst[w * 4 + 3] = out[0][w] | out[1][w] | out[2][w];
+                for (int w = 0; w < 4; w++) {
+                    dst[w * 4 + 0] = out[0][w];
+                    dst[w * 4 + 1] = out[1][w];
+                    dst[w * 4 + 2] = out[2][w];
+                    dst[w * 4 + 3] = out[0][w] | out[1][w] | out[2][w];
+                }
             }
+            if (pairs != nullptr) {
+#pragma unroll
+                for (int w = 0; w < 4; w++)
+                    lds.prow[piv_lane * 4 + w] =
+                        make_uint4(out[0][w], out[1][w], out[2][w], out[0][w] | out[1][w] | out[2][w]);
+            }
+        }
+        if (role == ROLE_TABLE0) {
+            if (pairs != nullptr) {
+                __syncthreads();
+                build_pair_table<P>(pairs, k, pair_w, lds.prow);
+            }
+            return;
+        }
+        // (m < pair_sets(n, k) always holds, see pair_sets)
+        if (main_wg && pairs != nullptr && m < pair_sets(n, k) && !(m == 0 && t0_elsewhere)) {
+            __syncthreads();
+            build_pair_table<P>(pairs + (size_t)m * pair_stride, k, pair_w, lds.prow);
+            __syncthreads();
         }
         if (ahead) {
             // publish: the rows and the set's description, then the flag
@@ -487,6 +569,10 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
             }
             __threadfence();
             if (lane == 0) __hip_atomic_store(&spec->flag, args.epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (pairs != nullptr) {
+                __syncthreads();
+                build_pair_table<P>(pairs + (size_t)pair_sets(n, k) * pair_stride, k, pair_w, lds.prow);
+            }
             return;
         }
         if (lane == 0) sranks[m] = kj;
@@ -495,6 +581,7 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
         for (int w = 0; w < 4; w++) used[w] |= pivmask[w] & unused[w];
         if (kj < k || m == BZ_MAX_M) break;
     }
+    if (role == ROLE_TABLE0) return;  // no first set (an invalid symbol, rank < k)
     if (ahead) {
         // no second set to hand over (an invalid symbol, rank < k, no unused column)
         if (lane == 0) spec->ok = 0;
@@ -674,8 +761,10 @@ __global__ __launch_bounds__(64) void decompose_kernel(const uint8_t *__restrict
         pre.vcap = args.rounds->vcap[lane];
         pre.cut = args.rounds->cut_g;
     }
-    // workgroup 1 (only with args.spec): the second information set ahead
-    decompose_code<P, WF>(G, cs, rows, args, lds, blockIdx.x == 1, pre);
+    // workgroup 1: the second information set ahead (with args.spec), else
+    // the first set's pair table; workgroup 2: the first set's pair table
+    const int role = blockIdx.x == 0 ? ROLE_MAIN : (blockIdx.x == 1 && args.spec != nullptr) ? ROLE_AHEAD : ROLE_TABLE0;
+    decompose_code<P, WF>(G, cs, rows, args, lds, role, pre);
 }
 
 // =====================================================================
@@ -834,6 +923,83 @@ __device__ __forceinline__ int extend_and_sweep(const u32 *__restrict__ rows, in
     });
 }
 
+// One unit of a pair table (see pair_units): W words of 16 bytes at a
+// wave-uniform index, held as a Row (F_3: planes 0, 1 of R_s + R_L in p[0],
+// p[1] and of R_s - R_L in p[2], any).
+// (through the constant address space: the table is read-only while the
+// enumeration runs, so the wave-uniform loads are scalar loads)
+typedef const __attribute__((address_space(4))) u32 *const_u32_ptr;
+template <int W>
+__device__ __forceinline__ Row<W> load_unit(const uint4 *__restrict__ ptab, int u) {
+    const_u32_ptr src = (const_u32_ptr)(ptab + (size_t)u * W);
+    Row<W> r;
+#pragma unroll
+    for (int w = 0; w < W; w++) {
+        r.p[0][w] = src[4 * w];
+        r.p[1][w] = src[4 * w + 1];
+        r.p[2][w] = src[4 * w + 2];
+        r.any[w] = src[4 * w + 3];
+    }
+    return r;
+}
+
+template <int W>
+__device__ __forceinline__ void pin_unit(const Row<W> &r) {
+#pragma unroll
+    for (int w = 0; w < W; w++) asm volatile("" ::"s"(r.p[0][w]), "s"(r.p[1][w]), "s"(r.p[2][w]), "s"(r.any[w]));
+}
+
+// Every combination Q + h_s R_s + h_L R_L of the pairs [e0, e1) of a pair
+// table with the lane's exact base Q, (p-1)^2 per pair, through isometric
+// additions and subtractions only: F_3 takes Q +- (R_s + R_L) and
+// Q +- (R_s - R_L); F_7 takes Q + h T_c, h = +-2^e, for the six units
+// T_c = R_s + c R_L (complete_all with one prefix).  UR units per step, their
+// loads issued before the first is used.
+template <int P, int W, bool HIST>
+__device__ __forceinline__ void sweep_pairs(const uint4 *__restrict__ ptab, int e0, int e1, const u32 (&Q)[3][W],
+                                            u32 &lmin, u32 *lh, u32 woff, u32 cap) {
+    constexpr int UN = (P == 3) ? 1 : P - 1;
+    constexpr int UR = (W <= 2) ? 4 : 2;
+    u32 Pv[1][3][W], anyQ[1][W];
+#pragma unroll
+    for (int w = 0; w < W; w++) {
+#pragma unroll
+        for (int b = 0; b < 3; b++) Pv[0][b][w] = Q[b][w];
+        anyQ[0][w] = Q[0][w] | Q[1][w] | Q[2][w];
+    }
+    const int u1 = uni(e1 * UN);
+    for (int u = uni(e0 * UN); u < u1; u += UR) {
+        Row<W> T[UR];
+#pragma unroll
+        for (int i = 0; i < UR; i++) T[i] = load_unit<W>(ptab, min(u + i, u1 - 1));
+#pragma unroll
+        for (int i = 0; i < UR; i++) pin_unit<W>(T[i]);
+#pragma unroll
+        for (int i = 0; i < UR; i++) {
+            if (u + i >= u1) break;
+            if constexpr (P == 3) {
+                u32 wa = 0, ws = 0, wb = 0, wt = 0;
+#pragma unroll
+                for (int w = 0; w < W; w++) {
+                    wa += __builtin_popcount(f3_iso_add(Q[0][w], Q[1][w], T[i].p[0][w], T[i].p[1][w]));
+                    ws += __builtin_popcount(f3_iso_sub(Q[0][w], Q[1][w], T[i].p[0][w], T[i].p[1][w]));
+                    wb += __builtin_popcount(f3_iso_add(Q[0][w], Q[1][w], T[i].p[2][w], T[i].any[w]));
+                    wt += __builtin_popcount(f3_iso_sub(Q[0][w], Q[1][w], T[i].p[2][w], T[i].any[w]));
+                }
+                lmin = min(lmin, min(min(wa, ws), min(wb, wt)));
+                if constexpr (HIST) {
+                    count_hist<P, W, HIST>(lh, min(wa + woff, cap));
+                    count_hist<P, W, HIST>(lh, min(ws + woff, cap));
+                    count_hist<P, W, HIST>(lh, min(wb + woff, cap));
+                    count_hist<P, W, HIST>(lh, min(wt + woff, cap));
+                }
+            } else {
+                complete_all<P, W, 1, HIST>(Pv, anyQ, T[i], lmin, lh, woff, cap);
+            }
+        }
+    }
+}
+
 // C(c, i) for c < crows and i < BIN_I into LDS: every load of a thread is
 // issued before its first store (a loop that stores each value before the next
 // load waits for one memory round trip per element).  blockDim.x = 256.
@@ -980,8 +1146,9 @@ __device__ void run_small_task(int g, int k, int j, const u32 *__restrict__ rows
 // combinations the lane evaluated (the rows its sweeps combined) to lcnt.
 template <int P, int W, bool HIST>
 __device__ void run_base_task(const StageDesc &sd, int k, int j, const u32 *__restrict__ rows, const uint4 *lrows,
-                              const u64 *sbin, const u64 *__restrict__ gbin, const QEntry *qtab, int nq, u64 task,
-                              u32 &lmin, u64 &lcnt, u32 *lh, u32 woff, u32 cap) {
+                              const uint4 *__restrict__ ptab, const u64 *sbin, const u64 *__restrict__ gbin,
+                              const QEntry *qtab, int nq, u64 task, u32 &lmin, u64 &lcnt, u32 *lh, u32 woff,
+                              u32 cap) {
     const int lane = __lane_id();
     const int g = uni(sd.g);
     const u64 M = uni(sd.coef_combos);
@@ -1007,6 +1174,23 @@ __device__ void run_base_task(const StageDesc &sd, int k, int j, const u32 *__re
     // multipliers of every last row its sweeps combine
     constexpr u32 PER_ROW = (u32)((P - 1) * (P - 1));
     u32 ncomb = 0;
+    // every row s of the block and every last row L > s for the lane's base Q:
+    // from the set's pair table when it has one, else through the exact
+    // prefixes Q + h R_s
+    auto sweep_block = [&]() {
+        if (ptab != nullptr) {
+            const int e0 = uni((int)pair_first(s_lo, k)), e1 = uni((int)pair_first(s_hi, k));
+            if (valid) {
+                sweep_pairs<P, W, HIST>(ptab, e0, e1, Q, lmin, lh, woff, cap);
+                ncomb += PER_ROW * (u32)(e1 - e0);
+            }
+            return;
+        }
+        for (int s = s_lo; s < s_hi; s++) {
+            const Row<W> Rs = load_row<P, W>(rows, j, uni(s));
+            if (valid) ncomb += PER_ROW * (u32)extend_and_sweep<P, W, P - 1, HIST>(rows, j, s, k, Q, Rs, lmin, lh, woff, cap);
+        }
+    };
     if (vd == 0) {
         // one base per lane
         if (valid) {
@@ -1016,10 +1200,7 @@ __device__ void run_base_task(const StageDesc &sd, int k, int j, const u32 *__re
                                add_scaled<P, W>(Q, r.p, coef);
                            });
         }
-        for (int s = s_lo; s < s_hi; s++) {
-            const Row<W> Rs = load_row<P, W>(rows, j, uni(s));
-            if (valid) ncomb += PER_ROW * (u32)extend_and_sweep<P, W, P - 1, HIST>(rows, j, s, k, Q, Rs, lmin, lh, woff, cap);
-        }
+        sweep_block();
         lcnt += ncomb;
         return;
     }
@@ -1037,10 +1218,7 @@ __device__ void run_base_task(const StageDesc &sd, int k, int j, const u32 *__re
         const Row<W> Rq = load_row<P, W>(rows, j, q);
         for (int v = 0; v < P - 1; v++) {
             if (v > 0 && valid) add_scaled<P, W>(Q, Rq.p, 1);
-            for (int s = s_lo; s < s_hi; s++) {
-                const Row<W> Rs = load_row<P, W>(rows, j, uni(s));
-                if (valid) ncomb += PER_ROW * (u32)extend_and_sweep<P, W, P - 1, HIST>(rows, j, s, k, Q, Rs, lmin, lh, woff, cap);
-            }
+            sweep_block();
         }
     }
     if constexpr (P == 3) {
@@ -1074,10 +1252,7 @@ __device__ void run_base_task(const StageDesc &sd, int k, int j, const u32 *__re
                     if (valid) add_scaled<P, W>(Q, Rd2.p, h);
                 }
             }
-            for (int s = s_lo; s < s_hi; s++) {
-                const Row<W> Rs = load_row<P, W>(rows, j, uni(s));
-                if (valid) ncomb += PER_ROW * (u32)extend_and_sweep<P, W, P - 1, HIST>(rows, j, s, k, Q, Rs, lmin, lh, woff, cap);
-            }
+            sweep_block();
         }
     }
     lcnt += ncomb;
@@ -1130,10 +1305,11 @@ __device__ void run_checker(CodeState *cs, const StageDesc *sdesc, int ns, const
 
 template <int P, int W, bool HIST>
 __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__restrict__ rows,
-                                                   const u64 *__restrict__ gbin, u64 *__restrict__ hist,
-                                                   EnumArgs ea) {
+                                                   const uint4 *__restrict__ pairs, const u64 *__restrict__ gbin,
+                                                   u64 *__restrict__ hist, EnumArgs ea) {
     const int lookahead = ea.lookahead;
     const u64 timeout_ticks = ea.timeout_ticks;
+    const int pslot1 = pairs != nullptr ? uni(cs->pair_slot1) : 1;  // slot of set 1's pair table
     __shared__ u64 sbin[BZ_MAX_K * BIN_I];
     __shared__ StageDesc sdesc[BZ_MAX_STAGES];
     __shared__ QEntry qtab[BZ_MAX_K];
@@ -1212,9 +1388,12 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
         if constexpr (HIST) {
             for (int w = lane; w <= n; w += 64) lh[w] = 0;
         }
-        if (sg > SUBSET_G)
-            run_base_task<P, W, HIST>(sd, k, uni(sd.j - 1), rows, lrows, sbin, gbin, qtab, k - 2 - (sg - 3), task,
-                                      lmin, lcnt, lh, woff, cap);
+        if (sg > SUBSET_G) {
+            const int sj = uni(sd.j - 1);
+            const uint4 *ptab = pairs != nullptr ? pairs + (size_t)(sj == 1 ? pslot1 : sj) * ea.pair_stride : nullptr;
+            run_base_task<P, W, HIST>(sd, k, sj, rows, lrows, ptab, sbin, gbin, qtab, k - 2 - (sg - 3), task, lmin,
+                                      lcnt, lh, woff, cap);
+        }
         else
             run_small_task<P, W, HIST>(sg, k, uni(sd.j - 1), rows, lrows, sbin, gbin, task, lmin, lcnt, lh, woff, cap);
         if constexpr (HIST) {
@@ -1421,7 +1600,8 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
 // BatchState::remaining.
 __global__ __launch_bounds__(64) void decompose_batch_kernel(const uint8_t *__restrict__ G,
                                                              const BatchCode *__restrict__ codes, CodeState *css,
-                                                             u64 *claims, u32 *__restrict__ rows, uint32_t grid,
+                                                             u64 *claims, u32 *__restrict__ rows,
+                                                             uint4 *__restrict__ pairs, uint32_t grid,
                                                              BatchState *bs, const int32_t *__restrict__ slots,
                                                              uint32_t *done_flags, CodeResult *res_map) {
     __shared__ DecompLDS lds;
@@ -1442,6 +1622,9 @@ __global__ __launch_bounds__(64) void decompose_batch_kernel(const uint8_t *__re
     a.spec = nullptr;
     a.epoch = 0;
     a.pad = 0;
+    a.pairs = (pairs != nullptr && bc.pair_offset != ~0ull) ? pairs + bc.pair_offset : nullptr;
+    a.pair_stride = bc.pair_stride;
+    a.pair_w = bc.W;
     const uint8_t *g = G + bc.g_offset;
     u32 *r = rows + bc.row_offset;
     if (bc.p == 3) {
@@ -1493,8 +1676,8 @@ __global__ void features_kernel(const CodeState *__restrict__ css, const int32_t
 // The lane's combinations are added to lcnt.
 template <int P, int W>
 __device__ void run_part(const StageDesc &sd, int s, uint32_t part, int k, const u32 *__restrict__ rows,
-                         const u64 *sbin, const u64 *__restrict__ gbin, const QEntry *qtab, u32 woff, u32 cap,
-                         u32 &lmin, u64 &lcnt) {
+                         const uint4 *__restrict__ ptab, const u64 *sbin, const u64 *__restrict__ gbin,
+                         const QEntry *qtab, u32 woff, u32 cap, u32 &lmin, u64 &lcnt) {
     const int wid = threadIdx.x >> 6;
     const int g = uni(sd.g), j = uni(sd.j - 1), nq = k - 2 - (g - 3);
     const u64 tiles = uni64(sd.tiles), tasks = uni64(sd.tasks);
@@ -1505,7 +1688,7 @@ __device__ void run_part(const StageDesc &sd, int s, uint32_t part, int k, const
         const u64 task = tile * WAVES_PER_GROUP + (u64)wid;
         if (task >= tasks) continue;
         if (g > SUBSET_G)
-            run_base_task<P, W, false>(sd, k, j, rows, nullptr, sbin, gbin, qtab, nq, task, lmin, lcnt, nullptr, woff,
+            run_base_task<P, W, false>(sd, k, j, rows, nullptr, ptab, sbin, gbin, qtab, nq, task, lmin, lcnt, nullptr, woff,
                                       cap);
         else
             run_small_task<P, W, false>(g, k, j, rows, nullptr, sbin, gbin, task, lmin, lcnt, nullptr, woff, cap);
@@ -1551,6 +1734,7 @@ template <int WMAX>
 __global__ __launch_bounds__(256) void enum_batch_kernel(CodeState *css, u64 *claims,
                                                          const BatchCode *__restrict__ codes,
                                                          int ncodes, const u32 *__restrict__ rows,
+                                                         const uint4 *__restrict__ pairs,
                                                          const u64 *__restrict__ gbin, BatchState *bs,
                                                          u64 timeout_ticks, const int32_t *__restrict__ order,
                                                          const uint32_t *yield, uint32_t *done_flags,
@@ -1648,18 +1832,22 @@ __global__ __launch_bounds__(256) void enum_batch_kernel(CodeState *css, u64 *cl
         const u32 woff = (uni(codes[code].flags) & FLAG_SKIP) ? (u32)sd.g : 0u;
         const u32 cap = (u32)n;
         const u32 *r = rows + row_off;
+        const u64 pair_off = uni64(codes[code].pair_offset);
+        const uint4 *pt = (pairs != nullptr && pair_off != ~0ull)
+                              ? pairs + pair_off + (size_t)uni(sd.j - 1) * uni(codes[code].pair_stride)
+                              : nullptr;
         u32 lmin = BIG;
         u64 lcnt = 0;
         if (p == 3) {
-            if (W == 1) run_part<3, 1>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin, lcnt);
-            if constexpr (WMAX >= 2) if (W == 2) run_part<3, 2>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin, lcnt);
-            if constexpr (WMAX >= 3) if (W == 3) run_part<3, 3>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin, lcnt);
-            if constexpr (WMAX >= 4) if (W == 4) run_part<3, 4>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin, lcnt);
+            if (W == 1) run_part<3, 1>(sd, s, part, k, r, pt, sbin, gbin, qtab, woff, cap, lmin, lcnt);
+            if constexpr (WMAX >= 2) if (W == 2) run_part<3, 2>(sd, s, part, k, r, pt, sbin, gbin, qtab, woff, cap, lmin, lcnt);
+            if constexpr (WMAX >= 3) if (W == 3) run_part<3, 3>(sd, s, part, k, r, pt, sbin, gbin, qtab, woff, cap, lmin, lcnt);
+            if constexpr (WMAX >= 4) if (W == 4) run_part<3, 4>(sd, s, part, k, r, pt, sbin, gbin, qtab, woff, cap, lmin, lcnt);
         } else {
-            if (W == 1) run_part<7, 1>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin, lcnt);
-            if constexpr (WMAX >= 2) if (W == 2) run_part<7, 2>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin, lcnt);
-            if constexpr (WMAX >= 3) if (W == 3) run_part<7, 3>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin, lcnt);
-            if constexpr (WMAX >= 4) if (W == 4) run_part<7, 4>(sd, s, part, k, r, sbin, gbin, qtab, woff, cap, lmin, lcnt);
+            if (W == 1) run_part<7, 1>(sd, s, part, k, r, pt, sbin, gbin, qtab, woff, cap, lmin, lcnt);
+            if constexpr (WMAX >= 2) if (W == 2) run_part<7, 2>(sd, s, part, k, r, pt, sbin, gbin, qtab, woff, cap, lmin, lcnt);
+            if constexpr (WMAX >= 3) if (W == 3) run_part<7, 3>(sd, s, part, k, r, pt, sbin, gbin, qtab, woff, cap, lmin, lcnt);
+            if constexpr (WMAX >= 4) if (W == 4) run_part<7, 4>(sd, s, part, k, r, pt, sbin, gbin, qtab, woff, cap, lmin, lcnt);
         }
         for (int off = 32; off >= 1; off >>= 1) {
             lmin = min(lmin, (u32)__shfl_xor((int)lmin, off));

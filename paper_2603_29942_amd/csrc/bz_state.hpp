@@ -21,6 +21,33 @@ typedef uint64_t u64;
 constexpr int ROW_WORDS = 16;
 constexpr uint64_t DEFAULT_LIMIT = 1ull << 44;
 
+// Pair tables: for each information set, the exact sums of two of its rows,
+// R_s + c R_L for s < L and every c in F_p^* up to the sign that the isometric
+// subtraction supplies (Sec. 4.2-4.3): F_3 keeps R_s + R_L and R_s - R_L
+// (planes 0 and 1 of each, one 16-byte unit per word), F_7 keeps c = 1..6 (six
+// units per pair, each word planes 0..2 and their OR).  A combination
+// base + h_s R_s + h_L R_L equals base + h_s T with T = R_s + (h_L / h_s) R_L,
+// so a lane with an exact base finishes all (p-1)^2 multipliers of the pair
+// from these units without an exact addition of its own.  Pairs are stored
+// row-major in s (all L > s of row s, ascending), so the pairs of a run of
+// rows s form one contiguous range.  Unit u of pair e, word w: at (e * units +
+// u) * W + w, in units of 16 bytes.
+BZ_HD int pair_units(int p) { return p == 3 ? 1 : p - 1; }
+// pairs (s', L) with s' < s: those of rows 0 .. s-1
+BZ_HD u64 pair_first(int s, int k) { return (u64)s * (u64)(k - 1) - (u64)s * (u64)(s - 1) / 2; }
+BZ_HD u64 pair_table_units(int p, int k, int W) { return (u64)k * (u64)(k - 1) / 2 * (u64)pair_units(p) * (u64)W; }
+// pair e = (s, s + 1 + rem) in that order: advance (s, rem) by d pairs
+BZ_HD void pair_advance(int k, int &s, int &rem, int d) {
+    rem += d;
+    while (s < k - 1 && rem >= k - 1 - s) {
+        rem -= k - 1 - s;
+        s++;
+    }
+}
+// information sets a decomposition can produce: every full-rank set takes k
+// unused columns and the first deficient one ends it
+BZ_HD int pair_sets(int n, int k) { return n / k + 1 < BZ_MAX_M ? n / k + 1 : BZ_MAX_M; }
+
 // One stage (g, j) of Algorithm 6, and how its work is cut into wave tasks
 // (64 lanes each):
 //   g = 1: a task covers 64 rows i (one combination per lane).
@@ -104,7 +131,7 @@ struct CodeState {
     // inputs of this run
     int32_t p, n, k, flags;
     int32_t U0;           // n - k + 1
-    int32_t pad0;
+    int32_t pair_slot1;   // slot of the second set's pair table (1, or pair_sets(n, k): built ahead)
     u64 max_codewords;
     // completion tracking: workgroups done with each stage
     uint32_t stage_done[BZ_MAX_STAGES];
@@ -140,6 +167,8 @@ struct BatchCode {
     int32_t p, n, k, flags;
     int32_t U0, WF, W;    // words per plane of G, and processed per combination
     uint32_t sweep_ops;  // VALU operations per lane and task
+    uint32_t pair_stride;  // 16-byte units per pair table (pair_table_units(p, k, W))
+    u64 pair_offset;       // 16-byte offset of its first pair table, ~0: no tables
 };
 
 // Batch-wide state: codes with stages left, the error flag of a time-out, and

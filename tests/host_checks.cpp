@@ -686,6 +686,57 @@ static void check_blocks() {
     if (fails == before) std::printf("OK blocks\n");
 }
 
+// Pair tables: the walk of pair_advance visits the pairs s < L row-major in s,
+// each once, at index pair_first(s, k) + (L - s - 1), from any start and in
+// steps of one or of 64; the pairs of a block of rows s of a q-group are the
+// index range [pair_first(s_lo), pair_first(s_hi)), consecutive blocks abut,
+// and a table holds exactly units x W x pairs entries.
+static void check_pairs() {
+    const int before = fails;
+    for (int k = 1; k <= 64; k++) {
+        const int np = k * (k - 1) / 2;
+        CHECK(pair_first(k - 1, k) == (u64)np && pair_first(0, k) == 0);
+        int s = 0, rem = 0, e = 0;
+        pair_advance(k, s, rem, 0);
+        for (int a = 0; a < k; a++)
+            for (int b = a + 1; b < k; b++, e++) {
+                CHECK(s == a && s + 1 + rem == b);
+                CHECK(pair_first(a, k) + (u64)(b - a - 1) == (u64)e);
+                pair_advance(k, s, rem, 1);
+            }
+        CHECK(e == np);
+        for (int t = 0; t < 64; t++) {
+            int s2 = 0, r2 = 0;
+            pair_advance(k, s2, r2, t);
+            for (int e2 = t; e2 < np; e2 += 64) {
+                const int L = s2 + 1 + r2;
+                CHECK(s2 < L && L < k && pair_first(s2, k) + (u64)r2 == (u64)e2);
+                pair_advance(k, s2, r2, 64);
+            }
+        }
+        for (int p : {3, 7})
+            for (int W = 1; W <= 4; W++)
+                CHECK(pair_table_units(p, k, W) == (u64)np * (u64)(p == 3 ? 1 : 6) * (u64)W);
+        for (int q = 0; q <= k - 3; q++)
+            for (uint32_t cap : {1u, 7u, 57u, 2000u}) {
+                const uint32_t nb = qgroup_blocks(k, cap, q);
+                u64 prev = pair_first(q + 1, k);
+                for (uint32_t b = 0; b < nb; b++) {
+                    const int lo = q + 1 + qgroup_block_start(k, q, nb, b);
+                    const int hi = q + 1 + qgroup_block_start(k, q, nb, b + 1);
+                    u64 want = 0;
+                    for (int r = lo; r < hi; r++) want += (u64)(k - 1 - r);
+                    CHECK(pair_first(lo, k) == prev && pair_first(hi, k) - pair_first(lo, k) == want);
+                    prev = pair_first(hi, k);
+                }
+                CHECK(prev == (u64)np);
+            }
+    }
+    for (int n = 1; n <= BZ_MAX_N; n++)
+        for (int k = 1; k <= n && k <= BZ_MAX_K; k++) CHECK(pair_sets(n, k) >= 1 && pair_sets(n, k) * k >= n);
+    if (fails == before) std::printf("OK pairs\n");
+}
+
 // The next row of a colex unranking (direct for i = 1, a table search above)
 // against a plain scan for the largest c with C(c, i) <= rho.
 static void check_top_row() {
@@ -712,6 +763,7 @@ int main() {
     check_top_row();
     check_bits();
     check_blocks();
+    check_pairs();
     check_digits();
     for (int a = 0; a <= 64; a++)
         for (int b = 0; b <= 64; b++) CHECK(binom_sat(a, b) == ~0ull || BINOM[a * 65 + b] == binom_sat(a, b));

@@ -25,8 +25,8 @@ def test_host_checks(tmp_path):
     out = subprocess.run([exe], capture_output=True, text=True)
     assert out.returncode == 0, out.stdout
     lines = out.stdout.splitlines()
-    assert [l.split(" (")[0] for l in lines] == ["OK top row", "OK bits", "OK blocks", "OK digits", "OK arith", "OK schedule",
-                                                   "OK parallel schedule", "OK unrank"]
+    assert [l.split(" (")[0] for l in lines] == ["OK top row", "OK bits", "OK blocks", "OK pairs", "OK digits",
+                                                   "OK arith", "OK schedule", "OK parallel schedule", "OK unrank"]
 
 
 SWEEP_MUTANTS = {
