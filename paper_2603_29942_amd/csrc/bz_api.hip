@@ -142,7 +142,7 @@ int init_ctx(int dev) {
     if (hipMalloc(&c.g_buf, (size_t)BZ_MAX_K * BZ_MAX_N) != hipSuccess) return BZ_ERR_NOMEM;
     if (hipMalloc(&c.cs, sizeof(CodeState)) != hipSuccess) return BZ_ERR_NOMEM;
     if (hipMalloc(&c.rows, sizeof(u32) * BZ_MAX_M * BZ_MAX_K * ROW_WORDS) != hipSuccess) return BZ_ERR_NOMEM;
-    if (hipMalloc(&c.pairs, sizeof(uint4) * max_pair_units()) != hipSuccess) return BZ_ERR_NOMEM;
+    if (hipMalloc(&c.pairs, sizeof(uint4) * (max_pair_units() + PAIR_PAD_UNITS)) != hipSuccess) return BZ_ERR_NOMEM;
     if (hipMalloc(&c.binom, sizeof(u64) * 65 * 65) != hipSuccess) return BZ_ERR_NOMEM;
     if (hipMalloc(&c.hist, sizeof(u64) * BZ_MAX_STAGES * (BZ_MAX_N + 1)) != hipSuccess) return BZ_ERR_NOMEM;
     if (hipMalloc(&c.spec, sizeof(SpecBuf)) != hipSuccess) return BZ_ERR_NOMEM;
@@ -444,7 +444,7 @@ int grow_batch(DevCtx &c, size_t ncodes, size_t row_words, size_t pair_units, si
         if (c.b_pairs) (void)hipFree(c.b_pairs);
         c.b_pairs = nullptr;
         c.b_pairs_cap = 0;
-        if (hipMalloc(&c.b_pairs, sizeof(uint4) * pair_units) != hipSuccess) return BZ_ERR_NOMEM;
+        if (hipMalloc(&c.b_pairs, sizeof(uint4) * (pair_units + PAIR_PAD_UNITS)) != hipSuccess) return BZ_ERR_NOMEM;
         c.b_pairs_cap = pair_units;
     }
     if (g_bytes > c.b_g_cap) {

@@ -954,7 +954,8 @@ __device__ __forceinline__ void pin_unit(const Row<W> &r) {
 // additions and subtractions only: F_3 takes Q +- (R_s + R_L) and
 // Q +- (R_s - R_L); F_7 takes Q + h T_c, h = +-2^e, for the six units
 // T_c = R_s + c R_L (complete_all with one prefix).  UR units per step, their
-// loads issued before the first is used.
+// loads issued before the first is used; the last step's loads may run past
+// the pairs' range into the next set's table or the buffer's PAIR_PAD_UNITS.
 template <int P, int W, bool HIST>
 __device__ __forceinline__ void sweep_pairs(const uint4 *__restrict__ ptab, int e0, int e1, const u32 (&Q)[3][W],
                                             u32 &lmin, u32 *lh, u32 woff, u32 cap) {
@@ -971,7 +972,7 @@ __device__ __forceinline__ void sweep_pairs(const uint4 *__restrict__ ptab, int 
     for (int u = uni(e0 * UN); u < u1; u += UR) {
         Row<W> T[UR];
 #pragma unroll
-        for (int i = 0; i < UR; i++) T[i] = load_unit<W>(ptab, min(u + i, u1 - 1));
+        for (int i = 0; i < UR; i++) T[i] = load_unit<W>(ptab, u + i);  // (past u1: padding or the next table)
 #pragma unroll
         for (int i = 0; i < UR; i++) pin_unit<W>(T[i]);
 #pragma unroll

@@ -44,6 +44,9 @@ BZ_HD void pair_advance(int k, int &s, int &rem, int d) {
         s++;
     }
 }
+// units past the last table of a buffer that a sweep's group of loads may
+// read (a group of UR units of W words, at most 8 of 16 bytes, is loaded whole)
+constexpr int PAIR_PAD_UNITS = 16;
 // information sets a decomposition can produce: every full-rank set takes k
 // unused columns and the first deficient one ends it
 BZ_HD int pair_sets(int n, int k) { return n / k + 1 < BZ_MAX_M ? n / k + 1 : BZ_MAX_M; }
@@ -245,8 +248,10 @@ BZ_HD int bound_c(int g, int k, int kj) {
 #endif
 constexpr uint32_t DEFAULT_SWEEP_OPS = BZ_SWEEP_OPS;
 // Task size of the plain path: F_3 tasks of 3000 operations (the F_3 [72,36]
-// codes run 3% faster than with 4500, F_7 [48,24] 4% slower).
-BZ_HD uint32_t plain_sweep_ops(int p) { return p == 3 ? 3000u : DEFAULT_SWEEP_OPS; }
+// codes run 3% faster than with 4500, F_7 [48,24] 4% slower); F_7 tasks of
+// 6000 (with the pair tables the F_7 [48,24] codes run 2% faster than with
+// 4500 or 9000, 18% slower with 3000).
+BZ_HD uint32_t plain_sweep_ops(int p) { return p == 3 ? 3000u : 6000u; }
 BZ_HD uint32_t sweep_cap_for(int p, int W, uint32_t ops = DEFAULT_SWEEP_OPS) {
     const uint32_t per = (p == 3) ? 2u * (6u * (uint32_t)W + 1u) : 6u * (25u * (uint32_t)W + 3u);
     const uint32_t cap = (ops ? ops : DEFAULT_SWEEP_OPS) / per;
