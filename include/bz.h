@@ -9,9 +9,9 @@
  * matrices Gamma_j, the bit-sliced packing in the natural encoding (Sec. 2 and
  * 4.1), the enumeration of all g-row combinations with the lowest coefficient
  * fixed to 1 (Sec. 4.2), exact prefix sums with the F_3 / F_7 additions of
- * Algorithms 3 and 4 (for the rounds g >= 5 of the batched calls and of F_7
- * plain calls, the sums of the two highest rows of a combination come from
- * a per-set table of all row pairs that the decomposition builds), the
+ * Algorithms 3 and 4 (for the rounds g >= 5 of the batched and served calls
+ * and of F_7 plain calls, the sums of the two highest rows of a combination
+ * come from a per-set table of all row pairs that the decomposition builds), the
  * isometric last addition (Sec. 4.3), the popcount
  * weight, the min-reduce against the upper bound U, and the stage-by-stage
  * lower-bound test with early termination (Sec. 4.4).
@@ -285,7 +285,10 @@ typedef struct {
 } bz_server_options;
 
 void bz_default_server_options(bz_server_options *o);
-/* Allocates the slots (about 28 KB + 4 KB x min(128, max_n) + 64 max_n bytes each). */
+/* Allocates the slots (about 28 KB + 4 KB x min(128, max_n) + 64 max_n bytes
+ * each, plus the pair tables of the largest code a slot may hold: 0.39 MB for
+ * max_n = 64, 1.7 MB for max_n = 128 with the identity skip, 0.77 / 2.3 MB
+ * without). */
 int bz_server_start(const bz_server_options *o, bz_server **out);
 /* Queues one code (G: host, k x n row-major, copied); tag is returned with its result.
  * BZ_ERR_ARG for an invalid shape or n > max_n; the code's own errors (VALUE,

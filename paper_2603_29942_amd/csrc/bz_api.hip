@@ -107,16 +107,17 @@ u64 code_pair_units(int p, int n, int k, int W, bool ahead_slot) {
     return (u64)(pair_sets(n, k) + (ahead_slot ? 1 : 0)) * pair_table_units(p, k, W);
 }
 
-// the largest plain-path code_pair_units of any code the library accepts (p =
-// 7 has the larger tables; W as the enumeration takes it, with or without the
-// identity skip)
-u64 max_pair_units() {
+// the largest code_pair_units of any code with n <= max_n (p = 7 has the
+// larger tables; W as the enumeration takes it: with the identity skip when
+// skip is 1, without it when 0, either when -1)
+u64 max_pair_units(int max_n, int skip, bool ahead_slot) {
     u64 best = 0;
-    for (int n = 1; n <= BZ_MAX_N; n++)
+    for (int n = 1; n <= max_n; n++)
         for (int k = 1; k <= n && k <= BZ_MAX_K; k++) {
-            const int WF = (n + 31) / 32, Ws = (n - k + 31) / 32;
-            for (int W : {WF, Ws < 1 ? 1 : Ws}) {
-                const u64 u = code_pair_units(7, n, k, W, true);
+            const int WF = (n + 31) / 32, Ws = (n - k + 31) / 32 < 1 ? 1 : (n - k + 31) / 32;
+            for (int W : {WF, Ws}) {
+                if ((skip == 1 && W != Ws) || (skip == 0 && W != WF)) continue;
+                const u64 u = code_pair_units(7, n, k, W, ahead_slot);
                 if (u > best) best = u;
             }
         }
@@ -142,7 +143,8 @@ int init_ctx(int dev) {
     if (hipMalloc(&c.g_buf, (size_t)BZ_MAX_K * BZ_MAX_N) != hipSuccess) return BZ_ERR_NOMEM;
     if (hipMalloc(&c.cs, sizeof(CodeState)) != hipSuccess) return BZ_ERR_NOMEM;
     if (hipMalloc(&c.rows, sizeof(u32) * BZ_MAX_M * BZ_MAX_K * ROW_WORDS) != hipSuccess) return BZ_ERR_NOMEM;
-    if (hipMalloc(&c.pairs, sizeof(uint4) * (max_pair_units() + PAIR_PAD_UNITS)) != hipSuccess) return BZ_ERR_NOMEM;
+    if (hipMalloc(&c.pairs, sizeof(uint4) * (max_pair_units(BZ_MAX_N, -1, true) + PAIR_PAD_UNITS)) != hipSuccess)
+        return BZ_ERR_NOMEM;
     if (hipMalloc(&c.binom, sizeof(u64) * 65 * 65) != hipSuccess) return BZ_ERR_NOMEM;
     if (hipMalloc(&c.hist, sizeof(u64) * BZ_MAX_STAGES * (BZ_MAX_N + 1)) != hipSuccess) return BZ_ERR_NOMEM;
     if (hipMalloc(&c.spec, sizeof(SpecBuf)) != hipSuccess) return BZ_ERR_NOMEM;
@@ -1053,12 +1055,13 @@ struct bz_server {
     hipEvent_t round_done = nullptr;
     bz_server_options o{};
     int slots = 0, grid = 0, decomp_grid = 0, flags = 0;
-    u64 max_cw = 0, timeout = 0, rows_per_slot = 0, g_per_slot = 0;
+    u64 max_cw = 0, timeout = 0, rows_per_slot = 0, g_per_slot = 0, pairs_per_slot = 0;
     // device
     CodeState *cs = nullptr;
     u64 *claims = nullptr;  // one claim word per slot, contiguous
     BatchCode *codes = nullptr;
     u32 *rows = nullptr;
+    uint4 *pairs = nullptr;  // pair tables, pairs_per_slot 16-byte units per slot
     uint8_t *g = nullptr;
     BatchState *bs = nullptr;
     int32_t *order_d = nullptr, *new_d = nullptr;
@@ -1117,8 +1120,9 @@ void servers_release(DevCtx &c) {
 void server_free(bz_server *s) {
     // teardown: errors are not actionable here
     if (s->run) (void)hipStreamSynchronize(s->run);
-    for (void *p : {(void *)s->cs, (void *)s->claims, (void *)s->codes, (void *)s->rows, (void *)s->g, (void *)s->bs,
-                    (void *)s->order_d, (void *)s->new_d, (void *)s->feat_d, (void *)s->pred_d, (void *)s->mlp_d})
+    for (void *p : {(void *)s->cs, (void *)s->claims, (void *)s->codes, (void *)s->rows, (void *)s->pairs,
+                    (void *)s->g, (void *)s->bs, (void *)s->order_d, (void *)s->new_d, (void *)s->feat_d,
+                    (void *)s->pred_d, (void *)s->mlp_d})
         if (p) (void)hipFree(p);
     for (void *p : {(void *)s->codes_h, (void *)s->g_h, (void *)s->yield_h, (void *)s->done_h, (void *)s->res_h,
                     (void *)s->order_h, (void *)s->new_h, (void *)s->pred_h, (void *)s->qfeat_h})
@@ -1157,7 +1161,7 @@ hipError_t server_launch(bz_server *s, int nactive) {
     const BatchCode *cds = s->codes;
     int nc = nactive;
     const u32 *rows = s->rows;
-    const uint4 *prs = nullptr;  // no pair tables: the lanes build their prefixes
+    const uint4 *prs = s->pairs;
     const u64 *bin = s->c->binom;
     BatchState *bs = s->bs;
     u64 to = s->timeout;
@@ -1247,8 +1251,8 @@ int server_round(bz_server *s) {
         b.W = s->o.identity_skip ? (r.n - r.k + 31) / 32 : b.WF;
         if (b.W < 1) b.W = 1;
         b.sweep_ops = DEFAULT_SWEEP_OPS;
-        b.pair_stride = 0;
-        b.pair_offset = ~0ull;
+        b.pair_stride = (uint32_t)pair_table_units(r.p, r.k, b.W);
+        b.pair_offset = (u64)i * s->pairs_per_slot;
         s->new_h[fresh.size()] = i;
         fresh.push_back(i);
     }
@@ -1260,7 +1264,7 @@ int server_round(bz_server *s) {
         HIP_OK(hipMemcpyAsync(s->codes, s->codes_h, sizeof(BatchCode) * (size_t)s->slots, hipMemcpyHostToDevice,
                               s->run));
         HIP_OK(hipMemcpyAsync(s->new_d, s->new_h, sizeof(int32_t) * (size_t)nf, hipMemcpyHostToDevice, s->run));
-        decompose_batch_kernel<<<nf, 64, 0, s->run>>>(s->g, s->codes, s->cs, s->claims, s->rows, nullptr,
+        decompose_batch_kernel<<<nf, 64, 0, s->run>>>(s->g, s->codes, s->cs, s->claims, s->rows, s->pairs,
                                                       (uint32_t)s->decomp_grid, s->bs, s->new_d, s->done_dev,
                                                       s->res_dev);
         HIP_OK(hipGetLastError());
@@ -1343,6 +1347,7 @@ int bz_server_start(const bz_server_options *opt, bz_server **out) {
     const int max_n = o.max_n ? o.max_n : BZ_MAX_N;
     s->wmax = (max_n + 31) / 32 <= 2 ? 2 : 4;
     s->rows_per_slot = batch_row_words(max_n, 1);
+    s->pairs_per_slot = max_pair_units(max_n, o.identity_skip ? 1 : 0, false);
     s->g_per_slot = (u64)(((max_n * BZ_MAX_K) + 255) / 256 * 256);
     s->grid = batch_grid(s->wmax, c->cu, o.blocks_per_cu ? o.blocks_per_cu : 4);
     s->decomp_grid = s->grid * 8;  // smaller parts: a yield waits for at most one short part
@@ -1354,6 +1359,7 @@ int bz_server_start(const bz_server_options *opt, bz_server **out) {
               hipMalloc(&s->claims, sizeof(u64) * ns) == hipSuccess &&
               hipMalloc(&s->codes, sizeof(BatchCode) * ns) == hipSuccess &&
               hipMalloc(&s->rows, sizeof(u32) * s->rows_per_slot * ns) == hipSuccess &&
+              hipMalloc(&s->pairs, sizeof(uint4) * (s->pairs_per_slot * ns + PAIR_PAD_UNITS)) == hipSuccess &&
               hipMalloc(&s->g, s->g_per_slot * ns) == hipSuccess && hipMalloc(&s->bs, sizeof(BatchState)) == hipSuccess &&
               hipMalloc(&s->order_d, sizeof(int32_t) * ns) == hipSuccess &&
               hipMalloc(&s->new_d, sizeof(int32_t) * ns) == hipSuccess &&
