@@ -93,6 +93,9 @@ typedef struct {
 /* bz_result.info: the second information set was computed ahead by a second
  * workgroup of the decomposition launch and handed over (see bz_options.no_ahead) */
 #define BZ_INFO_AHEAD 1
+/* bz_result.info: the rounds g >= 5 took the sums of their two highest rows
+ * from the information sets' pair tables (see bz_options.pair_tables) */
+#define BZ_INFO_PAIRS 2
 
 typedef struct {
     int32_t check;            /* BZ_CHECK_STAGE (default) or BZ_CHECK_ROUND */
@@ -135,6 +138,11 @@ typedef struct {
                                  0 .. k-1, the second set (columns k .. n-1 first) is taken
                                  from a second workgroup that computed it in parallel, if it
                                  has finished (BZ_INFO_AHEAD).  Results never depend on it */
+    int32_t pair_tables;      /* 0 (default): the decomposition builds each information set's
+                                 table of row-pair sums for F_7 codes, not for F_3 ones (the
+                                 plain F_3 runs measured no faster with it); 1: always; -1:
+                                 never (BZ_INFO_PAIRS tells which ran).  Results never depend
+                                 on it; bz_min_distance_noalloc never builds tables */
 } bz_options;
 
 /* Fill *o with the defaults above. */

@@ -26,6 +26,7 @@ OP_ADD, OP_SUB, OP_DOUBLE, OP_ISO_ADD, OP_ISO_SUB, OP_KAT_ADD = range(6)
 ENC_NATURAL, ENC_KAT = 0, 1
 
 INFO_AHEAD = 1
+INFO_PAIRS = 2
 NOALLOC_SCRATCH_BYTES = 640 * 1024
 
 EXPORTS = ("bz_default_options", "bz_min_distance", "bz_min_distance_ex", "bz_status_str",
@@ -56,7 +57,7 @@ class bz_options(ctypes.Structure):
                 ("hip_stream", ctypes.c_void_p), ("device", ctypes.c_int32),
                 ("blocks_per_cu", ctypes.c_int32), ("timing", ctypes.c_int32),
                 ("wait_timeout_s", ctypes.c_int32), ("trace_out", ctypes.POINTER(ctypes.c_uint64)),
-                ("cooperative", ctypes.c_int32), ("no_ahead", ctypes.c_int32)]
+                ("cooperative", ctypes.c_int32), ("no_ahead", ctypes.c_int32), ("pair_tables", ctypes.c_int32)]
 
 
 class bz_code(ctypes.Structure):
@@ -240,12 +241,14 @@ def result_dict(st, r, hist=None):
 
 def min_distance(p, G, *, check="stage", no_termination=False, identity_skip=True, max_codewords=0,
                  histograms=False, blocks_per_cu=0, trace=False, ahead=True,
-                 wait_timeout_s=0, stream=None):
+                 wait_timeout_s=0, stream=None, pair_tables=0):
     """Convenience wrapper: same keys as the oracle's result dict (plus
     ``info`` and, when asked for, ``trace``, the device timeline in ns).
-    stream: a torch stream to run on (G on the device), else the current one."""
+    stream: a torch stream to run on (G on the device), else the current one.
+    pair_tables: 0 the library's choice, 1 always, -1 never (bz_options)."""
     o = bz_default_options()
     o.no_ahead = int(not ahead)
+    o.pair_tables = int(pair_tables)
     o.wait_timeout_s = int(wait_timeout_s)
     if stream is not None:
         o.hip_stream = ctypes.c_void_p(stream.cuda_stream)

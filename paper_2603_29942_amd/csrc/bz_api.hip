@@ -504,6 +504,7 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, c
     if (o.check != BZ_CHECK_STAGE && o.check != BZ_CHECK_ROUND) return BZ_ERR_ARG;
     if (o.histograms && !o.hist_out) return BZ_ERR_ARG;
     if (o.blocks_per_cu < 0 || o.blocks_per_cu > 64 || o.cooperative) return BZ_ERR_ARG;
+    if (o.pair_tables < -1 || o.pair_tables > 1) return BZ_ERR_ARG;
     DevCtx *c = nullptr;
     st = get_ctx(o.device, &c);
     if (st != BZ_OK) return st;
@@ -568,9 +569,10 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, c
     a.spec = o.no_ahead ? nullptr : c->spec;
     a.epoch = c->spec_epoch;
     a.pad = 0;
-    // pair tables for F_7 only: the plain F_3 runs measured no faster with
-    // them (their enumeration is bound by latency, not by the prefixes)
-    a.pairs = p == 7 ? c->pairs : nullptr;
+    // pair tables by default for F_7 only: the plain F_3 runs measured no
+    // faster with them (their enumeration is bound by latency, not by the
+    // prefixes)
+    a.pairs = (o.pair_tables > 0 || (o.pair_tables == 0 && p == 7)) ? c->pairs : nullptr;
     a.pair_stride = (uint32_t)pair_table_units(p, k, W);
     a.pair_w = W;
     a.pair_t0 = 1;  // a workgroup of the decomposition launch of its own builds set 0's table
@@ -973,6 +975,7 @@ extern "C" int bz_min_distance_noalloc(int p, int n, int k, const uint8_t *G, co
     else bz_default_options(&o);
     if (o.check != BZ_CHECK_STAGE && o.check != BZ_CHECK_ROUND) return BZ_ERR_ARG;
     if (o.histograms || o.trace_out || o.timing || o.cooperative) return BZ_ERR_ARG;
+    if (o.pair_tables < -1 || o.pair_tables > 1) return BZ_ERR_ARG;
     if (o.blocks_per_cu < 0 || o.blocks_per_cu > 64 || o.device < 0 || o.device >= MAX_DEV) return BZ_ERR_ARG;
     DevCtx &c = g_ctx[o.device];
     std::lock_guard<std::mutex> lk(c.mu);

@@ -739,7 +739,7 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
         res.status = status;
         res.m = m;
         res.W = W;
-        res.info = handed ? BZ_INFO_AHEAD : 0;
+        res.info = (handed ? BZ_INFO_AHEAD : 0) | (pairs != nullptr ? BZ_INFO_PAIRS : 0);
         res.t_end = 0;
         res.ctl = ctl_make(0, -1, args.U0);
         res.n_table = ns;

@@ -98,7 +98,8 @@ def test_struct_layout(bzlib, tmp_path):
                 ' offsetof(bz_server_options, max_n));'
                 ' printf("%zu %zu %zu\\n", offsetof(bz_result, info), offsetof(bz_options, no_ahead),'
                 ' offsetof(bz_batch_options, code_ms_out));'
-                ' printf("%zu %zu\\n", offsetof(bz_server_options, admit_budget), sizeof(bz_server_options));'
+                ' printf("%zu %zu %zu\\n", offsetof(bz_server_options, admit_budget), sizeof(bz_server_options),'
+                ' offsetof(bz_options, pair_tables));'
                 ' return 0;}\n')
     exe = os.path.join(str(tmp_path), "layout")
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), src, "-o", exe], check=True)
@@ -111,7 +112,7 @@ def test_struct_layout(bzlib, tmp_path):
                ctypes.sizeof(bzlib.bz_server_options), bzlib.bz_server_options.max_codewords.offset,
                bzlib.bz_server_options.max_n.offset, bzlib.bz_result.info.offset, bzlib.bz_options.no_ahead.offset,
                bzlib.bz_batch_options.code_ms_out.offset, bzlib.bz_server_options.admit_budget.offset,
-               ctypes.sizeof(bzlib.bz_server_options)]
+               ctypes.sizeof(bzlib.bz_server_options), bzlib.bz_options.pair_tables.offset]
     assert c_vals == py_vals
 
 
