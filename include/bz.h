@@ -9,7 +9,7 @@
  * matrices Gamma_j, the bit-sliced packing in the natural encoding (Sec. 2 and
  * 4.1), the enumeration of all g-row combinations with the lowest coefficient
  * fixed to 1 (Sec. 4.2), exact prefix sums with the F_3 / F_7 additions of
- * Algorithms 3 and 4 (for the rounds g >= 5 of the batched and served calls
+ * Algorithms 3 and 4 (for the rounds g >= 4 of the batched and served calls
  * and of F_7 plain calls, the sums of the two highest rows of a combination
  * come from a per-set table of all row pairs that the decomposition builds), the
  * isometric last addition (Sec. 4.3), the popcount
@@ -93,7 +93,7 @@ typedef struct {
 /* bz_result.info: the second information set was computed ahead by a second
  * workgroup of the decomposition launch and handed over (see bz_options.no_ahead) */
 #define BZ_INFO_AHEAD 1
-/* bz_result.info: the rounds g >= 5 took the sums of their two highest rows
+/* bz_result.info: the rounds g >= 4 took the sums of their two highest rows
  * from the information sets' pair tables (see bz_options.pair_tables) */
 #define BZ_INFO_PAIRS 2
 
@@ -220,7 +220,8 @@ typedef struct {
     int32_t check;           /* BZ_CHECK_STAGE (default) or BZ_CHECK_ROUND */
     int32_t no_termination;  /* 1: every stage of every code (no L >= U exit) */
     int32_t identity_skip;   /* 1 (default) */
-    int32_t blocks_per_cu;   /* enumeration grid: workgroups per compute unit; 0 = default */
+    int32_t blocks_per_cu;   /* enumeration grid: workgroups per compute unit; 0 = as many
+                                as the kernel's registers and LDS allow */
     uint64_t max_codewords;  /* per-code work limit; 0 = default (2^44) */
     void *hip_stream;        /* NULL = library stream */
     int32_t device;
@@ -280,7 +281,7 @@ typedef struct {
     int32_t check;            /* BZ_CHECK_STAGE (default) or BZ_CHECK_ROUND */
     int32_t identity_skip;    /* 1 (default) */
     uint64_t max_codewords;   /* per-code work limit, 0 = default (2^44) */
-    int32_t blocks_per_cu;    /* persistent launch: workgroups per compute unit, 0 = default */
+    int32_t blocks_per_cu;    /* persistent launch: workgroups per compute unit, 0 = as many as fit */
     int32_t device;
     int32_t wait_timeout_s;   /* as in bz_batch_options */
     int32_t max_n;            /* largest n accepted, 0 = 128; sizes each slot */

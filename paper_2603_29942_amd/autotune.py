@@ -28,7 +28,7 @@ import time
 HERE = os.path.dirname(os.path.abspath(__file__))
 TABLE = os.path.join(HERE, "tuning_gfx950.json")
 SWEEP_CANDIDATES = (1500, 3000, 6000, 12000, 24000, 48000, 96000, 192000)
-BPC_CANDIDATES = (1, 2, 3, 4)
+BPC_CANDIDATES = (1, 2, 3, 4, 5, 6)
 KERNEL_SOURCES = ("bz_kernels.hpp", "bz_arith.hpp", "bz_state.hpp")
 
 

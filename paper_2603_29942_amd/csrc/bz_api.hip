@@ -728,7 +728,7 @@ int bz_min_distance_batch(int ncodes, const bz_code *codes, const uint8_t *G, ui
     hipStream_t s = o.hip_stream ? (hipStream_t)o.hip_stream : c->stream;
     st = grow_batch(*c, (size_t)ncodes, (size_t)row_words, (size_t)pair_units, G_is_device ? 0 : (size_t)g_bytes);
     if (st != BZ_OK) return st;
-    const int bpc = o.blocks_per_cu ? o.blocks_per_cu : 4;
+    const int bpc = o.blocks_per_cu ? o.blocks_per_cu : 64;  // default: as many as fit
     const int grid = batch_grid(wmax, c->cu, bpc);
     if (grid < 1) return BZ_ERR_DEVICE;
     const u64 timeout = c->ticks_per_s * (u64)(o.wait_timeout_s > 0 ? o.wait_timeout_s : 120);
@@ -1352,7 +1352,7 @@ int bz_server_start(const bz_server_options *opt, bz_server **out) {
     s->rows_per_slot = batch_row_words(max_n, 1);
     s->pairs_per_slot = max_pair_units(max_n, o.identity_skip ? 1 : 0, false);
     s->g_per_slot = (u64)(((max_n * BZ_MAX_K) + 255) / 256 * 256);
-    s->grid = batch_grid(s->wmax, c->cu, o.blocks_per_cu ? o.blocks_per_cu : 4);
+    s->grid = batch_grid(s->wmax, c->cu, o.blocks_per_cu ? o.blocks_per_cu : 64);  // default: as many as fit
     s->decomp_grid = s->grid * 8;  // smaller parts: a yield waits for at most one short part
     s->slot.resize((size_t)s->slots);
     const size_t ns = (size_t)s->slots;

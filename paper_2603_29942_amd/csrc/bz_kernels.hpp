@@ -1044,15 +1044,15 @@ __device__ __forceinline__ void prefixes_then_complete(const u32 (&Q)[3][W], con
     complete_all<P, W, NA, HIST>(Pv, anyP, T, lmin, lh, woff, cap);
 }
 
-// G = 3, 4: the lane's subset rows r[0] < ... < r[G-1]; r[0] has coefficient
-// 1, the middle rows every multiplier (exact prefixes, two at a time to keep
-// the registers of F_7 in check), the top row every multiplier through
-// complete_all.
+// G = 3 (and 4 when SUBSET_G is 4): the lane's subset rows r[0] < ... <
+// r[G-1]; r[0] has coefficient 1, the middle rows every multiplier (exact
+// prefixes, one at a time to keep the registers in check), the top row every
+// multiplier through complete_all.
 // Adds the combinations completed to the lane's count ncomb.
 template <int P, int W, int G, bool HIST>
 __device__ __forceinline__ void run_subset(const u32 *__restrict__ rows, const uint4 *lrows, int j,
                                            const int (&r)[G], u32 &lmin, u32 &ncomb, u32 *lh, u32 woff, u32 cap) {
-    constexpr int NA = 2;  // P - 1 is a multiple of 2
+    constexpr int NA = 1;  // one prefix at a time (registers)
     const Row<W> R0 = load_row_lane<P, W>(rows, lrows, j, r[0]);
     const Row<W> R1 = load_row_lane<P, W>(rows, lrows, j, r[1]);
     const Row<W> R2 = load_row_lane<P, W>(rows, lrows, j, r[2]);
@@ -1078,9 +1078,8 @@ __device__ __forceinline__ void run_subset(const u32 *__restrict__ rows, const u
     }
 }
 
-// g <= SUBSET_G: one item per lane (a row, a pair of rows, a triple, a
-// quadruple; colex rank task * 64 + lane).  Adds the combinations the lane
-// evaluated to lcnt.
+// g <= SUBSET_G: one item per lane (a row, a pair of rows, a triple; colex
+// rank task * 64 + lane).  Adds the combinations the lane evaluated to lcnt.
 template <int P, int W, bool HIST>
 __device__ void run_small_task(int g, int k, int j, const u32 *__restrict__ rows, const uint4 *lrows,
                                const u64 *sbin, const u64 *__restrict__ gbin, u64 task, u32 &lmin, u64 &lcnt,
@@ -1129,10 +1128,12 @@ __device__ void run_small_task(int g, int k, int j, const u32 *__restrict__ rows
             decode_subset<3>(item, k, bin, r);
             run_subset<P, W, 3, HIST>(rows, lrows, j, r, lmin, ncomb, lh, woff, cap);
         }
-    } else if (valid) {
-        int r[4];
-        decode_subset<4>(item, k, bin, r);
-        run_subset<P, W, 4, HIST>(rows, lrows, j, r, lmin, ncomb, lh, woff, cap);
+    } else if constexpr (SUBSET_G >= 4) {
+        if (valid) {
+            int r[4];
+            decode_subset<4>(item, k, bin, r);
+            run_subset<P, W, 4, HIST>(rows, lrows, j, r, lmin, ncomb, lh, woff, cap);
+        }
     }
     lcnt += ncomb;
 }
@@ -1145,7 +1146,9 @@ __device__ void run_small_task(int g, int k, int j, const u32 *__restrict__ rows
 // 1 -> 2) or subtracted (2 -> 1) per step; F_7 (vd = 1) through the
 // coefficients 1 .. 6 of row q, one addition of row q per step.  Adds the
 // combinations the lane evaluated (the rows its sweeps combined) to lcnt.
-template <int P, int W, bool HIST>
+// TABLE_ONLY: every caller passes a pair table, and the path without one is
+// not compiled (it would hold the p-1 prefixes in registers).
+template <int P, int W, bool HIST, bool TABLE_ONLY = false>
 __device__ void run_base_task(const StageDesc &sd, int k, int j, const u32 *__restrict__ rows, const uint4 *lrows,
                               const uint4 *__restrict__ ptab, const u64 *sbin, const u64 *__restrict__ gbin,
                               const QEntry *qtab, int nq, u64 task, u32 &lmin, u64 &lcnt, u32 *lh, u32 woff,
@@ -1179,7 +1182,7 @@ __device__ void run_base_task(const StageDesc &sd, int k, int j, const u32 *__re
     // from the set's pair table when it has one, else through the exact
     // prefixes Q + h R_s
     auto sweep_block = [&]() {
-        if (ptab != nullptr) {
+        if (TABLE_ONLY || ptab != nullptr) {
             const int e0 = uni((int)pair_first(s_lo, k)), e1 = uni((int)pair_first(s_hi, k));
             if (valid) {
                 sweep_pairs<P, W, HIST>(ptab, e0, e1, Q, lmin, lh, woff, cap);
@@ -1187,9 +1190,13 @@ __device__ void run_base_task(const StageDesc &sd, int k, int j, const u32 *__re
             }
             return;
         }
-        for (int s = s_lo; s < s_hi; s++) {
-            const Row<W> Rs = load_row<P, W>(rows, j, uni(s));
-            if (valid) ncomb += PER_ROW * (u32)extend_and_sweep<P, W, P - 1, HIST>(rows, j, s, k, Q, Rs, lmin, lh, woff, cap);
+        if constexpr (!TABLE_ONLY) {
+            for (int s = s_lo; s < s_hi; s++) {
+                const Row<W> Rs = load_row<P, W>(rows, j, uni(s));
+                if (valid)
+                    ncomb += PER_ROW * (u32)extend_and_sweep<P, W, P - 1, HIST>(rows, j, s, k, Q, Rs, lmin, lh, woff,
+                                                                                cap);
+            }
         }
     };
     if (vd == 0) {
@@ -1623,7 +1630,7 @@ __global__ __launch_bounds__(64) void decompose_batch_kernel(const uint8_t *__re
     a.spec = nullptr;
     a.epoch = 0;
     a.pad = 0;
-    a.pairs = (pairs != nullptr && bc.pair_offset != ~0ull) ? pairs + bc.pair_offset : nullptr;
+    a.pairs = pairs + bc.pair_offset;  // every code of a batch or a serving slot has its tables
     a.pair_stride = bc.pair_stride;
     a.pair_w = bc.W;
     const uint8_t *g = G + bc.g_offset;
@@ -1689,7 +1696,7 @@ __device__ void run_part(const StageDesc &sd, int s, uint32_t part, int k, const
         const u64 task = tile * WAVES_PER_GROUP + (u64)wid;
         if (task >= tasks) continue;
         if (g > SUBSET_G)
-            run_base_task<P, W, false>(sd, k, j, rows, nullptr, ptab, sbin, gbin, qtab, nq, task, lmin, lcnt, nullptr, woff,
+            run_base_task<P, W, false, true>(sd, k, j, rows, nullptr, ptab, sbin, gbin, qtab, nq, task, lmin, lcnt, nullptr, woff,
                                       cap);
         else
             run_small_task<P, W, false>(g, k, j, rows, nullptr, sbin, gbin, task, lmin, lcnt, nullptr, woff, cap);
@@ -1833,10 +1840,8 @@ __global__ __launch_bounds__(256) void enum_batch_kernel(CodeState *css, u64 *cl
         const u32 woff = (uni(codes[code].flags) & FLAG_SKIP) ? (u32)sd.g : 0u;
         const u32 cap = (u32)n;
         const u32 *r = rows + row_off;
-        const u64 pair_off = uni64(codes[code].pair_offset);
-        const uint4 *pt = (pairs != nullptr && pair_off != ~0ull)
-                              ? pairs + pair_off + (size_t)uni(sd.j - 1) * uni(codes[code].pair_stride)
-                              : nullptr;
+        // (every code of a batch or a serving slot has its pair tables)
+        const uint4 *pt = pairs + uni64(codes[code].pair_offset) + (size_t)uni(sd.j - 1) * uni(codes[code].pair_stride);
         u32 lmin = BIG;
         u64 lcnt = 0;
         if (p == 3) {

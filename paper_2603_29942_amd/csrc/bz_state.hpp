@@ -171,7 +171,7 @@ struct BatchCode {
     int32_t U0, WF, W;    // words per plane of G, and processed per combination
     uint32_t sweep_ops;  // VALU operations per lane and task
     uint32_t pair_stride;  // 16-byte units per pair table (pair_table_units(p, k, W))
-    u64 pair_offset;       // 16-byte offset of its first pair table, ~0: no tables
+    u64 pair_offset;       // 16-byte offset of its first pair table
 };
 
 // Batch-wide state: codes with stages left, the error flag of a time-out, and
@@ -506,8 +506,11 @@ BZ_HD int sweep_last_rows(int s, int k, Group &&group) {
 
 // Rounds g <= SUBSET_G give each lane one g-subset of the rows (all its
 // coefficient vectors); larger rounds give it a base of g-2 rows and sweep the
-// last two rows (see StageDesc).
-constexpr int SUBSET_G = 4;
+// last two rows (see StageDesc).  Round 4 takes bases of two rows: with the
+// pair tables its sweep needs no exact addition, and the four-row subsets
+// held the most registers of the batched kernel (119 VGPRs: four workgroups
+// per CU instead of five).
+constexpr int SUBSET_G = 3;
 
 // Tasks of a stage with g <= SUBSET_G: 64 subsets per task.
 BZ_HD u64 small_stage_tasks(int k, int g) { return (binom_sat(k, g) + 63) / 64; }

@@ -223,9 +223,9 @@ F7_BASE_ROUNDS = [(7, 16, 8, 0), (7, 20, 10, 0), (7, 18, 7, 0), (7, 128, 8, 0), 
 
 @pytest.mark.parametrize("p,n,k,limit", F7_BASE_ROUNDS, ids=[f"F{p}_{n}_{k}" for p, n, k, _ in F7_BASE_ROUNDS])
 def test_no_termination_histograms_base_rounds(bz, oracle, p, n, k, limit):
-    """Rounds g > 4 (bases of g-2 rows, the sweep over the last two rows) with
+    """Rounds g > 3 (bases of g-2 rows, the sweep over the last two rows) with
     every weight of every stage: for F_7 these carry nearly all the work of
-    F_7 [48,24].  k = 7..13 reaches rounds 5..13 (the F_7 [26,13] case up to a
+    F_7 [48,24].  k = 7..13 reaches rounds 4..13 (the F_7 [26,13] case up to a
     work limit); n = 128 with k = 8 takes four words per plane (identity skip
     on: 120 columns) and up to 16 information sets; both identity-skip settings,
     each with the sums of the two highest rows from the pair tables and from
