@@ -257,7 +257,9 @@ hipError_t launch_decompose(int WF, const uint8_t *G, CodeState *cs, u32 *rows, 
 template <int P, int W, bool H>
 hipError_t launch_enum_one(int grid, CodeState *cs, const u32 *rows, const uint4 *pairs, const u64 *binom, u64 *hist,
                            EnumArgs ea, hipStream_t s) {
-    enum_kernel<P, W, H><<<grid, 256, 0, s>>>(cs, rows, pairs, binom, hist, ea);
+    // with pair tables the instantiation that has no prefix path, else the one without tables
+    if (pairs != nullptr) enum_kernel<P, W, H, true><<<grid, 256, 0, s>>>(cs, rows, pairs, binom, hist, ea);
+    else enum_kernel<P, W, H, false><<<grid, 256, 0, s>>>(cs, rows, nullptr, binom, hist, ea);
     return hipGetLastError();
 }
 
@@ -279,33 +281,38 @@ hipError_t launch_enum(bool hist_mode, int W, int grid, CodeState *cs, const u32
                      : launch_enum_h<P, false>(W, grid, cs, rows, pairs, binom, hist, ea, s);
 }
 
-// Largest grid the enumeration kernel may get for (p, W, histograms): the
-// schedule is dealt to exactly this many workgroups.
-template <int P, int W, bool H>
+// Largest grid the enumeration kernel may get for (p, W, histograms, pair
+// tables): the schedule is dealt to exactly this many workgroups.
+template <int P, int W, bool H, bool T>
 int grid_for(int cu, int bpc) {
     static int max_bpc = -1;
     if (max_bpc < 0) {
         int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, enum_kernel<P, W, H>, 256, 0) != hipSuccess || nb < 1)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, enum_kernel<P, W, H, T>, 256, 0) != hipSuccess || nb < 1)
             return -1;
         max_bpc = nb;
     }
     return cu * (bpc < max_bpc ? bpc : max_bpc);
 }
 
-template <int P, bool H>
+template <int P, bool H, bool T>
 int grid_for_w(int W, int cu, int bpc) {
     switch (W) {
-    case 1: return grid_for<P, 1, H>(cu, bpc);
-    case 2: return grid_for<P, 2, H>(cu, bpc);
-    case 3: return grid_for<P, 3, H>(cu, bpc);
-    default: return grid_for<P, 4, H>(cu, bpc);
+    case 1: return grid_for<P, 1, H, T>(cu, bpc);
+    case 2: return grid_for<P, 2, H, T>(cu, bpc);
+    case 3: return grid_for<P, 3, H, T>(cu, bpc);
+    default: return grid_for<P, 4, H, T>(cu, bpc);
     }
 }
 
-int enum_grid(int p, bool hist, int W, int cu, int bpc) {
-    if (p == 3) return hist ? grid_for_w<3, true>(W, cu, bpc) : grid_for_w<3, false>(W, cu, bpc);
-    return hist ? grid_for_w<7, true>(W, cu, bpc) : grid_for_w<7, false>(W, cu, bpc);
+template <int P, bool T>
+int enum_grid_t(bool hist, int W, int cu, int bpc) {
+    return hist ? grid_for_w<P, true, T>(W, cu, bpc) : grid_for_w<P, false, T>(W, cu, bpc);
+}
+
+int enum_grid(int p, bool hist, bool tables, int W, int cu, int bpc) {
+    if (p == 3) return tables ? enum_grid_t<3, true>(hist, W, cu, bpc) : enum_grid_t<3, false>(hist, W, cu, bpc);
+    return tables ? enum_grid_t<7, true>(hist, W, cu, bpc) : enum_grid_t<7, false>(hist, W, cu, bpc);
 }
 
 // A plain call needs every workgroup of its persistent launch resident: it
@@ -525,7 +532,11 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, c
     if (W < 1) W = 1;
     // default: as many workgroups as fit (finer deals of the large stages)
     const int bpc = o.blocks_per_cu ? o.blocks_per_cu : 64;
-    const int grid = enum_grid(p, o.histograms != 0, W, c->cu, bpc);
+    // pair tables by default for F_7 only: the plain F_3 runs measured no
+    // faster with them (their enumeration is bound by latency, not by the
+    // prefixes)
+    const bool tables = o.pair_tables > 0 || (o.pair_tables == 0 && p == 7);
+    const int grid = enum_grid(p, o.histograms != 0, tables, W, c->cu, bpc);
     if (grid < 1) return BZ_ERR_DEVICE;
     const u64 timeout = c->ticks_per_s * (u64)(o.wait_timeout_s > 0 ? o.wait_timeout_s : 120);
 
@@ -569,10 +580,7 @@ int bz_min_distance_ex(int p, int n, int k, const uint8_t *G, int G_is_device, c
     a.spec = o.no_ahead ? nullptr : c->spec;
     a.epoch = c->spec_epoch;
     a.pad = 0;
-    // pair tables by default for F_7 only: the plain F_3 runs measured no
-    // faster with them (their enumeration is bound by latency, not by the
-    // prefixes)
-    a.pairs = (o.pair_tables > 0 || (o.pair_tables == 0 && p == 7)) ? c->pairs : nullptr;
+    a.pairs = tables ? c->pairs : nullptr;
     a.pair_stride = (uint32_t)pair_table_units(p, k, W);
     a.pair_w = W;
     a.pair_t0 = 1;  // a workgroup of the decomposition launch of its own builds set 0's table
@@ -997,7 +1005,7 @@ extern "C" int bz_min_distance_noalloc(int p, int n, int k, const uint8_t *G, co
     const int WF = (n + 31) / 32;
     int W = o.identity_skip ? (n - k + 31) / 32 : WF;
     if (W < 1) W = 1;
-    const int grid = enum_grid(p, false, W, na.cu, o.blocks_per_cu ? o.blocks_per_cu : 64);
+    const int grid = enum_grid(p, false, false, W, na.cu, o.blocks_per_cu ? o.blocks_per_cu : 64);
     if (grid < 1) return BZ_ERR_DEVICE;
     const u64 timeout = na.ticks_per_s * (u64)(o.wait_timeout_s > 0 ? o.wait_timeout_s : 120);
     NoAllocScratch *ws = na.ws;

@@ -1311,13 +1311,15 @@ __device__ void run_checker(CodeState *cs, const StageDesc *sdesc, int ns, const
     }
 }
 
-template <int P, int W, bool HIST>
+// TAB: the launch has pair tables (the base rounds take their two highest
+// rows from them; no prefix path is compiled), or has none.
+template <int P, int W, bool HIST, bool TAB>
 __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__restrict__ rows,
                                                    const uint4 *__restrict__ pairs, const u64 *__restrict__ gbin,
                                                    u64 *__restrict__ hist, EnumArgs ea) {
     const int lookahead = ea.lookahead;
     const u64 timeout_ticks = ea.timeout_ticks;
-    const int pslot1 = pairs != nullptr ? uni(cs->pair_slot1) : 1;  // slot of set 1's pair table
+    const int pslot1 = TAB ? uni(cs->pair_slot1) : 1;  // slot of set 1's pair table
     __shared__ u64 sbin[BZ_MAX_K * BIN_I];
     __shared__ StageDesc sdesc[BZ_MAX_STAGES];
     __shared__ QEntry qtab[BZ_MAX_K];
@@ -1398,9 +1400,9 @@ __global__ __launch_bounds__(256) void enum_kernel(CodeState *cs, const u32 *__r
         }
         if (sg > SUBSET_G) {
             const int sj = uni(sd.j - 1);
-            const uint4 *ptab = pairs != nullptr ? pairs + (size_t)(sj == 1 ? pslot1 : sj) * ea.pair_stride : nullptr;
-            run_base_task<P, W, HIST>(sd, k, sj, rows, lrows, ptab, sbin, gbin, qtab, k - 2 - (sg - 3), task, lmin,
-                                      lcnt, lh, woff, cap);
+            const uint4 *ptab = TAB ? pairs + (size_t)(sj == 1 ? pslot1 : sj) * ea.pair_stride : nullptr;
+            run_base_task<P, W, HIST, TAB>(sd, k, sj, rows, lrows, ptab, sbin, gbin, qtab, k - 2 - (sg - 3), task,
+                                           lmin, lcnt, lh, woff, cap);
         }
         else
             run_small_task<P, W, HIST>(sg, k, uni(sd.j - 1), rows, lrows, sbin, gbin, task, lmin, lcnt, lh, woff, cap);
