@@ -341,6 +341,28 @@ def test_second_information_set_ahead(bz):
     assert r["info"] & bz.INFO_AHEAD == 0
 
 
+def test_second_set_ahead_with_pair_tables(bz):
+    """With pair tables, a second set taken over from the workgroup ahead
+    comes with that workgroup's table (a slot of its own): F_7 [48,24] (tables
+    by default) and F_3 [72,36] with tables forced, against the oracle's
+    stored results, with the hand-over taken at least once for each."""
+    for part, cfg, tables in (("config3", 3, 0), ("config2", 2, 1)):
+        both = 0
+        for seed in range(8):
+            p, G = synth.config_code(cfg, seed)
+            want = golden_result(part, seed)
+            say(f"case ahead + tables {part} seed={seed}")
+            for ahead in (True, True, False):
+                r = bz.min_distance(p, G, ahead=ahead, pair_tables=tables)
+                same(r, want)
+                assert r["info"] & bz.INFO_PAIRS
+                if ahead and r["info"] & bz.INFO_AHEAD:
+                    both += 1
+                if not ahead:
+                    assert r["info"] & bz.INFO_AHEAD == 0
+        assert both >= 1, part
+
+
 def test_calls_alternating_streams(bz, oracle):
     """Plain calls alternate between the library's stream (host generators)
     and a user stream (device generators): a call that returns at its final
