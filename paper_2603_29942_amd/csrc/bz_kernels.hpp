@@ -1022,6 +1022,34 @@ __device__ __forceinline__ void sweep_pairs(const uint4 *__restrict__ ptab, int 
     }
 }
 
+// F_7: sweep_pairs for the NA exact sums of a run of bases at once (their
+// planes in Pv, nonzero masks in anyP): each unit, loaded once, serves all of
+// them (complete_all with NA prefixes), so the run's loads, loop control and
+// waits are paid once instead of NA times.
+template <int P, int W, bool HIST, int NA>
+__device__ __forceinline__ void sweep_pairs_multi(const uint4 *__restrict__ ptab, int e0, int e1,
+                                                  const u32 (&Pv)[NA][3][W], const u32 (&anyP)[NA][W], u32 &lmin,
+                                                  u32 *lh, u32 woff, u32 cap) {
+    static_assert(P == 7, "F_7 units");
+    constexpr int UN = P - 1, UR = 4;
+    const int u1 = uni(e1 * UN);
+    int u = uni(e0 * UN);
+    for (; u + UR <= u1; u += UR) {
+        Row<W> T[UR];
+#pragma unroll
+        for (int i = 0; i < UR; i++) T[i] = load_unit<W>(ptab, u + i);
+#pragma unroll
+        for (int i = 0; i < UR; i++) pin_unit<W>(T[i]);
+#pragma unroll
+        for (int i = 0; i < UR; i++) complete_all<P, W, NA, HIST>(Pv, anyP, T[i], lmin, lh, woff, cap);
+    }
+    for (; u < u1; u++) {
+        const Row<W> T = load_unit<W>(ptab, u);
+        pin_unit<W>(T);
+        complete_all<P, W, NA, HIST>(Pv, anyP, T, lmin, lh, woff, cap);
+    }
+}
+
 // C(c, i) for c < crows and i < BIN_I into LDS: every load of a thread is
 // issued before its first store (a loop that stores each value before the next
 // load waits for one memory round trip per element).  blockDim.x = 256.
@@ -1246,9 +1274,29 @@ __device__ void run_base_task(const StageDesc &sd, int k, int j, const u32 *__re
                            });
         }
         const Row<W> Rq = load_row<P, W>(rows, j, q);
-        for (int v = 0; v < P - 1; v++) {
-            if (v > 0 && valid) add_scaled<P, W>(Q, Rq.p, 1);
-            sweep_block();
+        if constexpr (TABLE_ONLY && GROUPS && W == 1) {
+            // the six sums of the run at once (sweep_pairs_multi)
+            u32 Pv[P - 1][3][W], anyP[P - 1][W];
+#pragma unroll
+            for (int v = 0; v < P - 1; v++) {
+                if (v > 0) add_scaled<P, W>(Q, Rq.p, 1);
+#pragma unroll
+                for (int w = 0; w < W; w++) {
+#pragma unroll
+                    for (int b = 0; b < 3; b++) Pv[v][b][w] = Q[b][w];
+                    anyP[v][w] = Q[0][w] | Q[1][w] | Q[2][w];
+                }
+            }
+            const int e0 = uni((int)pair_first(s_lo, k)), e1 = uni((int)pair_first(s_hi, k));
+            if (valid) {
+                sweep_pairs_multi<P, W, HIST, P - 1>(ptab, e0, e1, Pv, anyP, lmin, lh, woff, cap);
+                ncomb += (P - 1) * PER_ROW * (u32)(e1 - e0);
+            }
+        } else {
+            for (int v = 0; v < P - 1; v++) {
+                if (v > 0 && valid) add_scaled<P, W>(Q, Rq.p, 1);
+                sweep_block();
+            }
         }
     }
     if constexpr (P == 3) {
