@@ -1274,7 +1274,7 @@ __device__ void run_base_task(const StageDesc &sd, int k, int j, const u32 *__re
                            });
         }
         const Row<W> Rq = load_row<P, W>(rows, j, q);
-        if constexpr (TABLE_ONLY && GROUPS && W == 1) {
+        if constexpr (TABLE_ONLY && W == 1) {
             // the six sums of the run at once (sweep_pairs_multi)
             u32 Pv[P - 1][3][W], anyP[P - 1][W];
 #pragma unroll
