@@ -420,12 +420,18 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
             if (f == args.epoch && uni(__hip_atomic_load(&spec->ok, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
                 const int kj2 = uni(__hip_atomic_load(&spec->kj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
                 if (lane < k) {
-                    const u32 *srow = spec->rows + (size_t)lane * ROW_WORDS;
-                    u32 *drow = rows + (size_t)(BZ_MAX_K + lane) * ROW_WORDS;
+                    // plain 16-byte loads: the acquire of the flag orders them after
+                    // the other workgroup's stores (its release); all issued first
+                    const uint4 *srow = reinterpret_cast<const uint4 *>(spec->rows + (size_t)lane * ROW_WORDS);
+                    uint4 *drow = reinterpret_cast<uint4 *>(rows + (size_t)(BZ_MAX_K + lane) * ROW_WORDS);
+                    uint4 v[ROW_WORDS / 4];
 #pragma unroll
-                    for (int w = 0; w < 16; w++)
-                        drow[w] = __hip_atomic_load(const_cast<u32 *>(srow + w), __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
+                    for (int w = 0; w < ROW_WORDS / 4; w++) v[w] = srow[w];
+#pragma unroll
+                    for (int w = 0; w < ROW_WORDS / 4; w++)  // (one wait for all the loads)
+                        asm volatile("" ::"v"(v[w].x), "v"(v[w].y), "v"(v[w].z), "v"(v[w].w));
+#pragma unroll
+                    for (int w = 0; w < ROW_WORDS / 4; w++) drow[w] = v[w];
                 }
                 // its pair table is built by that workgroup, in slot pair_sets(n, k)
                 if (lane == 0 && pairs != nullptr) cs->pair_slot1 = pair_sets(n, k);
