@@ -19,6 +19,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
+
 #include "bz_arith.hpp"
 #include "bz_mlp.hpp"
 #include "bz_state.hpp"
@@ -83,12 +85,36 @@ __device__ __forceinline__ void hand_out_result(const CodeState *cs, CodeResult 
                                                 uint32_t value) {
     const int lane = __lane_id();
     if (res_out) {
-        constexpr int NWORDS = (int)(sizeof(CodeResult) / sizeof(u32));
+        // what the host reads of the block: the header, ranks[0, m) and the
+        // stage minima and counts of the n_table stages, as 32-bit words;
+        // the loads of 256 words are issued before their stores
         static_assert(sizeof(CodeResult) % sizeof(u32) == 0, "the result block in 32-bit words");
+        constexpr int RK = (int)(offsetof(CodeResult, ranks) / 4), SM = (int)(offsetof(CodeResult, stage_min) / 4),
+                      SC = (int)(offsetof(CodeResult, stage_count) / 4);
         const u32 *src = reinterpret_cast<const u32 *>(&cs->res);
         u32 *dst = reinterpret_cast<u32 *>(res_out);
-        for (int i = lane; i < NWORDS; i += 64)
-            dst[i] = __hip_atomic_load(const_cast<u32 *>(src + i), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const int m = min(max(uni(__hip_atomic_load(&cs->res.m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)), 0), BZ_MAX_M);
+        const int ns = min(max(uni(__hip_atomic_load(&cs->res.n_table, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)), 0),
+                           BZ_MAX_STAGES);
+        const int n1 = RK + m, n2 = n1 + ns, total = n2 + 2 * ns;
+        auto word = [&](int t) { return t < n1 ? t : (t < n2 ? SM + (t - n1) : SC + (t - n2)); };
+        for (int t0 = 0; t0 < total; t0 += 4 * 64) {
+            u32 v[4];
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int t = t0 + lane + 64 * r;
+                v[r] = t < total ? __hip_atomic_load(const_cast<u32 *>(src + word(t)), __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT)
+                                 : 0u;
+            }
+#pragma unroll
+            for (int r = 0; r < 4; r++) asm volatile("" ::"v"(v[r]));
+#pragma unroll
+            for (int r = 0; r < 4; r++) {
+                const int t = t0 + lane + 64 * r;
+                if (t < total) dst[word(t)] = v[r];
+            }
+        }
         __atomic_thread_fence(__ATOMIC_RELEASE);  // system scope: the stores before the flag
     }
     if (lane == 0) __hip_atomic_store(flag, value, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
