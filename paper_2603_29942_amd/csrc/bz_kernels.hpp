@@ -443,29 +443,36 @@ __device__ void decompose_code(const uint8_t *__restrict__ G, CodeState *cs, u32
                 if (f == args.epoch) break;
                 __builtin_amdgcn_s_sleep(1);
             }
-            if (f == args.epoch && uni(__hip_atomic_load(&spec->ok, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))) {
-                const int kj2 = uni(__hip_atomic_load(&spec->kj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            // every load of the hand-over issued together (one wait): its
+            // status, size and pivot columns, and the rows as plain 16-byte loads
+            // (the acquire of the flag orders them after the other workgroup's
+            // stores, its release)
+            u32 okv = 0, kjv = 0, pmv[4] = {0, 0, 0, 0};
+            uint4 v[ROW_WORDS / 4];
+            if (f == args.epoch) {
+                okv = __hip_atomic_load(&spec->ok, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                kjv = __hip_atomic_load(&spec->kj, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                for (int w = 0; w < 4; w++)
+                    pmv[w] = __hip_atomic_load(&spec->pivmask[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint4 *srow = reinterpret_cast<const uint4 *>(spec->rows + (size_t)(lane < k ? lane : 0) * ROW_WORDS);
+#pragma unroll
+                for (int w = 0; w < ROW_WORDS / 4; w++) v[w] = srow[w];
+#pragma unroll
+                for (int w = 0; w < ROW_WORDS / 4; w++)
+                    asm volatile("" ::"v"(v[w].x), "v"(v[w].y), "v"(v[w].z), "v"(v[w].w));
+            }
+            if (f == args.epoch && uni(okv)) {
+                const int kj2 = uni((int)kjv);
                 if (lane < k) {
-                    // plain 16-byte loads: the acquire of the flag orders them after
-                    // the other workgroup's stores (its release); all issued first
-                    const uint4 *srow = reinterpret_cast<const uint4 *>(spec->rows + (size_t)lane * ROW_WORDS);
                     uint4 *drow = reinterpret_cast<uint4 *>(rows + (size_t)(BZ_MAX_K + lane) * ROW_WORDS);
-                    uint4 v[ROW_WORDS / 4];
-#pragma unroll
-                    for (int w = 0; w < ROW_WORDS / 4; w++) v[w] = srow[w];
-#pragma unroll
-                    for (int w = 0; w < ROW_WORDS / 4; w++)  // (one wait for all the loads)
-                        asm volatile("" ::"v"(v[w].x), "v"(v[w].y), "v"(v[w].z), "v"(v[w].w));
 #pragma unroll
                     for (int w = 0; w < ROW_WORDS / 4; w++) drow[w] = v[w];
                 }
                 // its pair table is built by that workgroup, in slot pair_sets(n, k)
                 if (lane == 0 && pairs != nullptr) cs->pair_slot1 = pair_sets(n, k);
 #pragma unroll
-                for (int w = 0; w < 4; w++) {
-                    const u32 pm = uni(__hip_atomic_load(&spec->pivmask[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-                    used[w] |= pm & unused[w];
-                }
+                for (int w = 0; w < 4; w++) used[w] |= uni(pmv[w]) & unused[w];
                 if (lane == 0) sranks[1] = kj2;
                 m = 2;
                 handed = true;
