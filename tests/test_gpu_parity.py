@@ -199,11 +199,15 @@ SHAPES = [(3, 33, 8), (3, 63, 12), (3, 65, 10), (3, 95, 8), (3, 97, 10), (3, 127
 
 @pytest.mark.parametrize("p,n,k", SHAPES, ids=[f"F{p}_{n}_{k}" for p, n, k in SHAPES])
 def test_random_shapes(bz, oracle, p, n, k):
+    """Three option sets per seed; the round-mode set takes the other pair-table
+    setting than the default (F_3 with tables, F_7 without), so both paths of
+    the base rounds see every shape."""
+    flip = 1 if p == 3 else -1
     for seed in range(3):
         G = synth.random_generator(p, n, k, seed, stream=500)
-        for check, skip in (("stage", True), ("round", True), ("stage", False)):
+        for check, skip, tables in (("stage", True, 0), ("round", True, flip), ("stage", False, 0)):
             run_both(bz, oracle, p, G, f"shape seed={seed}", check=check, identity_skip=skip,
-                     max_codewords=1 << 30)
+                     max_codewords=1 << 30, pair_tables=tables)
 
 
 @pytest.mark.parametrize("p,n,k", [(3, 9, 4), (3, 12, 5), (7, 7, 3), (7, 9, 3), (3, 13, 3), (7, 5, 4),
