@@ -734,6 +734,17 @@ static void check_pairs() {
     }
     for (int n = 1; n <= BZ_MAX_N; n++)
         for (int k = 1; k <= n && k <= BZ_MAX_K; k++) CHECK(pair_sets(n, k) >= 1 && pair_sets(n, k) * k >= n);
+    // a pair's units cover its (p-1)^2 coefficient pairs once each: unit c
+    // holds R_s + c R_L (F_3: c = 1 and c = 2 = -1 in one unit), and a lane
+    // takes Q + h T_c for every h in F_p^*, i.e. coefficients (h, h c) on (s, L)
+    for (int P : {3, 7}) {
+        std::vector<int> seen(P * P, 0);
+        for (int c = 1; c < P; c++)
+            for (int h = 1; h < P; h++) seen[h * P + (h * c) % P]++;
+        for (int hs = 1; hs < P; hs++)
+            for (int hl = 1; hl < P; hl++) CHECK(seen[hs * P + hl] == 1);
+        CHECK((int)pair_units(P) * (P == 3 ? 2 : 1) == P - 1);
+    }
     if (fails == before) std::printf("OK pairs\n");
 }
 
